@@ -1,0 +1,138 @@
+"""Plain FP64 CPU oracle for MTTKRP and TTMc (Deinsum, arXiv 2206.08301).
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py`` may import this package.  The
+product library never links or calls it, and it shares no code with the HIP
+path.
+
+The arithmetic lives in ``oracle.c`` (plain loops, FP64, no FMA contraction):
+  * ``mttkrp``  -- the MTTKRP einsum of Tab. IV summed term by term
+                   (Sec. III-B, "tensor operations");
+  * ``ttm``     -- one mode product (Sec. III-B);
+  * ``ttmc``    -- the TTM chain over all modes but one (Sec. III-B).
+This module only marshals numpy arrays to that library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dpp = ctypes.POINTER(ctypes.c_void_p)
+    lib.oracle_num_threads.restype = ctypes.c_int
+    for name in ("oracle_mttkrp", "oracle_mttkrp_ld"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int64,
+                      ctypes.c_void_p, dpp, ctypes.c_void_p]
+    lib.oracle_ttm.restype = ctypes.c_int
+    lib.oracle_ttm.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int64,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.oracle_ttmc.restype = ctypes.c_int
+    lib.oracle_ttmc.argtypes = [ctypes.c_int, i64p, ctypes.c_int, i64p,
+                                ctypes.c_void_p, dpp, ctypes.c_void_p]
+    _lib = lib
+    return lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _dims(shape):
+    return (ctypes.c_int64 * len(shape))(*[int(s) for s in shape])
+
+
+def _factor_table(U, N, skip):
+    """U: sequence of N entries indexed by mode (entry ``skip`` ignored)."""
+    keep = []
+    ptrs = (ctypes.c_void_p * N)()
+    for m in range(N):
+        if m == skip or U[m] is None:
+            ptrs[m] = None
+            continue
+        a = _f64(U[m])
+        keep.append(a)
+        ptrs[m] = a.ctypes.data
+    return ptrs, keep
+
+
+def mttkrp(X, U, n, long_double=False):
+    """M[i_n, r] = sum over the other indices of X[i] * prod_{m != n} U[m][i_m, r].
+
+    ``U`` holds one matrix per mode (``U[n]`` is ignored).
+    """
+    X = _f64(X)
+    N = X.ndim
+    R = None
+    for m in range(N):
+        if m != n:
+            R = np.shape(U[m])[1]
+            if np.shape(U[m])[0] != X.shape[m]:
+                raise ValueError(f"factor of mode {m} has {np.shape(U[m])[0]} rows, X has {X.shape[m]}")
+    if R is None:
+        raise ValueError("MTTKRP needs at least one contracted mode")
+    ptrs, keep = _factor_table(U, N, n)
+    M = np.empty((X.shape[n], R), dtype=np.float64)
+    fn = _load().oracle_mttkrp_ld if long_double else _load().oracle_mttkrp
+    rc = fn(N, _dims(X.shape), n, R, X.ctypes.data, ptrs, M.ctypes.data)
+    if rc:
+        raise RuntimeError(f"oracle_mttkrp failed with {rc}")
+    return M
+
+
+def ttm(X, Um, m):
+    """Mode-m product: Y[.., r, ..] = sum_{i_m} X[.., i_m, ..] * Um[i_m, r]."""
+    X = _f64(X)
+    Um = _f64(Um)
+    if Um.shape[0] != X.shape[m]:
+        raise ValueError("factor rows must equal the contracted dimension")
+    shape = list(X.shape)
+    shape[m] = Um.shape[1]
+    Y = np.empty(shape, dtype=np.float64)
+    rc = _load().oracle_ttm(X.ndim, _dims(X.shape), m, Um.shape[1], X.ctypes.data,
+                            Um.ctypes.data, Y.ctypes.data)
+    if rc:
+        raise RuntimeError(f"oracle_ttm failed with {rc}")
+    return Y
+
+
+def ttmc(X, U, n):
+    """TTM chain over every mode except ``n`` (``U[n]`` is ignored)."""
+    X = _f64(X)
+    N = X.ndim
+    ranks = [0] * N
+    shape = list(X.shape)
+    for m in range(N):
+        if m == n:
+            continue
+        if np.shape(U[m])[0] != X.shape[m]:
+            raise ValueError(f"factor of mode {m} has wrong row count")
+        ranks[m] = np.shape(U[m])[1]
+        shape[m] = ranks[m]
+    ptrs, keep = _factor_table(U, N, n)
+    Y = np.empty(shape, dtype=np.float64)
+    rc = _load().oracle_ttmc(N, _dims(X.shape), n, _dims(ranks), X.ctypes.data, ptrs,
+                             Y.ctypes.data)
+    if rc:
+        raise RuntimeError(f"oracle_ttmc failed with {rc}")
+    return Y
