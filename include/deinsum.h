@@ -1,0 +1,207 @@
+/*
+ * deinsum.h -- C ABI of the MI355X (gfx950) MTTKRP / TTMc library.
+ *
+ * The library computes the two local multilinear kernels that dominate
+ * Deinsum's run time (Ziogas et al., "Deinsum: Practically I/O Optimal
+ * Multilinear Algebra", arXiv 2206.08301):
+ *   - mode-n MTTKRP (Sec. III-B; benchmark forms MTTKRP-O3-M{0,1,2} and
+ *     MTTKRP-O5-M{0,2,4} of Tab. IV), computed without ever forming the
+ *     Khatri-Rao product in memory (the fused schedule of Sec. IV-D);
+ *   - the mode-n TTM chain, TTMc (Sec. III-B; TTMc-O5-M0 of Tab. IV).
+ * Problems are stated in Einstein notation (Sec. III-A), as the paper's
+ * front end takes them; the parser accepts exactly these two families.
+ *
+ * Conventions for every entry point
+ *   - All functions are extern "C" and return a deinsum_status (0 = OK,
+ *     negative = error).  On error a message is available from
+ *     deinsum_last_error() (thread-local, valid until the next call on the
+ *     same thread).
+ *   - Tensors are dense and row-major (last index contiguous), as NumPy
+ *     C order.  X is I_0 x .. x I_{N-1}.  A factor operand "<m><r>" is an
+ *     I_m x R matrix, R contiguous.  The MTTKRP output is I_n x R; the TTMc
+ *     output has the dims of X with every contracted I_m replaced by R_m,
+ *     in place (the output string of the spec).
+ *   - Arrays named X, U, M, Y, workspace are DEVICE pointers owned by the
+ *     caller; the library never frees or retains them.  dims / ranks are
+ *     host arrays read during the call only.  Device pointers must be
+ *     16-byte aligned.
+ *   - The output is overwritten (the paper zero-initialises, then
+ *     accumulates); it must not overlap X or any factor.
+ *   - Argument errors are reported synchronously and nothing is enqueued.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
+ *     and the call returns without synchronising.  A device fault surfaces
+ *     as DEINSUM_ERR_DEVICE from a later call or from the caller's sync.
+ *   - Results are deterministic: for a given problem, plan and device the
+ *     output is bitwise identical run to run (fixed reduction order, no
+ *     floating-point atomics).
+ */
+#ifndef DEINSUM_H
+#define DEINSUM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DEINSUM_MAX_ORDER 8
+#define DEINSUM_MAX_RANK 256
+
+typedef enum deinsum_status {
+    DEINSUM_OK = 0,
+    DEINSUM_ERR_INVALID_ARG = -1, /* null pointer, overlap, bad enum      */
+    DEINSUM_ERR_PARSE = -2,       /* malformed einsum string              */
+    DEINSUM_ERR_UNSUPPORTED = -3, /* well-formed but not MTTKRP / TTMc    */
+    DEINSUM_ERR_SHAPE = -4,       /* dims or ranks < 1 or too large       */
+    DEINSUM_ERR_NO_MEMORY = -5,   /* workspace too small / alloc failed   */
+    DEINSUM_ERR_DEVICE = -6,      /* HIP runtime error                    */
+    DEINSUM_ERR_BUSY = -7         /* resource temporarily unavailable     */
+} deinsum_status;
+
+typedef enum deinsum_kind { DEINSUM_MTTKRP = 1, DEINSUM_TTMC = 2 } deinsum_kind;
+
+typedef enum deinsum_dtype { DEINSUM_F64 = 0, DEINSUM_F32 = 1, DEINSUM_BF16 = 2 } deinsum_dtype;
+
+/*
+ * Arithmetic form.  The paper fixes no precision (Sec. VI-A); FP64 is the
+ * plain form, the others trade accuracy for HBM bytes.
+ *   FP64   : X, factors, output FP64; FP64 matrix-core products.
+ *   FP32   : X and factors FP32; FP32 matrix-core products over one slice
+ *            of the contiguous mode, FP64 accumulation and reduction
+ *            beyond it; output FP32 or FP64.
+ *   BF16   : X BF16, factors FP32 (rounded to BF16 on the device); BF16
+ *            matrix-core products with FP32 accumulation, FP64 beyond one
+ *            slice; output FP32 or FP64.
+ *   BF16X3 : X and factors FP32, each split on the device into hi + lo
+ *            BF16 parts; products hi*hi + hi*lo + lo*hi on the matrix cores
+ *            with FP32 accumulation, FP64 beyond one slice.
+ */
+typedef enum deinsum_precision {
+    DEINSUM_PREC_FP64 = 0,
+    DEINSUM_PREC_FP32 = 1,
+    DEINSUM_PREC_BF16 = 2,
+    DEINSUM_PREC_BF16X3 = 3
+} deinsum_precision;
+
+/* Parsed einsum (deinsum_parse).  Letters are ASCII a-z / A-Z. */
+typedef struct deinsum_spec {
+    int32_t kind;                           /* deinsum_kind                           */
+    int32_t order;                          /* N, 2 <= N <= 8                         */
+    int32_t free_mode;                      /* n                                      */
+    int32_t n_factors;                      /* N - 1                                  */
+    int32_t factor_mode[DEINSUM_MAX_ORDER]; /* operand k contracts mode factor_mode[k] */
+    int32_t operand_of_mode[DEINSUM_MAX_ORDER]; /* inverse map; -1 for the free mode  */
+    char tensor_idx[DEINSUM_MAX_ORDER + 1]; /* letters of X                           */
+    char rank_idx[DEINSUM_MAX_ORDER + 1];   /* rank letter per MODE ('-' at n)        */
+    char out_idx[DEINSUM_MAX_ORDER + 2];    /* output letters                         */
+} deinsum_spec;
+
+/* Optional per-call report (filled when deinsum_opts.report != NULL). */
+typedef struct deinsum_report {
+    int32_t plan_id;            /* kernel family chosen (see plan_name)         */
+    int32_t tile_m, tile_k;     /* output rows per wave, contraction slice      */
+    int32_t waves_per_group;    /* waves per workgroup                          */
+    int64_t groups;             /* workgroups launched by the main kernel       */
+    int64_t partials;           /* partial outputs reduced in the fixed-order pass */
+    size_t workspace_bytes;     /* workspace used                                */
+    double alg_bytes;           /* X once + factors once + output once           */
+    double alg_flops;           /* flops of the two-stage method                 */
+    char plan_name[48];
+} deinsum_report;
+
+typedef struct deinsum_opts {
+    int32_t precision;        /* deinsum_precision (default FP64)                    */
+    int32_t out_dtype;        /* DEINSUM_F64 or DEINSUM_F32 (F64 required for FP64)  */
+    void *workspace;          /* optional caller device buffer; NULL = library pool  */
+    size_t workspace_bytes;   /* its size                                            */
+    int32_t plan_hint;        /* 0 = planner choice; else a plan id (tuning, tests)  */
+    int32_t split_hint;       /* 0 = planner choice; else outer-chunk count          */
+    deinsum_report *report;   /* optional host out-parameter                         */
+} deinsum_opts;
+
+/* Fill *opts with defaults: FP64, F64 output, library workspace, planner choice. */
+void deinsum_opts_init(deinsum_opts *opts);
+
+/*
+ * Parse an einsum string of the MTTKRP or TTMc family (host only, no GPU).
+ *   MTTKRP: "<X>,<f_1>,...,<f_{N-1}>-><n><r>", X has N distinct letters,
+ *           each factor is "<mode letter><r>" with one shared rank letter r
+ *           not in X, each mode but the free mode n appears in exactly one
+ *           factor (any order), e.g. "ijk,ja,ka->ia" (Tab. IV).
+ *   TTMc  : same operands with a distinct rank letter per factor; the output
+ *           is X's letters with each contracted letter replaced by its rank
+ *           letter in place, e.g. "ijklm,jb,kc,ld,me->ibcde" (Tab. IV).
+ * Whitespace is ignored.  Rejected with DEINSUM_ERR_PARSE: missing "->",
+ * ellipsis, non-letters, a letter repeated inside an operand, empty
+ * operands.  Rejected with DEINSUM_ERR_UNSUPPORTED: anything else outside
+ * the two families (a factor with its letters swapped, a factor on the free
+ * mode, a mode contracted twice or not at all, other output orders,
+ * N > 8).  N = 2 specs whose output is "<n><r>" parse as MTTKRP.
+ */
+deinsum_status deinsum_parse(const char *spec, deinsum_spec *out);
+
+/*
+ * Workspace (device bytes) a call with these arguments needs.  ranks: for
+ * MTTKRP ranks[0] = R; for TTMc one rank per factor operand (operand order).
+ */
+deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *dims,
+                                      const int64_t *ranks, const deinsum_opts *opts,
+                                      size_t *bytes);
+
+/*
+ * Mode-n MTTKRP (Sec. III-B, Tab. IV):
+ *   M[i_n, r] = sum_{i_m, m != n} X[i_0..i_{N-1}] * prod_{m != n} U^{m}[i_m, r]
+ * spec  : parsed MTTKRP spec; dims: N host sizes of X in its letter order.
+ * R     : rank, 1 <= R <= 256.
+ * X     : device tensor, dtype by precision (FP64: f64; FP32, BF16X3: f32; BF16: bf16).
+ * U     : host array of N-1 device pointers in OPERAND order (operand k is
+ *         I_{factor_mode[k]} x R; f64 for FP64, f32 otherwise).
+ * M     : device I_n x R output, dtype opts->out_dtype.
+ * opts  : NULL for defaults.
+ */
+deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R,
+                              const void *X, const void *const *U, void *M,
+                              const deinsum_opts *opts, void *stream);
+
+/*
+ * Mode-n TTMc (Sec. III-B, Tab. IV): the chain X x_m U^{m} over every m != n,
+ * each product contracting the factor's first index (I_m x R_m):
+ *   Y[r_0..i_n..r_{N-1}] = sum_{i_m, m != n} X[i] * prod_{m != n} U^{m}[i_m, r_m]
+ * ranks : host array of N-1 ranks in operand order, each 1..256.
+ * Other arguments as for deinsum_mttkrp.
+ */
+deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
+                            const void *X, const void *const *U, void *Y,
+                            const deinsum_opts *opts, void *stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char *deinsum_last_error(void);
+
+/*
+ * Synthetic input (setup, not part of the method): fill `count` elements of
+ * the device array X (dtype f64 / f32 / bf16) with the counter-based
+ * SplitMix64 stream (Steele, Lea & Flood, OOPSLA 2014).  Element e gets
+ * z = mix64(seed + (offset + e + 1) * 0x9E3779B97F4A7C15) mapped by `dist`:
+ *   0 uniform: 2 * ((z >> 11) * 2^-53) - 1 (exact in f64, rounded to
+ *              nearest even for f32 / bf16);
+ *   1 int5   : ((z >> 32) mod 5) - 2;   2 int3: ((z >> 32) mod 3) - 1.
+ * Asynchronous on `stream`.
+ */
+deinsum_status deinsum_synth_fill(void *X, int32_t dtype, int64_t count, uint64_t seed,
+                                  int64_t offset, int32_t dist, void *stream);
+
+/* Elementwise conversion f64 -> f32 / bf16 or f32 -> bf16, round to nearest even. */
+deinsum_status deinsum_convert(const void *src, int32_t src_dtype, void *dst, int32_t dst_dtype,
+                               int64_t count, void *stream);
+
+/* Release the library's device workspace pools and plan caches. */
+deinsum_status deinsum_shutdown(void);
+
+/* Library version string. */
+const char *deinsum_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEINSUM_H */

@@ -1,0 +1,123 @@
+"""ctypes declarations of libdeinsum.so (argument marshalling only).
+
+torch is imported before the library is loaded so that libdeinsum.so binds
+to the HIP runtime torch already mapped (same soname): device pointers and
+stream handles then belong to one runtime.  A missing library is an error;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede loading libdeinsum.so)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdeinsum.so")
+MAX_ORDER = 8
+
+OK = 0
+STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "PARSE", -3: "UNSUPPORTED", -4: "SHAPE",
+                -5: "NO_MEMORY", -6: "DEVICE", -7: "BUSY"}
+
+
+class DeinsumError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"deinsum {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Spec(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("free_mode", ctypes.c_int32),
+        ("n_factors", ctypes.c_int32),
+        ("factor_mode", ctypes.c_int32 * MAX_ORDER),
+        ("operand_of_mode", ctypes.c_int32 * MAX_ORDER),
+        ("tensor_idx", ctypes.c_char * (MAX_ORDER + 1)),
+        ("rank_idx", ctypes.c_char * (MAX_ORDER + 1)),
+        ("out_idx", ctypes.c_char * (MAX_ORDER + 2)),
+    ]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [
+        ("plan_id", ctypes.c_int32),
+        ("tile_m", ctypes.c_int32),
+        ("tile_k", ctypes.c_int32),
+        ("waves_per_group", ctypes.c_int32),
+        ("groups", ctypes.c_int64),
+        ("partials", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("alg_bytes", ctypes.c_double),
+        ("alg_flops", ctypes.c_double),
+        ("plan_name", ctypes.c_char * 48),
+    ]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("out_dtype", ctypes.c_int32),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+        ("plan_hint", ctypes.c_int32),
+        ("split_hint", ctypes.c_int32),
+        ("report", ctypes.POINTER(Report)),
+    ]
+
+
+# Every extern "C" symbol declared in include/deinsum.h.
+EXPORTS = (
+    "deinsum_opts_init", "deinsum_parse", "deinsum_workspace_size", "deinsum_mttkrp",
+    "deinsum_ttmc", "deinsum_last_error", "deinsum_synth_fill", "deinsum_convert",
+    "deinsum_shutdown", "deinsum_version",
+)
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `python paper_2206_08301_amd/build.py` (no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vp = ctypes.c_void_p
+    lib.deinsum_opts_init.argtypes = [ctypes.POINTER(Opts)]
+    lib.deinsum_opts_init.restype = None
+    lib.deinsum_parse.argtypes = [ctypes.c_char_p, ctypes.POINTER(Spec)]
+    lib.deinsum_parse.restype = ctypes.c_int
+    lib.deinsum_workspace_size.argtypes = [ctypes.POINTER(Spec), i64p, i64p, ctypes.POINTER(Opts),
+                                           ctypes.POINTER(ctypes.c_size_t)]
+    lib.deinsum_workspace_size.restype = ctypes.c_int
+    lib.deinsum_mttkrp.argtypes = [ctypes.POINTER(Spec), i64p, ctypes.c_int64, vp,
+                                   ctypes.POINTER(vp), vp, ctypes.POINTER(Opts), vp]
+    lib.deinsum_mttkrp.restype = ctypes.c_int
+    lib.deinsum_ttmc.argtypes = [ctypes.POINTER(Spec), i64p, i64p, vp, ctypes.POINTER(vp), vp,
+                                 ctypes.POINTER(Opts), vp]
+    lib.deinsum_ttmc.restype = ctypes.c_int
+    lib.deinsum_last_error.argtypes = []
+    lib.deinsum_last_error.restype = ctypes.c_char_p
+    lib.deinsum_synth_fill.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                       ctypes.c_int64, ctypes.c_int32, vp]
+    lib.deinsum_synth_fill.restype = ctypes.c_int
+    lib.deinsum_convert.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int64, vp]
+    lib.deinsum_convert.restype = ctypes.c_int
+    lib.deinsum_shutdown.argtypes = []
+    lib.deinsum_shutdown.restype = ctypes.c_int
+    lib.deinsum_version.argtypes = []
+    lib.deinsum_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(status: int):
+    if status != OK:
+        msg = load().deinsum_last_error()
+        raise DeinsumError(status, msg.decode() if msg else "")

@@ -1,0 +1,419 @@
+// abi.cpp -- the extern "C" entry points: argument validation, planning,
+// workspace management and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+#include "kernels.h"
+#include "mttkrp.h"
+#include "plan.h"
+#include "ttmc.h"
+
+namespace deinsum {
+
+deinsum_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(DEINSUM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return DEINSUM_OK;
+}
+
+namespace {
+
+// ------------------------------------------------------------------ workspace pool
+// One grow-only device buffer per device.  Calls that use the pool must be
+// ordered (one stream, or synchronised streams); concurrent calls pass their
+// own workspace.
+struct Pool {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::mutex g_pool_mu;
+Pool g_pool[64];
+
+deinsum_status pool_get(size_t bytes, void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(DEINSUM_ERR_DEVICE, "workspace: no current HIP device");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    Pool &p = g_pool[dev];
+    if (p.bytes < bytes) {
+        if (p.ptr) {
+            // Earlier work may still use the old buffer.
+            if (hipDeviceSynchronize() != hipSuccess)
+                return fail(DEINSUM_ERR_DEVICE, "workspace: device synchronise failed");
+            (void)hipFree(p.ptr);
+            p.ptr = nullptr;
+            p.bytes = 0;
+        }
+        size_t want = std::max<size_t>(bytes, size_t(1) << 20);
+        if (hipMalloc(&p.ptr, want) != hipSuccess) {
+            (void)hipGetLastError();
+            p.ptr = nullptr;
+            return fail(DEINSUM_ERR_NO_MEMORY, "workspace: hipMalloc of " + std::to_string(want) + " bytes failed");
+        }
+        p.bytes = want;
+    }
+    *out = p.ptr;
+    return DEINSUM_OK;
+}
+
+size_t x_elem_bytes(int prec)
+{
+    switch (prec) {
+    case DEINSUM_PREC_FP64: return 8;
+    case DEINSUM_PREC_BF16: return 2;
+    default: return 4;
+    }
+}
+size_t u_elem_bytes(int prec) { return prec == DEINSUM_PREC_FP64 ? 8 : 4; }
+size_t dtype_bytes(int dt) { return dt == DEINSUM_F64 ? 8 : (dt == DEINSUM_F32 ? 4 : 2); }
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return na && nb && pa < pb + nb && pb < pa + na;
+}
+
+deinsum_status resolve_opts(const deinsum_opts *in, deinsum_opts *o)
+{
+    deinsum_opts_init(o);
+    if (in) *o = *in;
+    if (o->precision < DEINSUM_PREC_FP64 || o->precision > DEINSUM_PREC_BF16X3)
+        return fail(DEINSUM_ERR_INVALID_ARG, "opts.precision is not a deinsum_precision");
+    if (o->out_dtype != DEINSUM_F64 && o->out_dtype != DEINSUM_F32)
+        return fail(DEINSUM_ERR_INVALID_ARG, "opts.out_dtype must be DEINSUM_F64 or DEINSUM_F32");
+    if (o->precision == DEINSUM_PREC_FP64 && o->out_dtype != DEINSUM_F64)
+        return fail(DEINSUM_ERR_INVALID_ARG, "the FP64 form writes an F64 output");
+    if (o->workspace == nullptr && o->workspace_bytes != 0)
+        return fail(DEINSUM_ERR_INVALID_ARG, "opts.workspace_bytes set without a workspace");
+    return DEINSUM_OK;
+}
+
+deinsum_status check_dims(const deinsum_spec *spec, const int64_t *dims)
+{
+    if (!spec || !dims) return fail(DEINSUM_ERR_INVALID_ARG, "null spec or dims");
+    if (spec->order < 2 || spec->order > DEINSUM_MAX_ORDER || spec->free_mode < 0 ||
+        spec->free_mode >= spec->order || spec->n_factors != spec->order - 1)
+        return fail(DEINSUM_ERR_INVALID_ARG, "spec is not a parsed deinsum_spec");
+    for (int m = 0; m < spec->order; ++m)
+        if (dims[m] < 0) return fail(DEINSUM_ERR_SHAPE, "dims must be >= 0");
+    // Element count must fit comfortably in 62 bits.
+    long double total = 1;
+    for (int m = 0; m < spec->order; ++m) total *= static_cast<long double>(dims[m]);
+    if (total > 4.0e18L) return fail(DEINSUM_ERR_SHAPE, "tensor too large");
+    return DEINSUM_OK;
+}
+
+__global__ void zero_fill_kernel(unsigned char *p, int64_t n)
+{
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+deinsum_status zero_bytes(void *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return DEINSUM_OK;
+    const unsigned g = static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 4096));
+    zero_fill_kernel<<<g, 256, 0, s>>>(static_cast<unsigned char *>(p), n);
+    return check_launch("zero_fill");
+}
+
+// ------------------------------------------------------------------ MTTKRP
+struct MttkrpCall {
+    MttkrpProblem pb;
+    MttkrpPlan plan;
+    const void *X;
+    const void *U[DEINSUM_MAX_ORDER];  // by mode
+    void *M;
+    int out_dtype;
+};
+
+deinsum_status prepare_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R,
+                              const deinsum_opts &o, MttkrpCall *call)
+{
+    if (deinsum_status st = check_dims(spec, dims)) return st;
+    if (spec->kind != DEINSUM_MTTKRP) return fail(DEINSUM_ERR_INVALID_ARG, "spec is not an MTTKRP");
+    if (R < 1 || R > DEINSUM_MAX_RANK)
+        return fail(DEINSUM_ERR_SHAPE, "rank must be 1.." + std::to_string(DEINSUM_MAX_RANK));
+    MttkrpProblem &pb = call->pb;
+    pb.N = spec->order;
+    pb.n = spec->free_mode;
+    for (int m = 0; m < pb.N; ++m) pb.dims[m] = dims[m];
+    pb.R = R;
+    pb.prec = o.precision;
+    call->out_dtype = o.out_dtype;
+    return plan_mttkrp(pb, o.plan_hint, o.split_hint, &call->plan);
+}
+
+deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
+{
+    const MttkrpProblem &pb = c.pb;
+    const MttkrpPlan &p = c.plan;
+    const int N = pb.N, n = pb.n;
+    const size_t ub = u_elem_bytes(pb.prec), xb = x_elem_bytes(pb.prec);
+    int64_t stride[DEINSUM_MAX_ORDER];
+    {
+        int64_t st = 1;
+        for (int m = N - 1; m >= 0; --m) {
+            stride[m] = st;
+            st *= pb.dims[m];
+        }
+    }
+    const int cols_pad = 16 * p.nt;
+    for (int64_t cb = 0; cb < p.col_blocks; ++cb) {
+        const int64_t col0 = cb * cols_pad;
+        const int ncols = static_cast<int>(std::min<int64_t>(cols_pad, pb.R - col0));
+        auto ucol = [&](int m) {
+            return static_cast<const void *>(static_cast<const char *>(c.U[m]) + col0 * ub);
+        };
+        double *P = static_cast<double *>(ws);
+        if (p.family == PLAN_MTTKRP_KCONTIG) {
+            Mk1Args a{};
+            a.X = c.X;
+            a.Ug = ucol(N - 1);
+            a.ldu = pb.R;
+            int k = 0;
+            for (int m = 0; m < N - 1; ++m) {
+                if (m == n) continue;
+                a.od.dim[k] = pb.dims[m];
+                a.od.xstride[k] = stride[m];
+                a.od.U[k] = ucol(m);
+                ++k;
+            }
+            a.od.n_outer = k;
+            a.In = pb.dims[n];
+            a.stride_n = stride[n];
+            a.Ig = pb.dims[N - 1];
+            a.ncols = ncols;
+            a.n_tiles = static_cast<int>(p.n_tiles);
+            a.n_kgroups = static_cast<int>(p.n_kgroups);
+            a.wk = p.wk;
+            a.wo = p.wo;
+            a.O = 1;
+            for (int i = 0; i < k; ++i) a.O *= a.od.dim[i];
+            a.o_per_chunk = p.o_per_chunk;
+            a.vec_ok = ((a.Ig * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
+            a.P = P;
+            if (deinsum_status st = launch_mttkrp_kcontig(pb.prec, p.nt, p.kl, a, p.groups, s)) return st;
+            if (deinsum_status st = launch_reduce_partials(P, p.parts, p.n_tiles, 16, cols_pad, pb.dims[n], ncols,
+                                                           static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
+                                                           c.out_dtype, pb.R, s))
+                return st;
+        } else {
+            Mk2Args a{};
+            a.X = c.X;
+            a.Ug = ucol(N - 2);
+            a.ldu = pb.R;
+            int k = 0;
+            for (int m = 0; m < N - 2; ++m) {
+                a.od.dim[k] = pb.dims[m];
+                a.od.xstride[k] = stride[m];
+                a.od.U[k] = ucol(m);
+                ++k;
+            }
+            a.od.n_outer = k;
+            a.In = pb.dims[N - 1];
+            a.Ig = pb.dims[N - 2];
+            a.stride_g = stride[N - 2];
+            a.ncols = ncols;
+            a.n_tiles = static_cast<int>(p.n_tiles);
+            a.O = 1;
+            for (int i = 0; i < k; ++i) a.O *= a.od.dim[i];
+            a.o_per_chunk = p.o_per_chunk;
+            a.n_igchunks = p.n_igchunks;
+            a.ig_per_chunk = p.ig_per_chunk;
+            a.vec_ok = ((a.In * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
+            a.P = P;
+            if (deinsum_status st = launch_mttkrp_mcontig(pb.prec, p.nt, p.mt, a, p.groups, s)) return st;
+            if (deinsum_status st = launch_reduce_partials(P, p.parts, p.n_tiles, 16 * p.mt, cols_pad, pb.dims[N - 1],
+                                                           ncols,
+                                                           static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
+                                                           c.out_dtype, pb.R, s))
+                return st;
+        }
+    }
+    return DEINSUM_OK;
+}
+
+void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p, size_t ws_bytes)
+{
+    if (!r) return;
+    std::memset(r, 0, sizeof(*r));
+    r->plan_id = p.family;
+    r->tile_m = p.family == PLAN_MTTKRP_KCONTIG ? 16 : 16 * p.mt;
+    r->tile_k = p.family == PLAN_MTTKRP_KCONTIG ? 4 * p.kl : 4;
+    r->waves_per_group = p.waves;
+    r->groups = p.groups * p.col_blocks;
+    r->partials = p.parts;
+    r->workspace_bytes = ws_bytes;
+    double nx = 1, fsum = 0;
+    for (int m = 0; m < pb.N; ++m) nx *= static_cast<double>(pb.dims[m]);
+    for (int m = 0; m < pb.N; ++m)
+        if (m != pb.n) fsum += static_cast<double>(pb.dims[m]) * static_cast<double>(pb.R);
+    r->alg_bytes = nx * x_elem_bytes(pb.prec) + fsum * u_elem_bytes(pb.prec) +
+                   static_cast<double>(pb.dims[pb.n]) * pb.R * 8.0;
+    // Two-stage flops: GEMM over one mode (2 nX R) + Hadamard of each stage-1 row.
+    const int g = (pb.n == pb.N - 1) ? pb.N - 2 : pb.N - 1;
+    r->alg_flops = 2.0 * nx * pb.R + 2.0 * (nx / static_cast<double>(pb.dims[g])) * pb.R * std::max(1, pb.N - 2);
+    std::snprintf(r->plan_name, sizeof(r->plan_name), "%s", p.name.c_str());
+}
+
+}  // namespace
+}  // namespace deinsum
+
+using namespace deinsum;
+
+extern "C" {
+
+void deinsum_opts_init(deinsum_opts *opts)
+{
+    if (!opts) return;
+    std::memset(opts, 0, sizeof(*opts));
+    opts->precision = DEINSUM_PREC_FP64;
+    opts->out_dtype = DEINSUM_F64;
+}
+
+const char *deinsum_version(void) { return "deinsum-mi355x 0.1 (gfx950)"; }
+
+deinsum_status deinsum_parse(const char *spec, deinsum_spec *out) { return parse_spec(spec, out); }
+
+deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
+                                      const deinsum_opts *opts, size_t *bytes)
+{
+    if (!bytes || !ranks) return fail(DEINSUM_ERR_INVALID_ARG, "null ranks or bytes");
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (spec && spec->kind == DEINSUM_TTMC) return ttmc_workspace_size(spec, dims, ranks, o, bytes);
+    MttkrpCall c{};
+    if (deinsum_status st = prepare_mttkrp(spec, dims, ranks[0], o, &c)) return st;
+    *bytes = c.plan.workspace;
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R, const void *X,
+                              const void *const *U, void *M, const deinsum_opts *opts, void *stream)
+{
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    MttkrpCall c{};
+    if (deinsum_status st = check_dims(spec, dims)) return st;
+    if (spec->kind != DEINSUM_MTTKRP) return fail(DEINSUM_ERR_INVALID_ARG, "spec is not an MTTKRP");
+    if (R < 1 || R > DEINSUM_MAX_RANK)
+        return fail(DEINSUM_ERR_SHAPE, "rank must be 1.." + std::to_string(DEINSUM_MAX_RANK));
+    if (!U || !M) return fail(DEINSUM_ERR_INVALID_ARG, "null factor table or output");
+    const int N = spec->order, n = spec->free_mode;
+    int64_t nx = 1;
+    bool empty = false;
+    for (int m = 0; m < N; ++m) {
+        nx *= dims[m];
+        if (dims[m] == 0) empty = true;
+    }
+    const size_t xb = x_elem_bytes(o.precision), ub = u_elem_bytes(o.precision);
+    const size_t mbytes = static_cast<size_t>(dims[n]) * R * dtype_bytes(o.out_dtype);
+    if (!X && nx) return fail(DEINSUM_ERR_INVALID_ARG, "null X");
+    for (int k = 0; k < N - 1; ++k) {
+        const int m = spec->factor_mode[k];
+        if (!U[k] && dims[m]) return fail(DEINSUM_ERR_INVALID_ARG, "null factor operand " + std::to_string(k));
+        if (overlaps(M, mbytes, U[k], static_cast<size_t>(dims[m]) * R * ub))
+            return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps factor operand " + std::to_string(k));
+        c.U[m] = U[k];
+    }
+    if (overlaps(M, mbytes, X, static_cast<size_t>(nx) * xb))
+        return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps X");
+    if (reinterpret_cast<uintptr_t>(M) % dtype_bytes(o.out_dtype) != 0 ||
+        reinterpret_cast<uintptr_t>(X) % xb != 0)
+        return fail(DEINSUM_ERR_INVALID_ARG, "X and M must be aligned to their element size");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dims[n] == 0) { clear_error(); return DEINSUM_OK; }
+    if (empty) {  // an empty sum: M = 0
+        if (deinsum_status st = zero_bytes(M, static_cast<int64_t>(mbytes), s)) return st;
+        clear_error();
+        return DEINSUM_OK;
+    }
+    if (deinsum_status st = prepare_mttkrp(spec, dims, R, o, &c)) return st;
+    c.X = X;
+    c.M = M;
+    void *ws = o.workspace;
+    if (ws) {
+        if (o.workspace_bytes < c.plan.workspace)
+            return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(c.plan.workspace) + " bytes");
+    } else if (deinsum_status st = pool_get(c.plan.workspace, &ws)) {
+        return st;
+    }
+    fill_report(o.report, c.pb, c.plan, c.plan.workspace);
+    if (deinsum_status st = run_mttkrp(c, ws, s)) return st;
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
+                            const void *const *U, void *Y, const deinsum_opts *opts, void *stream)
+{
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (deinsum_status st = check_dims(spec, dims)) return st;
+    if (spec->kind != DEINSUM_TTMC) return fail(DEINSUM_ERR_INVALID_ARG, "spec is not a TTMc");
+    void *ws = o.workspace;
+    size_t need = 0;
+    if (deinsum_status st = ttmc_workspace_size(spec, dims, ranks, o, &need)) return st;
+    if (ws) {
+        if (o.workspace_bytes < need)
+            return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(need) + " bytes");
+    } else if (need) {
+        if (deinsum_status st = pool_get(need, &ws)) return st;
+    }
+    if (deinsum_status st = run_ttmc(spec, dims, ranks, X, U, Y, o, ws, need, static_cast<hipStream_t>(stream)))
+        return st;
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_synth_fill(void *X, int32_t dtype, int64_t count, uint64_t seed, int64_t offset, int32_t dist,
+                                  void *stream)
+{
+    if (count < 0 || offset < 0) return fail(DEINSUM_ERR_INVALID_ARG, "negative count or offset");
+    if (count == 0) return DEINSUM_OK;
+    if (!X) return fail(DEINSUM_ERR_INVALID_ARG, "null X");
+    if (dist < 0 || dist > 2) return fail(DEINSUM_ERR_INVALID_ARG, "dist must be 0 (uniform), 1 (int5) or 2 (int3)");
+    return launch_synth_fill(X, dtype, count, seed, offset, dist, static_cast<hipStream_t>(stream));
+}
+
+deinsum_status deinsum_convert(const void *src, int32_t src_dtype, void *dst, int32_t dst_dtype, int64_t count,
+                               void *stream)
+{
+    if (count < 0) return fail(DEINSUM_ERR_INVALID_ARG, "negative count");
+    if (count == 0) return DEINSUM_OK;
+    if (!src || !dst) return fail(DEINSUM_ERR_INVALID_ARG, "null pointer");
+    if (overlaps(src, count * dtype_bytes(src_dtype), dst, count * dtype_bytes(dst_dtype)))
+        return fail(DEINSUM_ERR_INVALID_ARG, "convert: buffers overlap");
+    return launch_convert(src, src_dtype, dst, dst_dtype, count, static_cast<hipStream_t>(stream));
+}
+
+deinsum_status deinsum_shutdown(void)
+{
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (int d = 0; d < 64; ++d) {
+        if (!g_pool[d].ptr) continue;
+        (void)hipSetDevice(d);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(g_pool[d].ptr);
+        g_pool[d] = Pool{};
+    }
+    (void)hipSetDevice(cur);
+    clear_error();
+    return DEINSUM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// kernels.h -- device-side building blocks shared by the gfx950 kernels, and
+// the host launch interface of each kernel family.
+//
+// Matrix-core operand layouts on gfx950 (wave64, 16x16 output tiles; lane l,
+// g = l / 16, c = l % 16), established on the device:
+//   v_mfma_f64_16x16x4_f64 : A[c][g], B[g][c];           D reg v = D[4v + g][c]
+//   v_mfma_f32_16x16x4_f32 : A[c][g], B[g][c];           D reg v = D[4g + v][c]
+//   v_mfma_f32_16x16x32_bf16: A[c][8g+e], B[8g+e][c] (e=0..7); D reg v = D[4g + v][c]
+// The pairing of A and B along k only requires both operands to use the same
+// (g, e) slot for the same k, so kernels assign k to slots freely.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "deinsum.h"
+#include "internal.h"
+
+namespace deinsum {
+
+// ----------------------------------------------------------------- types
+struct __align__(2) bf16_t {
+    uint16_t u;
+};
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+enum PrecisionId { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
+
+// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<uint16_t>((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h)
+{
+    return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+__device__ __forceinline__ double to_f64(double x) { return x; }
+__device__ __forceinline__ double to_f64(float x) { return static_cast<double>(x); }
+__device__ __forceinline__ double to_f64(bf16_t x) { return static_cast<double>(bf16_bits_to_f32(x.u)); }
+
+template <typename T> __device__ __forceinline__ T from_f64(double x);
+template <> __device__ __forceinline__ double from_f64<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_f64<float>(double x) { return static_cast<float>(x); }
+// f64 -> bf16 goes through f32 (RNE at each step), the convention of the host generator.
+template <> __device__ __forceinline__ bf16_t from_f64<bf16_t>(double x)
+{
+    bf16_t r;
+    r.u = f32_to_bf16_bits(static_cast<float>(x));
+    return r;
+}
+
+// ----------------------------------------------------------------- matrix-core wrappers
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_bf16(u16x8 a, u16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+// Row of the 16x16 output tile held in register v of lane l.
+template <int P> __device__ __forceinline__ int tile_row(int lane, int v);
+template <> __device__ __forceinline__ int tile_row<P_FP64>(int lane, int v) { return 4 * v + (lane >> 4); }
+template <> __device__ __forceinline__ int tile_row<P_FP32>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ __forceinline__ int tile_row<P_BF16>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ __forceinline__ int tile_row<P_BF16X3>(int lane, int v) { return 4 * (lane >> 4) + v; }
+
+// ----------------------------------------------------------------- launch interface
+// Modes other than the free mode and the matrix-core mode ("outer" modes), in
+// increasing mode order; the last one varies fastest in the walk.
+constexpr int kMaxOuter = DEINSUM_MAX_ORDER - 2;
+struct OuterDesc {
+    int n_outer;
+    int64_t dim[kMaxOuter];
+    int64_t xstride[kMaxOuter];  // element stride of that mode in X
+    const void *U[kMaxOuter];    // factor of that mode, column block applied
+};
+
+deinsum_status check_launch(const char *what);
+
+deinsum_status launch_synth_fill(void *x, int dtype, int64_t count, uint64_t seed, int64_t offset,
+                                 int dist, hipStream_t stream);
+deinsum_status launch_convert(const void *src, int sdt, void *dst, int ddt, int64_t count,
+                              hipStream_t stream);
+
+}  // namespace deinsum

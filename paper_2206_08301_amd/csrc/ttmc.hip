@@ -1,0 +1,612 @@
+// ttmc.hip -- mode-n TTM chain (paper Sec. III-B; TTMc-O5-M0 of Tab. IV):
+//   Y[r_0..i_n..r_{N-1}] = sum_{i_m, m != n} X[i] prod_{m != n} U^m[i_m, r_m].
+//
+// The chain is evaluated with X streamed from HBM once.  One fused pass
+// contracts two modes per X slab (all indices but i_a, i_c fixed):
+//   stage 1, matrix cores, K = i_a:  D[i_c, r_a] = sum_{i_a} X[slab, i_a, i_c] U^a[i_a, r_a]
+//       (the contiguous mode c = N-1 is the matrix-core M dimension, so each
+//       lane streams a contiguous run of X; U^a rows are read per K-step);
+//   stage 2, matrix cores, K = i_c:  Z[r_a, r_c] = sum_{i_c} D[i_c, r_a] U^c[i_c, r_c]
+//       with D taken straight from the accumulator registers as the B operand.
+// If the free mode is the contiguous one, stage 2 is skipped (i_c = i_n stays).
+// Partial Z tiles of the workgroups are summed in a fixed order; the modes
+// left after the fused pass are contracted one at a time on the (much
+// smaller) intermediate, the last product writing Y in its output order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "mttkrp.h"
+#include "ttmc.h"
+
+namespace deinsum {
+
+namespace {
+
+constexpr int kMaxTtmcRank = 64;
+
+template <int P> struct TkTypes;
+template <> struct TkTypes<P_FP64> { using XT = double; using DT = f64x4; };
+template <> struct TkTypes<P_FP32> { using XT = float;  using DT = f32x4; };
+
+__device__ __forceinline__ int64_t tmin(int64_t a, int64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int64_t tmax(int64_t a, int64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ double ldu_p(const void *p, int64_t i, int prec)
+{
+    return prec == P_FP64 ? static_cast<const double *>(p)[i]
+                          : static_cast<double>(static_cast<const float *>(p)[i]);
+}
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+template <typename T, int MT>
+__device__ __forceinline__ void load_m(T (&dst)[MT], const T *__restrict__ src, bool vec, int valid)
+{
+    if constexpr ((MT * sizeof(T)) % 16 == 0) {
+        if (vec && valid >= MT) {
+            constexpr int NV = MT * sizeof(T) / 16;
+            const v4u *s = reinterpret_cast<const v4u *>(src);
+            v4u tmp[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) tmp[i] = __builtin_nontemporal_load(s + i);
+            __builtin_memcpy(dst, tmp, sizeof(dst));
+            return;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < MT; ++i) dst[i] = (i < valid) ? src[i] : T{};
+}
+
+struct SlabWalk {
+    int64_t idx[kMaxOuter];
+    int64_t off;
+    __device__ void init(const OuterDesc &od, int64_t o)
+    {
+        off = 0;
+        for (int m = od.n_outer - 1; m >= 0; --m) {
+            idx[m] = o % od.dim[m];
+            o /= od.dim[m];
+            off += idx[m] * od.xstride[m];
+        }
+    }
+    __device__ void next(const OuterDesc &od)
+    {
+        for (int m = od.n_outer - 1; m >= 0; --m) {
+            off += od.xstride[m];
+            if (++idx[m] < od.dim[m]) return;
+            off -= idx[m] * od.xstride[m];
+            idx[m] = 0;
+        }
+    }
+};
+
+template <int P, int NTA, int NTC, int MT, bool STAGE2>
+__global__ void __launch_bounds__(256) ttmc_fused_kernel(const TkArgs a)
+{
+    using XT = typename TkTypes<P>::XT;
+    using DT = typename TkTypes<P>::DT;
+    constexpr int UB = 4;
+    constexpr int TA = 16 * NTA, TC = 16 * NTC;
+    __shared__ double lds[STAGE2 ? 4 * TA * TC : 1];
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int64_t b = blockIdx.x;
+    const int cgroup = static_cast<int>(b % a.n_cgroups);
+    const int64_t sg = b / a.n_cgroups;
+    const int ctile = cgroup * a.nwaves + w;
+    const int64_t cbase = static_cast<int64_t>(ctile) * 16 * MT;
+    const int64_t ibase = cbase + MT * c;
+    const int ivalid = (ctile < a.n_ctiles) ? static_cast<int>(tmin(MT, tmax(0, a.Ic - ibase))) : 0;
+    const int64_t s0 = sg * a.slabs_per_group;
+    const int64_t s1 = tmin(a.n_slabs, s0 + a.slabs_per_group);
+    const XT *__restrict__ X = static_cast<const XT *>(a.X);
+    const bool vec = a.vec_ok != 0;
+    const int64_t nsteps = (a.Ia + 3) / 4;
+    const int tile_elems = TA * TC;
+
+    SlabWalk walk;
+    walk.init(a.od, s0);
+    for (int64_t slab = s0; slab < s1; ++slab) {
+        DT d[MT][NTA];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NTA; ++nt) d[mt][nt] = DT{0, 0, 0, 0};
+        const XT *xs = X + walk.off + ibase;
+        XT xbuf[2][UB][MT];
+        double ubuf[2][UB][NTA];
+        auto load_block = [&](int s, int64_t st0) {
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+                const int64_t r = (st0 + u) * 4 + g;
+                const bool rv = r < a.Ia;
+                load_m<XT, MT>(xbuf[s][u], xs + r * a.stride_a, vec, rv ? ivalid : 0);
+#pragma unroll
+                for (int nt = 0; nt < NTA; ++nt) {
+                    const int col = nt * 16 + c;
+                    ubuf[s][u][nt] = (rv && col < a.ra) ? ldu_p(a.Ua, r * a.ldua + col, P) : 0.0;
+                }
+            }
+        };
+        auto mac_block = [&](int s) {
+#pragma unroll
+            for (int u = 0; u < UB; ++u)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NTA; ++nt) {
+                        if constexpr (P == P_FP64)
+                            d[mt][nt] = mfma_f64(xbuf[s][u][mt], ubuf[s][u][nt], d[mt][nt]);
+                        else
+                            d[mt][nt] = mfma_f32(xbuf[s][u][mt], static_cast<float>(ubuf[s][u][nt]), d[mt][nt]);
+                    }
+        };
+        load_block(0, 0);
+        for (int64_t st = 0; st < nsteps; st += 2 * UB) {
+            if (st + UB < nsteps) load_block(1, st + UB);
+            mac_block(0);
+            if (st + UB >= nsteps) break;
+            if (st + 2 * UB < nsteps) load_block(0, st + 2 * UB);
+            mac_block(1);
+        }
+
+        if constexpr (STAGE2) {
+            // Z[r_c, r_a] = sum_{i_c} U^c[i_c, r_c] D[i_c, r_a]: K-step v pairs slot g
+            // with the D row that lanes of group g hold in register v.
+            DT z[NTC][NTA];
+#pragma unroll
+            for (int tc = 0; tc < NTC; ++tc)
+#pragma unroll
+                for (int ta = 0; ta < NTA; ++ta) z[tc][ta] = DT{0, 0, 0, 0};
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t rowc = cbase + MT * tile_row<P>(lane, v) + mt;
+#pragma unroll
+                    for (int tc = 0; tc < NTC; ++tc) {
+                        const int col = tc * 16 + c;
+                        const double u = (ctile < a.n_ctiles && rowc < a.Ic && col < a.rc)
+                                             ? ldu_p(a.Uc, rowc * a.lduc + col, P) : 0.0;
+#pragma unroll
+                        for (int ta = 0; ta < NTA; ++ta) {
+                            if constexpr (P == P_FP64)
+                                z[tc][ta] = mfma_f64(u, d[mt][ta][v], z[tc][ta]);
+                            else
+                                z[tc][ta] = mfma_f32(static_cast<float>(u), d[mt][ta][v], z[tc][ta]);
+                        }
+                    }
+                }
+            // Fixed-order reduction over the workgroup's c-tiles.
+#pragma unroll
+            for (int tc = 0; tc < NTC; ++tc)
+#pragma unroll
+                for (int ta = 0; ta < NTA; ++ta)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        lds[w * tile_elems + (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v)] =
+                            static_cast<double>(z[tc][ta][v]);
+            __syncthreads();
+            double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * tile_elems;
+            for (int i = threadIdx.x; i < tile_elems; i += 64 * a.nwaves) {
+                double s = lds[i];
+                for (int ww = 1; ww < a.nwaves; ++ww) s += lds[ww * tile_elems + i];
+                out[i] = s;
+            }
+            __syncthreads();
+        } else {
+            const int64_t rows = static_cast<int64_t>(a.n_ctiles) * 16 * MT;
+            double *out = a.P + slab * rows * TA;
+            if (ctile < a.n_ctiles) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int ta = 0; ta < NTA; ++ta)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            out[(cbase + MT * tile_row<P>(lane, v) + mt) * TA + ta * 16 + c] =
+                                static_cast<double>(d[mt][ta][v]);
+            }
+        }
+        walk.next(a.od);
+    }
+}
+
+// Sum `parts` padded partial tensors and scatter into a strided destination.
+// Element (s, x, y): s over the slab modes (dims sdim), x < X1 (padded PX), y < Y1 (padded PY).
+struct ReduceArgs {
+    const double *P;
+    int64_t parts, part_stride;
+    int nd;
+    int64_t sdim[DEINSUM_MAX_ORDER];
+    int64_t sstr[DEINSUM_MAX_ORDER];  // destination strides of the slab modes
+    int64_t X1, PX, xstr, Y1, PY, ystr;
+    int64_t total;
+    void *out;
+    int out_dtype;
+};
+
+__global__ void __launch_bounds__(256) reduce_strided_kernel(const ReduceArgs a)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.total) return;
+    const int64_t y = e % a.Y1;
+    const int64_t x = (e / a.Y1) % a.X1;
+    int64_t s = e / (a.Y1 * a.X1);
+    int64_t off = x * a.xstr + y * a.ystr;
+    const int64_t slab = s;
+    for (int m = a.nd - 1; m >= 0; --m) {
+        off += (s % a.sdim[m]) * a.sstr[m];
+        s /= a.sdim[m];
+    }
+    const double *p = a.P + (slab * a.PX + x) * a.PY + y;
+    double acc = 0.0;
+    for (int64_t q = 0; q < a.parts; ++q) acc += p[q * a.part_stride];
+    if (a.out_dtype == DEINSUM_F64) static_cast<double *>(a.out)[off] = acc;
+    else static_cast<float *>(a.out)[off] = static_cast<float>(acc);
+}
+
+// One mode product on an FP64 intermediate with a strided destination.
+struct SmallTtmArgs {
+    const double *T;
+    int nd;
+    int64_t odim[DEINSUM_MAX_ORDER];  // output extents (dim m is Rm)
+    int64_t tstr[DEINSUM_MAX_ORDER];  // input strides
+    int64_t ostr[DEINSUM_MAX_ORDER];  // output strides
+    int m;
+    int64_t Im;
+    const void *U;
+    int64_t ldu;
+    int uprec;
+    int64_t total;
+    void *out;
+    int out_dtype;
+};
+
+__global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.total) return;
+    int64_t rem = e, ioff = 0, ooff = 0, r = 0;
+    for (int d = a.nd - 1; d >= 0; --d) {
+        const int64_t i = rem % a.odim[d];
+        rem /= a.odim[d];
+        ooff += i * a.ostr[d];
+        if (d == a.m) r = i;
+        else ioff += i * a.tstr[d];
+    }
+    double acc = 0.0;
+    for (int64_t i = 0; i < a.Im; ++i) acc += a.T[ioff + i * a.tstr[a.m]] * ldu_p(a.U, i * a.ldu + r, a.uprec);
+    if (a.out_dtype == DEINSUM_F64) static_cast<double *>(a.out)[ooff] = acc;
+    else static_cast<float *>(a.out)[ooff] = static_cast<float>(acc);
+}
+
+template <int P, int NTA, int NTC, int MT, bool S2>
+void launch_tk(const TkArgs &a, int64_t grid, hipStream_t s)
+{
+    ttmc_fused_kernel<P, NTA, NTC, MT, S2><<<static_cast<unsigned>(grid), 64 * a.nwaves, 0, s>>>(a);
+}
+
+using TkLaunch = void (*)(const TkArgs &, int64_t, hipStream_t);
+#define TK(P, A, C) {P, A, C, true, &launch_tk<P, A, C, 4, true>}
+#define TK1(P, A) {P, A, 0, false, &launch_tk<P, A, 1, 4, false>}
+const struct { int p, nta, ntc; bool s2; TkLaunch fn; } kTkTable[] = {
+    TK(P_FP64, 1, 1), TK(P_FP64, 1, 2), TK(P_FP64, 1, 4), TK(P_FP64, 2, 1), TK(P_FP64, 2, 2),
+    TK(P_FP64, 2, 4), TK(P_FP64, 4, 1), TK(P_FP64, 4, 2), TK(P_FP64, 4, 4),
+    TK(P_FP32, 1, 1), TK(P_FP32, 1, 2), TK(P_FP32, 1, 4), TK(P_FP32, 2, 1), TK(P_FP32, 2, 2),
+    TK(P_FP32, 2, 4), TK(P_FP32, 4, 1), TK(P_FP32, 4, 2), TK(P_FP32, 4, 4),
+    TK1(P_FP64, 1), TK1(P_FP64, 2), TK1(P_FP64, 4), TK1(P_FP32, 1), TK1(P_FP32, 2), TK1(P_FP32, 4),
+};
+#undef TK
+#undef TK1
+constexpr int kTkMT = 4;
+
+int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int ntiles_for(int64_t r) { return r <= 16 ? 1 : (r <= 32 ? 2 : 4); }
+
+// ------------------------------------------------------------------ host plan
+struct DimInfo {
+    int mode;
+    int64_t extent;
+};
+
+struct TtmcPlan {
+    int N = 0, n = 0, a = -1, c = -1;
+    bool stage2 = true, via_mttkrp = false;
+    int64_t I[DEINSUM_MAX_ORDER] = {0}, Rm[DEINSUM_MAX_ORDER] = {0};
+    int nta = 1, ntc = 1;
+    std::vector<int> slab_modes;
+    int64_t n_slabs = 1;
+    int n_ctiles = 1, nwaves = 1, n_cgroups = 1;
+    int64_t spg = 1, groups = 0;
+    size_t p_bytes = 0, z_bytes = 0, t_bytes = 0, total = 0;
+};
+
+deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, int prec,
+                         TtmcPlan *out)
+{
+    TtmcPlan p;
+    p.N = spec->order;
+    p.n = spec->free_mode;
+    for (int m = 0; m < p.N; ++m) {
+        p.I[m] = dims[m];
+        if (m == p.n) continue;
+        const int64_t r = ranks[spec->operand_of_mode[m]];
+        if (r < 1 || r > kMaxTtmcRank)
+            return fail(DEINSUM_ERR_SHAPE, "TTMc ranks must be 1.." + std::to_string(kMaxTtmcRank));
+        p.Rm[m] = r;
+    }
+    if (prec != P_FP64 && prec != P_FP32)
+        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64 and FP32 forms");
+    const int N = p.N, n = p.n;
+    if (N == 2 && n == 0) {  // a single product over the contiguous mode: the MTTKRP kernel computes it
+        p.via_mttkrp = true;
+        *out = p;
+        return DEINSUM_OK;
+    }
+    p.c = N - 1;
+    if (n == N - 1) {
+        p.stage2 = false;
+        p.a = N - 2;
+    } else {
+        p.stage2 = true;
+        p.a = (N - 2 != n) ? N - 2 : N - 3;
+    }
+    p.nta = ntiles_for(p.Rm[p.a]);
+    p.ntc = p.stage2 ? ntiles_for(p.Rm[p.c]) : 1;
+    for (int m = 0; m < N; ++m)
+        if (m != p.a && m != p.c) {
+            p.slab_modes.push_back(m);
+            p.n_slabs *= p.I[m];
+        }
+    p.n_ctiles = static_cast<int>(cdivl(p.I[p.c], 16 * kTkMT));
+    p.nwaves = std::min(4, p.n_ctiles);
+    p.n_cgroups = static_cast<int>(cdivl(p.n_ctiles, p.nwaves));
+    if (!p.stage2) p.n_cgroups = static_cast<int>(cdivl(p.n_ctiles, p.nwaves));
+    p.spg = std::max<int64_t>(1, (p.n_slabs * p.n_cgroups) / 4096);
+    p.groups = p.n_cgroups * cdivl(p.n_slabs, p.spg);
+    const int64_t TA = 16 * p.nta, TC = 16 * p.ntc;
+    if (p.stage2) p.p_bytes = static_cast<size_t>(p.n_cgroups * p.n_slabs * TA * TC) * 8;
+    else p.p_bytes = static_cast<size_t>(p.n_slabs * p.n_ctiles * 16 * kTkMT * TA) * 8;
+    // Intermediate after the fused pass, then ping-pong buffers for the remaining products.
+    int64_t zel = p.n_slabs * p.Rm[p.a] * (p.stage2 ? p.Rm[p.c] : p.I[n]);
+    const bool remaining = p.slab_modes.size() > (p.stage2 ? 1u : 0u);
+    if (remaining) {
+        p.z_bytes = static_cast<size_t>(zel) * 8;
+        p.t_bytes = p.z_bytes;  // every later intermediate is no larger (ranks <= extents not assumed)
+        int64_t cur = zel, mx = 0;
+        for (int m : p.slab_modes) {
+            if (m == n) continue;
+            cur = cur / p.I[m] * p.Rm[m];
+            mx = std::max(mx, cur);
+        }
+        p.t_bytes = static_cast<size_t>(mx) * 8;
+    }
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    p.total = align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes);
+    *out = p;
+    return DEINSUM_OK;
+}
+
+}  // namespace
+
+deinsum_status ttmc_workspace_size(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
+                                   const deinsum_opts &o, size_t *bytes)
+{
+    if (!spec || !dims || !ranks || !bytes) return fail(DEINSUM_ERR_INVALID_ARG, "null argument");
+    if (spec->kind != DEINSUM_TTMC) return fail(DEINSUM_ERR_INVALID_ARG, "spec is not a TTMc");
+    for (int m = 0; m < spec->order; ++m)
+        if (dims[m] < 1) return fail(DEINSUM_ERR_SHAPE, "TTMc dims must be >= 1");
+    TtmcPlan p;
+    if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, &p)) return st;
+    if (p.via_mttkrp) {
+        const int64_t R = ranks[0];
+        deinsum_spec ms = *spec;
+        ms.kind = DEINSUM_MTTKRP;
+        return deinsum_workspace_size(&ms, dims, &R, &o, bytes);
+    }
+    *bytes = p.total;
+    return DEINSUM_OK;
+}
+
+deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
+                        const void *const *U, void *Y, const deinsum_opts &o, void *ws, size_t ws_bytes,
+                        hipStream_t s)
+{
+    if (!ranks || !U || !Y || !X) return fail(DEINSUM_ERR_INVALID_ARG, "null argument");
+    for (int m = 0; m < spec->order; ++m)
+        if (dims[m] < 1) return fail(DEINSUM_ERR_SHAPE, "TTMc dims must be >= 1");
+    TtmcPlan p;
+    if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, &p)) return st;
+    const int N = p.N, n = p.n;
+    const size_t xb = o.precision == P_FP64 ? 8 : 4, ub = xb;
+    const size_t ob = o.out_dtype == DEINSUM_F64 ? 8 : 4;
+    const void *Um[DEINSUM_MAX_ORDER] = {nullptr};
+    int64_t nx = 1, ny = 1;
+    for (int m = 0; m < N; ++m) {
+        nx *= p.I[m];
+        ny *= (m == n) ? p.I[m] : p.Rm[m];
+        if (m != n) {
+            Um[m] = U[spec->operand_of_mode[m]];
+            if (!Um[m]) return fail(DEINSUM_ERR_INVALID_ARG, "null factor");
+        }
+    }
+    {
+        auto ov = [](const void *a0, size_t na, const void *b0, size_t nb) {
+            const uintptr_t pa = reinterpret_cast<uintptr_t>(a0), pb = reinterpret_cast<uintptr_t>(b0);
+            return pa < pb + nb && pb < pa + na;
+        };
+        if (ov(Y, ny * ob, X, nx * xb)) return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps X");
+        for (int m = 0; m < N; ++m)
+            if (m != n && ov(Y, ny * ob, Um[m], p.I[m] * p.Rm[m] * ub))
+                return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps a factor");
+    }
+    if (p.via_mttkrp) {
+        const int64_t R = p.Rm[1];
+        deinsum_spec ms = *spec;
+        ms.kind = DEINSUM_MTTKRP;
+        deinsum_opts o2 = o;
+        o2.workspace = ws;
+        o2.workspace_bytes = ws_bytes;
+        return deinsum_mttkrp(&ms, dims, R, X, U, Y, &o2, s);
+    }
+    int64_t stride[DEINSUM_MAX_ORDER], ystr[DEINSUM_MAX_ORDER];
+    {
+        int64_t st = 1, sy = 1;
+        for (int m = N - 1; m >= 0; --m) {
+            stride[m] = st;
+            st *= p.I[m];
+            ystr[m] = sy;
+            sy *= (m == n) ? p.I[m] : p.Rm[m];
+        }
+    }
+    auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+    char *base = static_cast<char *>(ws);
+    double *P = reinterpret_cast<double *>(base);
+    double *Z = reinterpret_cast<double *>(base + align(p.p_bytes));
+    double *T0 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes));
+    double *T1 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes) + align(p.t_bytes));
+
+    // ---- fused pass
+    TkArgs a{};
+    a.X = X;
+    a.Ua = Um[p.a];
+    a.ldua = p.Rm[p.a];
+    a.Uc = p.stage2 ? Um[p.c] : nullptr;
+    a.lduc = p.stage2 ? p.Rm[p.c] : 0;
+    a.Ia = p.I[p.a];
+    a.Ic = p.I[p.c];
+    a.stride_a = stride[p.a];
+    a.od.n_outer = static_cast<int>(p.slab_modes.size());
+    for (size_t k = 0; k < p.slab_modes.size(); ++k) {
+        a.od.dim[k] = p.I[p.slab_modes[k]];
+        a.od.xstride[k] = stride[p.slab_modes[k]];
+        a.od.U[k] = nullptr;
+    }
+    a.n_slabs = p.n_slabs;
+    a.slabs_per_group = p.spg;
+    a.n_ctiles = p.n_ctiles;
+    a.nwaves = p.nwaves;
+    a.n_cgroups = p.n_cgroups;
+    a.ra = static_cast<int>(p.Rm[p.a]);
+    a.rc = p.stage2 ? static_cast<int>(p.Rm[p.c]) : 0;
+    a.vec_ok = ((p.I[p.c] * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    a.P = P;
+    bool launched = false;
+    for (const auto &e : kTkTable)
+        if (e.p == o.precision && e.nta == p.nta && e.s2 == p.stage2 && (!p.stage2 || e.ntc == p.ntc)) {
+            e.fn(a, p.groups, s);
+            launched = true;
+            break;
+        }
+    if (!launched) return fail(DEINSUM_ERR_UNSUPPORTED, "no fused TTMc kernel for this precision and ranks");
+    if (deinsum_status st = check_launch("ttmc_fused")) return st;
+
+    // ---- logical dims of the intermediate: slab modes, then (a, c) or (n, a)
+    std::vector<DimInfo> zd;
+    for (int m : p.slab_modes) zd.push_back({m, p.I[m]});
+    std::vector<int> remaining;
+    for (int m : p.slab_modes)
+        if (m != n) remaining.push_back(m);
+    const int64_t TA = 16 * p.nta, TC = 16 * p.ntc;
+    ReduceArgs r{};
+    r.P = P;
+    r.nd = static_cast<int>(p.slab_modes.size());
+    for (int k = 0; k < r.nd; ++k) r.sdim[k] = p.I[p.slab_modes[k]];
+    if (p.stage2) {
+        r.parts = p.n_cgroups;
+        r.part_stride = p.n_slabs * TA * TC;
+        r.X1 = p.Rm[p.a];
+        r.PX = TA;
+        r.Y1 = p.Rm[p.c];
+        r.PY = TC;
+    } else {
+        r.parts = 1;
+        r.part_stride = 0;
+        r.X1 = p.I[p.c];
+        r.PX = static_cast<int64_t>(p.n_ctiles) * 16 * kTkMT;
+        r.Y1 = p.Rm[p.a];
+        r.PY = TA;
+    }
+    r.total = p.n_slabs * r.X1 * r.Y1;
+    const int xmode = p.stage2 ? p.a : p.c, ymode = p.stage2 ? p.c : p.a;
+    if (remaining.empty()) {
+        // Straight into Y.
+        for (int k = 0; k < r.nd; ++k) r.sstr[k] = ystr[p.slab_modes[k]];
+        r.xstr = ystr[xmode];
+        r.ystr = ystr[ymode];
+        r.out = Y;
+        r.out_dtype = o.out_dtype;
+    } else {
+        // Contiguous FP64 intermediate [slab modes..., x, y].
+        int64_t st = r.X1 * r.Y1;
+        for (int k = r.nd - 1; k >= 0; --k) {
+            r.sstr[k] = st;
+            st *= r.sdim[k];
+        }
+        r.xstr = r.Y1;
+        r.ystr = 1;
+        r.out = Z;
+        r.out_dtype = DEINSUM_F64;
+    }
+    reduce_strided_kernel<<<static_cast<unsigned>(cdivl(r.total, 256)), 256, 0, s>>>(r);
+    if (deinsum_status st = check_launch("ttmc_reduce")) return st;
+    if (remaining.empty()) return DEINSUM_OK;
+
+    // ---- remaining mode products on the intermediate
+    std::vector<DimInfo> cur = zd;
+    cur.push_back({xmode, r.X1});
+    cur.push_back({ymode, r.Y1});
+    const double *src = Z;
+    for (size_t k = 0; k < remaining.size(); ++k) {
+        const int m = remaining[remaining.size() - 1 - k];  // last mode first
+        const bool last = (k + 1 == remaining.size());
+        SmallTtmArgs t{};
+        t.T = src;
+        t.nd = static_cast<int>(cur.size());
+        int pos = -1;
+        for (int d = 0; d < t.nd; ++d)
+            if (cur[d].mode == m) pos = d;
+        t.m = pos;
+        t.Im = p.I[m];
+        int64_t st = 1;
+        for (int d = t.nd - 1; d >= 0; --d) {
+            t.tstr[d] = st;
+            st *= cur[d].extent;
+        }
+        cur[pos].extent = p.Rm[m];
+        t.total = 1;
+        for (int d = 0; d < t.nd; ++d) {
+            t.odim[d] = cur[d].extent;
+            t.total *= cur[d].extent;
+        }
+        void *dst = last ? Y : static_cast<void *>((k % 2 == 0) ? T0 : T1);
+        if (last) {
+            for (int d = 0; d < t.nd; ++d) t.ostr[d] = ystr[cur[d].mode];
+        } else {
+            int64_t so = 1;
+            for (int d = t.nd - 1; d >= 0; --d) {
+                t.ostr[d] = so;
+                so *= cur[d].extent;
+            }
+        }
+        t.U = Um[m];
+        t.ldu = p.Rm[m];
+        t.uprec = o.precision;
+        t.out = dst;
+        t.out_dtype = last ? o.out_dtype : DEINSUM_F64;
+        small_ttm_kernel<<<static_cast<unsigned>(cdivl(t.total, 256)), 256, 0, s>>>(t);
+        if (deinsum_status st2 = check_launch("ttmc_small_ttm")) return st2;
+        src = static_cast<const double *>(dst);
+    }
+    return DEINSUM_OK;
+}
+
+}  // namespace deinsum

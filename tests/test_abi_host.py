@@ -1,0 +1,142 @@
+"""Host-side tests of the C ABI (no GPU): exported symbols, the einsum parser,
+and argument validation that must fail before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2206_08301_amd as m
+    m._lib.load()
+    return m
+
+
+def test_library_exports_every_declared_symbol(dn):
+    header = open(os.path.join(ROOT, "include", "deinsum.h")).read()
+    declared = set(re.findall(r"^(?:deinsum_status|void|const char\s*\*)\s*(deinsum_\w+)\s*\(", header, re.M))
+    assert declared == set(dn._lib.EXPORTS)
+    lib = dn._lib.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version(dn):
+    assert "gfx950" in dn.version()
+
+
+TAB4 = {
+    "ijk,ja,ka->ia": (1, 3, 0, [1, 2]),
+    "ijk,ia,ka->ja": (1, 3, 1, [0, 2]),
+    "ijk,ia,ja->ka": (1, 3, 2, [0, 1]),
+    "ijklm,ja,ka,la,ma->ia": (1, 5, 0, [1, 2, 3, 4]),
+    "ijklm,ia,ja,la,ma->ka": (1, 5, 2, [0, 1, 3, 4]),
+    "ijklm,ia,ja,ka,la->ma": (1, 5, 4, [0, 1, 2, 3]),
+    "ijklm,jb,kc,ld,me->ibcde": (2, 5, 0, [1, 2, 3, 4]),
+}
+
+
+@pytest.mark.parametrize("spec", sorted(TAB4))
+def test_parse_tab4_strings(dn, spec):
+    s = dn.parse(spec)
+    kind, order, free, fm = TAB4[spec]
+    assert (s.kind, s.order, s.free_mode) == (kind, order, free)
+    assert list(s.factor_mode)[: order - 1] == fm
+    assert s.out_idx.decode() == spec.split("->")[1]
+
+
+def test_parse_operand_order_and_whitespace(dn):
+    s = dn.parse(" ijk , ka , ja -> ia ")
+    assert s.kind == 1 and s.free_mode == 0
+    assert list(s.factor_mode)[:2] == [2, 1]
+    assert list(s.operand_of_mode)[:3] == [-1, 1, 0]
+
+
+def test_parse_ttmc_other_modes(dn):
+    s = dn.parse("ijk,ib,kc->bjc")
+    assert s.kind == 2 and s.free_mode == 1
+    s = dn.parse("ij,ia->aj")
+    assert s.kind == 2 and s.free_mode == 1
+    s = dn.parse("ij,ja->ia")
+    assert s.kind == 1  # order 2: the MTTKRP and TTMc outputs coincide
+
+
+@pytest.mark.parametrize("bad,status", [
+    ("ijk,ja,ka", -2),            # implicit output
+    ("...k,ka->...a", -2),        # ellipsis
+    ("iik,ia,ka->ia", -2),        # repeated letter (diagonal)
+    ("ijk,j1,ka->ia", -2),        # non-letter
+    ("ijk,,ka->ia", -2),          # empty operand
+    ("ijk,aj,ka->ia", -3),        # transposed factor
+    ("ijk,ja,ka->ai", -3),        # output permuted
+    ("ijk,ia,ja,ka->ia", -3),     # factor on the free mode / too many factors
+    ("ijk,ja,ja->ia", -3),        # mode contracted twice
+    ("ijk,ja->ia", -3),           # a mode neither free nor contracted
+    ("ijk,ja,kb->ia", -3),        # mixed rank letters, MTTKRP output
+    ("ijk,jb,kc->icb", -3),       # TTMc output not in place
+    ("i,ia->a", -3),              # order 1
+    ("abcdefghi,ba,cz,dz,ez,fz,gz,hz,iz->az", -3),  # order 9
+    ("ijk,jaa,ka->ia", -2),
+])
+def test_parse_rejects(dn, bad, status):
+    with pytest.raises(dn.DeinsumError) as e:
+        dn.parse(bad)
+    assert e.value.status == status
+    assert dn.last_error()
+
+
+def test_workspace_size_host_only(dn):
+    n = dn.workspace_size("ijk,ja,ka->ia", [1024, 1024, 1024], [24])
+    assert 0 < n < 0.02 * 8 * 1024 ** 3
+    n2 = dn.workspace_size("ijk,ia,ja->ka", [1024, 1024, 1024], [24])
+    assert 0 < n2 < 0.02 * 8 * 1024 ** 3
+    n3 = dn.workspace_size("ijk,jb,kc->ibc", [1024, 1024, 1024], [32, 32])
+    assert 0 < n3 < 0.02 * 8 * 1024 ** 3
+
+
+def _call_mttkrp(dn, spec, dims, R, X, U, M, opts=None):
+    lib = dn._lib.load()
+    s = dn.parse(spec)
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    ptrs = (ctypes.c_void_p * len(U))(*U)
+    return lib.deinsum_mttkrp(ctypes.byref(s), d, R, X, ptrs, M,
+                              ctypes.byref(opts) if opts is not None else None, None)
+
+
+def test_mttkrp_argument_errors_before_enqueue(dn):
+    # Fake (never dereferenced) addresses: validation must reject before any launch.
+    X, B, C, M = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, 4, 4], 0, X, [B, C], M) == -4       # R < 1
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, 4, 4], 300, X, [B, C], M) == -4     # R > 256
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, -1, 4], 2, X, [B, C], M) == -4      # negative dim
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, 4, 4], 2, X, [B, None], M) == -1    # null factor
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, 4, 4], 2, X, [B, C], X + 8) == -1   # M overlaps X
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, 4, 4], 2, X, [B, C], B) == -1       # M overlaps a factor
+    o = dn._lib.Opts()
+    dn._lib.load().deinsum_opts_init(ctypes.byref(o))
+    o.precision = 9
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, 4, 4], 2, X, [B, C], M, o) == -1    # bad precision
+    o.precision = 0
+    o.out_dtype = 1
+    assert _call_mttkrp(dn, "ijk,ja,ka->ia", [4, 4, 4], 2, X, [B, C], M, o) == -1    # FP64 form, F32 out
+    lib = dn._lib.load()
+    s = dn.parse("ijk,jb,kc->ibc")
+    d = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert lib.deinsum_mttkrp(ctypes.byref(s), d, 2, X, (ctypes.c_void_p * 2)(B, C), M, None, None) == -1  # TTMc spec
+
+
+def test_ttmc_rank_limit(dn):
+    with pytest.raises(dn.DeinsumError):
+        dn.workspace_size("ijk,jb,kc->ibc", [8, 8, 8], [65, 4])
+
+
+def test_synth_and_convert_argument_errors(dn):
+    lib = dn._lib.load()
+    assert lib.deinsum_synth_fill(None, 0, 10, 1, 0, 0, None) == -1
+    assert lib.deinsum_synth_fill(ctypes.c_void_p(0x1000), 0, 10, 1, 0, 7, None) == -1
+    assert lib.deinsum_synth_fill(None, 0, 0, 1, 0, 0, None) == 0  # nothing to do
+    assert lib.deinsum_convert(ctypes.c_void_p(0x1000), 0, ctypes.c_void_p(0x1008), 1, 10, None) == -1

@@ -1,0 +1,202 @@
+"""GPU parity of the HIP MTTKRP path against the CPU oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import SPEC3, flush, mttkrp_spec, nrel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2206_08301_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    m._lib.load()
+    return m
+
+
+def run(dn, spec, X, U, **kw):
+    out = dn.einsum(spec, X, *U, **kw)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy()
+
+
+def factors_for(rng, dims, R, n):
+    return [None if m == n else rng.standard_normal((d, R)) for m, d in enumerate(dims)]
+
+
+def operands(U, n):
+    return [u for m, u in enumerate(U) if m != n]
+
+
+# ------------------------------------------------------------------ input generator
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("dist", ["uniform", "int5", "int3"])
+def test_device_generator_matches_host(dn, synth, dtype, dist):
+    n, off, seed = 300_001, 12345, 2206083111
+    t = torch.empty(n, dtype=dtype, device="cuda")
+    dn.synth_fill(t, seed, dist=dist, offset=off)
+    host = synth.x_values(seed, np.arange(off, off + n, dtype=np.uint64), dist)
+    got = t.cpu()
+    if dtype == torch.float64:
+        assert np.array_equal(got.numpy(), host)
+    elif dtype == torch.float32:
+        assert np.array_equal(got.numpy(), host.astype(np.float32))
+    else:
+        ref = synth.bf16_round(host.astype(np.float32))
+        assert np.array_equal(got.float().numpy(), ref)
+
+
+# ------------------------------------------------------------------ small config (64^3, R=16)
+def test_small_config_mode0(dn, synth, oracle_mod):
+    dims, R = (64, 64, 64), 16
+    X = synth.x_tensor(synth.config_seed(1, 0), dims)
+    U = [None] + [synth.normal_factor(synth.config_seed(1, 1 + m), 64, R) for m in (1, 2)]
+    ref = oracle_mod.mttkrp(X, U, 0)
+    got = run(dn, SPEC3[0], to_dev(X), [to_dev(u) for u in U[1:]])
+    assert nrel(got, ref) <= 1e-12
+
+
+SHAPES = [
+    ((97, 80, 33), (1, 8, 24)),
+    ((33, 17, 45), (16, 64)),
+    ((16, 64, 128), (24, 100)),
+    ((5, 3, 130), (3,)),
+    ((40, 50), (24, 7)),
+    ((12, 7, 9, 20), (24,)),
+    ((6, 5, 4, 7, 80), (24,)),
+    ((7, 9, 6, 8, 5), (5, 33)),
+]
+
+
+@pytest.mark.parametrize("dims,Rs", SHAPES)
+def test_fp64_all_modes(dn, oracle_mod, dims, Rs):
+    rng = np.random.default_rng(sum(dims))
+    X = rng.uniform(-1, 1, dims)
+    Xd = to_dev(X)
+    for R in Rs:
+        for n in range(len(dims)):
+            flush(f"fp64 dims={dims} R={R} n={n}")
+            U = factors_for(rng, dims, R, n)
+            ref = oracle_mod.mttkrp(X, U, n)
+            got = run(dn, mttkrp_spec(len(dims), n), Xd, [to_dev(u) for u in operands(U, n)])
+            assert nrel(got, ref) <= 1e-12, (dims, R, n)
+
+
+def test_operand_order_is_respected(dn, oracle_mod):
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-1, 1, (9, 10, 11))
+    B, C = rng.standard_normal((10, 4)), rng.standard_normal((11, 4))
+    ref = oracle_mod.mttkrp(X, [None, B, C], 0)
+    got = run(dn, "ijk,ka,ja->ia", to_dev(X), [to_dev(C), to_dev(B)])
+    assert nrel(got, ref) <= 1e-12
+
+
+FORMS_LAST_OK = {"fp64", "fp32"}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "bf16x3"])
+@pytest.mark.parametrize("dims", [(37, 64, 96), (16, 21, 130), (6, 5, 7, 48), (64, 64, 64)])
+def test_integer_inputs_exact_every_form(dn, synth, oracle_mod, precision, dims):
+    """Entries in {-2..2}: every partial sum is an integer below 2^24, exact in all forms."""
+    rng = np.random.default_rng(len(dims) * 7 + dims[0])
+    X = synth.x_tensor(77, dims, "int5")
+    xdt = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16, "bf16x3": torch.float32}[precision]
+    udt = torch.float64 if precision == "fp64" else torch.float32
+    Xd = to_dev(X, xdt)
+    for n in range(len(dims)):
+        if n == len(dims) - 1 and precision not in FORMS_LAST_OK:
+            continue
+        flush(f"int {precision} dims={dims} n={n}")
+        U = [None if m == n else rng.integers(-2, 3, (d, 20)).astype(np.float64) for m, d in enumerate(dims)]
+        ref = oracle_mod.mttkrp(X, U, n)
+        got = run(dn, mttkrp_spec(len(dims), n), Xd, [to_dev(u, udt) for u in operands(U, n)],
+                  precision=precision, out_dtype=torch.float64)
+        assert np.array_equal(got, ref), (precision, dims, n)
+
+
+def test_run_to_run_bitwise(dn):
+    rng = np.random.default_rng(3)
+    X = to_dev(rng.uniform(-1, 1, (128, 96, 160)))
+    U = [to_dev(rng.standard_normal((d, 24))) for d in (128, 96, 160)]
+    for n in range(3):
+        ops = [U[m] for m in range(3) if m != n]
+        a = dn.einsum(SPEC3[n], X, *ops)
+        b = dn.einsum(SPEC3[n], X, *ops)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("bf16x3", 1e-5), ("bf16", 2e-2)])
+def test_mixed_precision_error(dn, synth, oracle_mod, precision, tol):
+    dims, R = (96, 128, 256), 24
+    X = synth.x_tensor(4242, dims)
+    rng = np.random.default_rng(9)
+    xdt = torch.bfloat16 if precision == "bf16" else torch.float32
+    Xd = to_dev(X, torch.float32) if xdt == torch.float32 else to_dev(X, torch.float32).to(torch.bfloat16)
+    for n in range(3):
+        if n == 2 and precision not in FORMS_LAST_OK:
+            continue
+        U = factors_for(rng, dims, R, n)
+        ref = oracle_mod.mttkrp(X, U, n)
+        got = run(dn, SPEC3[n], Xd, [to_dev(u, torch.float32) for u in operands(U, n)], precision=precision)
+        err = nrel(got, ref)
+        flush(f"{precision} mode {n}: normwise error {err:.3e}")
+        assert err <= tol
+
+
+def test_degenerate_and_empty(dn, oracle_mod):
+    rng = np.random.default_rng(4)
+    for dims in [(1, 1, 1), (1, 5, 1), (3, 1, 7), (1, 1, 300)]:
+        X = rng.uniform(-1, 1, dims)
+        for n in range(3):
+            U = factors_for(rng, dims, 1, n)
+            got = run(dn, SPEC3[n], to_dev(X), [to_dev(u) for u in operands(U, n)])
+            assert nrel(got, oracle_mod.mttkrp(X, U, n)) <= 1e-12
+    # an empty contracted mode: the sum is empty, M = 0
+    X = torch.empty((5, 0, 4), dtype=torch.float64, device="cuda")
+    B = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    C = torch.ones((4, 3), dtype=torch.float64, device="cuda")
+    out = torch.full((5, 3), 7.0, dtype=torch.float64, device="cuda")
+    dn.einsum(SPEC3[0], X, B, C, out=out)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(out).item() == 0
+
+
+def test_output_canaries_untouched(dn, oracle_mod):
+    rng = np.random.default_rng(6)
+    dims, R = (50, 40, 70), 24
+    X = rng.uniform(-1, 1, dims)
+    for n in range(3):
+        U = factors_for(rng, dims, R, n)
+        buf = torch.full((dims[n] * R + 2048,), -123.5, dtype=torch.float64, device="cuda")
+        out = buf[1024:1024 + dims[n] * R].view(dims[n], R)
+        dn.einsum(SPEC3[n], to_dev(X), *[to_dev(u) for u in operands(U, n)], out=out)
+        torch.cuda.synchronize()
+        assert torch.all(buf[:1024] == -123.5) and torch.all(buf[1024 + dims[n] * R:] == -123.5)
+        assert nrel(out.cpu().numpy(), oracle_mod.mttkrp(X, U, n)) <= 1e-12
+
+
+def test_full_size_1024cubed_sampled_rows(dn, synth, oracle_mod):
+    """X 1024^3 FP64 generated on the device (8 GiB), R = 24, every mode, in the
+    benchmark's launch configuration; sampled output rows against the oracle on
+    host slabs produced by the host generator."""
+    dims, R = (1024, 1024, 1024), 24
+    seed = synth.config_seed(2, 0)
+    X = torch.empty(dims, dtype=torch.float64, device="cuda")
+    dn.synth_fill(X, seed)
+    U = [synth.normal_factor(synth.config_seed(2, 1 + m), 1024, R) for m in range(3)]
+    Ud = [to_dev(u) for u in U]
+    for n in range(3):
+        flush(f"1024^3 mode {n}")
+        M = dn.einsum(SPEC3[n], X, *[Ud[m] for m in range(3) if m != n])
+        torch.cuda.synchronize()
+        Mh = M.cpu().numpy()
+        for i in (0, 517, 1023):
+            slab = synth.x_slab(seed, dims, n, i)
+            Un = [None if m == n else U[m] for m in range(3)]
+            ref = oracle_mod.mttkrp(slab, Un, n)[0]
+            assert nrel(Mh[i], ref) <= 1e-12, (n, i)
+    del X
+    torch.cuda.empty_cache()

@@ -1,0 +1,96 @@
+"""GPU parity of the HIP TTMc path against the CPU oracle (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import flush, nrel, to_dev, ttmc_spec
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2206_08301_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    m._lib.load()
+    return m
+
+
+CASES = [
+    ((20, 30, 40), (5, 7, 9)),
+    ((64, 70, 130), (16, 32, 24)),
+    ((9, 11, 13, 17), (3, 4, 5, 6)),
+    ((6, 7, 5, 8, 9), (2, 3, 4, 3, 2)),
+    ((33, 47), (5, 6)),
+]
+
+
+@pytest.mark.parametrize("dims,ranks", CASES)
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_ttmc_all_modes(dn, oracle_mod, dims, ranks, precision, tol):
+    rng = np.random.default_rng(sum(dims) + len(precision))
+    X = rng.uniform(-1, 1, dims)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Xd = to_dev(X, dt)
+    for n in range(len(dims)):
+        flush(f"ttmc {precision} dims={dims} n={n}")
+        U = [None if m == n else rng.standard_normal((d, ranks[m])) for m, d in enumerate(dims)]
+        ref = oracle_mod.ttmc(X, U, n)
+        got = dn.einsum(ttmc_spec(len(dims), n), Xd, *[to_dev(u, dt) for u in U if u is not None],
+                        precision=precision, out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert nrel(got.cpu().numpy(), ref) <= tol, (dims, n)
+
+
+def test_ttmc_integer_exact(dn, synth, oracle_mod):
+    dims = (40, 64, 96)
+    X = synth.x_tensor(99, dims, "int5")
+    rng = np.random.default_rng(1)
+    for precision, dt in [("fp64", torch.float64), ("fp32", torch.float32)]:
+        for n in range(3):
+            U = [None if m == n else rng.integers(-2, 3, (d, 16)).astype(np.float64) for m, d in enumerate(dims)]
+            ref = oracle_mod.ttmc(X, U, n)
+            got = dn.einsum(ttmc_spec(3, n), to_dev(X, dt), *[to_dev(u, dt) for u in U if u is not None],
+                            precision=precision, out_dtype=torch.float64)
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), ref), (precision, n)
+
+
+def test_ttmc_identity_factors_return_x(dn):
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, (12, 16, 20))
+    Xd = to_dev(X)
+    got = dn.einsum("ijk,jb,kc->ibc", Xd, to_dev(np.eye(16)), to_dev(np.eye(20)))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), X)
+
+
+def test_mttkrp_equals_ttmc_diagonal(dn):
+    rng = np.random.default_rng(3)
+    X = to_dev(rng.uniform(-1, 1, (50, 60, 70)))
+    B, C = to_dev(rng.standard_normal((60, 16))), to_dev(rng.standard_normal((70, 16)))
+    M = dn.einsum("ijk,ja,ka->ia", X, B, C)
+    Y = dn.einsum("ijk,jb,kc->ibc", X, B, C)
+    torch.cuda.synchronize()
+    assert nrel(M.cpu().numpy(), torch.diagonal(Y, dim1=1, dim2=2).cpu().numpy()) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,rank", [((1024, 1024, 1024), 32), ((192, 192, 192, 192), 16)])
+def test_full_size_sampled_slabs(dn, synth, oracle_mod, dims, rank):
+    """TTMc mode 0 at the full Tucker-step sizes (orthonormal factors), sampled slabs."""
+    N = len(dims)
+    cfg = 4
+    seed = synth.config_seed(cfg, 0) + (0 if N == 3 else 50)
+    X = torch.empty(dims, dtype=torch.float64, device="cuda")
+    dn.synth_fill(X, seed)
+    U = [None] + [synth.orthonormal_factor(synth.config_seed(cfg, 1 + m) + (0 if N == 3 else 50), dims[m], rank)
+                  for m in range(1, N)]
+    flush(f"ttmc full {dims}")
+    Y = dn.einsum(ttmc_spec(N, 0), X, *[to_dev(u) for u in U[1:]])
+    torch.cuda.synchronize()
+    for i in (0, dims[0] // 2 + 1, dims[0] - 1):
+        slab = synth.x_slab(seed, dims, 0, i)
+        ref = oracle_mod.ttmc(slab, U, 0)[0]
+        assert nrel(Y[i].cpu().numpy(), ref) <= 1e-12, i
+    del X
+    torch.cuda.empty_cache()
