@@ -1,0 +1,259 @@
+"""Benchmark: dense MTTKRP on one MI355X at the one-GPU tile shape.
+
+Workload (one step): X of shape 1024 x 1024 x 1024, FP64, entries uniform in
+[-1, 1) from the counter-based generator; three factors 1024 x 24, N(0,1);
+MTTKRP in every mode (0, 1, 2) in the plain FP64 form.  X and the factors are
+resident in HBM before the timed region.  The JSON line reports GFLOP/s of the
+two-stage method, the HBM roofline of the dominant kernel, the mixed-precision
+forms (X stored FP32 / BF16) with their error against the FP64 oracle on
+sampled rows, the Tucker-step TTMc (1024^3, ranks 32) and the CPU oracle timed
+on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DIMS = (1024, 1024, 1024)
+R = 24
+SPECS = {0: "ijk,ja,ka->ia", 1: "ijk,ia,ka->ja", 2: "ijk,ia,ja->ka"}
+
+
+def parse_args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and TTMc fields")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--only", default="", help="profiling: run just one form (fp64|fp32|bf16|bf16x3|ttmc)")
+    return ap.parse_args()
+
+
+def alg_counts(dims, R, n, xbytes):
+    """Algorithmic bytes (X once, factors once, output once) and two-stage flops."""
+    nx = 1
+    for d in dims:
+        nx *= d
+    fac = sum(d for m, d in enumerate(dims) if m != n) * R
+    ub = 8 if xbytes == 8 else 4
+    byts = nx * xbytes + fac * ub + dims[n] * R * 8
+    g = len(dims) - 2 if n == len(dims) - 1 else len(dims) - 1
+    flops = 2 * nx * R + 2 * (nx // dims[g]) * R * max(1, len(dims) - 2)
+    return byts, flops
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is not part of it",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2206_08301_amd as dn
+    from paper_2206_08301_amd import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    seed = synth.config_seed(2, 0)
+
+    print(f"[bench] generating X {DIMS} fp64 on the device", file=sys.stderr, flush=True)
+    X = torch.empty(DIMS, dtype=torch.float64, device=dev)
+    dn.synth_fill(X, seed)
+    U = [synth.normal_factor(synth.config_seed(2, 1 + m), DIMS[m], R) for m in range(3)]
+    Ud = [torch.from_numpy(u).to(dev) for u in U]
+    Uf = [u.float() for u in Ud]
+    ops = {n: [Ud[m] for m in range(3) if m != n] for n in range(3)}
+    opsf = {n: [Uf[m] for m in range(3) if m != n] for n in range(3)}
+    outs = {n: torch.empty((DIMS[n], R), dtype=torch.float64, device=dev) for n in range(3)}
+    reports = {n: dn.Report() for n in range(3)}
+    torch.cuda.synchronize()
+
+    def step():
+        for n in range(3):
+            dn.mttkrp(SPECS[n], X, ops[n], out=outs[n])
+
+    # ---- the timed step (FP64, three modes)
+    steps, warmup = args.steps, args.warmup
+    if args.only and args.only != "fp64":
+        steps = 0
+    ms_step = float("nan")
+    per_mode_ms = {0: [], 1: [], 2: []}
+    if steps:
+        for n in range(3):
+            dn.mttkrp(SPECS[n], X, ops[n], out=outs[n], report=reports[n])
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        ms_step = (time.perf_counter() - t0) * 1e3 / steps
+        # per-call durations with HIP events on the launch stream
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        for s in range(steps):
+            ev[s][0].record(stream)
+            for n in range(3):
+                dn.mttkrp(SPECS[n], X, ops[n], out=outs[n])
+                ev[s][n + 1].record(stream)
+        torch.cuda.synchronize()
+        for s in range(steps):
+            for n in range(3):
+                per_mode_ms[n].append(ev[s][n].elapsed_time(ev[s][n + 1]))
+
+    flops_step = sum(alg_counts(DIMS, R, n, 8)[1] for n in range(3))
+    bytes_mode = {n: alg_counts(DIMS, R, n, 8)[0] for n in range(3)}
+    result = {
+        "metric": "MTTKRP/TTMc GFLOP/s & %roofline (FP64 vs mixed); p99 latency batched",
+        "value": round(flops_step / (ms_step / 1e3) / 1e9, 1) if steps else None,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(ms_step, 4) if steps else None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (counter-based SplitMix64 X, uniform [-1,1); N(0,1) factors)",
+        "config": {"workload": "MTTKRP order 3, X 1024x1024x1024 FP64, R=24, modes 0+1+2 per step",
+                   "global_batch": 1, "parallelism": "single GPU"},
+    }
+    if steps:
+        med = {n: statistics.median(per_mode_ms[n]) for n in range(3)}
+        gbs = {n: bytes_mode[n] / (med[n] / 1e3) / 1e9 for n in range(3)}
+        # dominant kernel: the K-contiguous MTTKRP (modes 0 and 1: two of three launches)
+        dom_ms = (med[0] + med[1]) / 2
+        dom_gbs = bytes_mode[0] / (dom_ms / 1e3) / 1e9
+        result["roofline"] = {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                              "kernel": "mttkrp_kcontig (FP64, modes 0 and 1; duration includes the fixed-order reduce)"}
+        result["modes"] = {str(n): {"ms": round(med[n], 4), "GB/s": round(gbs[n], 1),
+                                     "frac_hbm": round(gbs[n] / HBM_PEAK_GBS, 4),
+                                     "GFLOP/s": round(alg_counts(DIMS, R, n, 8)[1] / (med[n] / 1e3) / 1e9, 1),
+                                     "plan": reports[n].plan_name.decode()} for n in range(3)}
+
+    # ---- parity spot check of the timed outputs (sampled rows against the oracle)
+    import oracle
+    checks = {}
+
+    def sampled_error(Mdev_by_mode, rows=(3, 700)):
+        errs = []
+        for n, Md in Mdev_by_mode.items():
+            Mh = Md.double().cpu().numpy()
+            Un = [None if m == n else U[m] for m in range(3)]
+            for i in rows:
+                ref = oracle.mttkrp(synth.x_slab(seed, DIMS, n, i), Un, n)[0]
+                errs.append(float(np.linalg.norm(Mh[i] - ref) / np.linalg.norm(ref)))
+        return max(errs)
+
+    if steps:
+        checks["fp64_max_rel_err_sampled"] = sampled_error(outs)
+
+    # ---- mixed-precision forms and TTMc (extras)
+    if not args.no_extras:
+        forms = {}
+        X32 = torch.empty(DIMS, dtype=torch.float32, device=dev)
+        dn.convert(X, X32)
+        Xb = None
+        todo = ["fp32", "bf16x3", "bf16"] if not args.only else ([args.only] if args.only in ("fp32", "bf16x3", "bf16") else [])
+        for prec in todo:
+            if prec == "bf16" and Xb is None:
+                Xb = torch.empty(DIMS, dtype=torch.bfloat16, device=dev)
+                dn.convert(X, Xb)
+            Xp = Xb if prec == "bf16" else X32
+            modes = [0, 1, 2] if prec == "fp32" else [0, 1]
+            o32 = {n: torch.empty((DIMS[n], R), dtype=torch.float32, device=dev) for n in modes}
+            for _ in range(2):
+                for n in modes:
+                    dn.mttkrp(SPECS[n], Xp, opsf[n], precision=prec, out=o32[n])
+            torch.cuda.synchronize()
+            res = {}
+            for n in modes:
+                evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+                evs[0].record(stream)
+                for k in range(10):
+                    dn.mttkrp(SPECS[n], Xp, opsf[n], precision=prec, out=o32[n])
+                    evs[k + 1].record(stream)
+                torch.cuda.synchronize()
+                t = statistics.median(evs[k].elapsed_time(evs[k + 1]) for k in range(10))
+                xb = 2 if prec == "bf16" else 4
+                b, f = alg_counts(DIMS, R, n, xb)
+                res[str(n)] = {"ms": round(t, 4), "GB/s": round(b / (t / 1e3) / 1e9, 1),
+                               "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "GFLOP/s": round(f / (t / 1e3) / 1e9, 1)}
+                if steps:
+                    res[str(n)]["speedup_vs_fp64"] = round(med[n] / t, 3)
+            err = sampled_error(o32)
+            forms[prec] = {"x_storage": "bf16" if prec == "bf16" else "f32", "modes": res,
+                           "max_rel_err_sampled_vs_fp64_oracle": err}
+            print(f"[bench] {prec}: {res} err {err:.2e}", file=sys.stderr, flush=True)
+        if forms:
+            result["mixed_forms"] = forms
+        del X32, Xb
+        torch.cuda.empty_cache()
+        if not args.only or args.only == "ttmc":
+            Rt = 32
+            Bt = [torch.from_numpy(synth.orthonormal_factor(synth.config_seed(4, 1 + m), 1024, Rt)).to(dev)
+                  for m in (1, 2)]
+            Y = torch.empty((1024, Rt, Rt), dtype=torch.float64, device=dev)
+            for _ in range(2):
+                dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y)
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+            evs[0].record(stream)
+            for k in range(10):
+                dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y)
+                evs[k + 1].record(stream)
+            torch.cuda.synchronize()
+            t = statistics.median(evs[k].elapsed_time(evs[k + 1]) for k in range(10))
+            nx = 1024 ** 3
+            b = nx * 8 + 2 * 1024 * Rt * 8 + 1024 * Rt * Rt * 8
+            f = 2 * nx * Rt + 2 * 1024 * 1024 * Rt * Rt
+            Bh = [None] + [b_.cpu().numpy() for b_ in Bt]
+            errs = []
+            for i in (5, 999):
+                ref = oracle.ttmc(synth.x_slab(seed, DIMS, 0, i), Bh, 0)[0]
+                errs.append(float(np.linalg.norm(Y[i].cpu().numpy() - ref) / np.linalg.norm(ref)))
+            result["ttmc"] = {"workload": "TTMc order 3 mode 0, X 1024^3 FP64, B and C 1024x32 orthonormal",
+                              "ms": round(t, 4), "GB/s": round(b / (t / 1e3) / 1e9, 1),
+                              "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                              "GFLOP/s": round(f / (t / 1e3) / 1e9, 1), "max_rel_err_sampled": max(errs)}
+    result["checks"] = checks
+
+    # ---- CPU oracle on a bounded sample of the same workload (mode 0, some output rows)
+    if not args.no_cpu:
+        rows = int(os.environ.get("BENCH_CPU_ROWS", "512"))
+        Un = [None, U[1], U[2]]
+        t = 0.0
+        for r0 in range(0, rows, 64):  # generate 64 output rows' slab at a time; time only the oracle
+            r1 = min(rows, r0 + 64)
+            X_sample = synth.x_range(seed, r0 * 1024 * 1024, (r1 - r0) * 1024 * 1024).reshape(r1 - r0, 1024, 1024)
+            t0 = time.perf_counter()
+            oracle.mttkrp(X_sample, Un, 0)
+            t += time.perf_counter() - t0
+            del X_sample
+        f = alg_counts((rows, 1024, 1024), R, 0, 8)[1]
+        result["cpu_baseline"] = {"value": round(f / t / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"MTTKRP mode 0 on {rows} of the 1024 output rows of the same X and "
+                                            f"factors ({rows}x1024x1024 of X in host RAM, 64 rows at a time, generation excluded), "
+                                            f"{t:.1f} s; flops counted as for the GPU"}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -6,7 +6,7 @@
  * Multilinear Algebra", arXiv 2206.08301):
  *   - mode-n MTTKRP (Sec. III-B; benchmark forms MTTKRP-O3-M{0,1,2} and
  *     MTTKRP-O5-M{0,2,4} of Tab. IV), computed without ever forming the
- *     Khatri-Rao product in memory (the fused schedule of Sec. IV-D);
+ *     Khatri-Rao product in memory (the fused schedule of Sec. IV-E);
  *   - the mode-n TTM chain, TTMc (Sec. III-B; TTMc-O5-M0 of Tab. IV).
  * Problems are stated in Einstein notation (Sec. III-A), as the paper's
  * front end takes them; the parser accepts exactly these two families.
@@ -24,7 +24,8 @@
  *   - Arrays named X, U, M, Y, workspace are DEVICE pointers owned by the
  *     caller; the library never frees or retains them.  dims / ranks are
  *     host arrays read during the call only.  Device pointers must be
- *     16-byte aligned.
+ *     aligned to their element size; 16-byte alignment (torch's default)
+ *     lets the kernels use vector loads.
  *   - The output is overwritten (the paper zero-initialises, then
  *     accumulates); it must not overlap X or any factor.
  *   - Argument errors are reported synchronously and nothing is enqueued.

@@ -159,6 +159,8 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
     const MttkrpProblem &pb = c.pb;
     const MttkrpPlan &p = c.plan;
     const int N = pb.N, n = pb.n;
+    const bool kcontig = p.family == PLAN_MTTKRP_KCONTIG;
+    const int gmode = kcontig ? N - 1 : N - 2;
     const size_t ub = u_elem_bytes(pb.prec), xb = x_elem_bytes(pb.prec);
     int64_t stride[DEINSUM_MAX_ORDER];
     {
@@ -175,71 +177,42 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
         auto ucol = [&](int m) {
             return static_cast<const void *>(static_cast<const char *>(c.U[m]) + col0 * ub);
         };
-        double *P = static_cast<double *>(ws);
-        if (p.family == PLAN_MTTKRP_KCONTIG) {
-            Mk1Args a{};
-            a.X = c.X;
-            a.Ug = ucol(N - 1);
-            a.ldu = pb.R;
-            int k = 0;
-            for (int m = 0; m < N - 1; ++m) {
-                if (m == n) continue;
-                a.od.dim[k] = pb.dims[m];
-                a.od.xstride[k] = stride[m];
-                a.od.U[k] = ucol(m);
-                ++k;
-            }
-            a.od.n_outer = k;
-            a.In = pb.dims[n];
-            a.stride_n = stride[n];
-            a.Ig = pb.dims[N - 1];
-            a.ncols = ncols;
-            a.n_tiles = static_cast<int>(p.n_tiles);
-            a.n_kgroups = static_cast<int>(p.n_kgroups);
-            a.wk = p.wk;
-            a.wo = p.wo;
-            a.O = 1;
-            for (int i = 0; i < k; ++i) a.O *= a.od.dim[i];
-            a.o_per_chunk = p.o_per_chunk;
-            a.vec_ok = ((a.Ig * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
-            a.P = P;
-            if (deinsum_status st = launch_mttkrp_kcontig(pb.prec, p.nt, p.kl, a, p.groups, s)) return st;
-            if (deinsum_status st = launch_reduce_partials(P, p.parts, p.n_tiles, 16, cols_pad, pb.dims[n], ncols,
-                                                           static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
-                                                           c.out_dtype, pb.R, s))
-                return st;
-        } else {
-            Mk2Args a{};
-            a.X = c.X;
-            a.Ug = ucol(N - 2);
-            a.ldu = pb.R;
-            int k = 0;
-            for (int m = 0; m < N - 2; ++m) {
-                a.od.dim[k] = pb.dims[m];
-                a.od.xstride[k] = stride[m];
-                a.od.U[k] = ucol(m);
-                ++k;
-            }
-            a.od.n_outer = k;
-            a.In = pb.dims[N - 1];
-            a.Ig = pb.dims[N - 2];
-            a.stride_g = stride[N - 2];
-            a.ncols = ncols;
-            a.n_tiles = static_cast<int>(p.n_tiles);
-            a.O = 1;
-            for (int i = 0; i < k; ++i) a.O *= a.od.dim[i];
-            a.o_per_chunk = p.o_per_chunk;
-            a.n_igchunks = p.n_igchunks;
-            a.ig_per_chunk = p.ig_per_chunk;
-            a.vec_ok = ((a.In * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
-            a.P = P;
-            if (deinsum_status st = launch_mttkrp_mcontig(pb.prec, p.nt, p.mt, a, p.groups, s)) return st;
-            if (deinsum_status st = launch_reduce_partials(P, p.parts, p.n_tiles, 16 * p.mt, cols_pad, pb.dims[N - 1],
-                                                           ncols,
-                                                           static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
-                                                           c.out_dtype, pb.R, s))
-                return st;
+        StreamArgs a{};
+        a.X = c.X;
+        a.Ug = ucol(gmode);
+        a.ldu = pb.R;
+        int k = 0;
+        for (int m = 0; m < N; ++m) {
+            if (m == n || m == gmode) continue;
+            a.od.dim[k] = pb.dims[m];
+            a.od.xstride[k] = stride[m];
+            a.od.U[k] = ucol(m);
+            ++k;
         }
+        a.od.n_outer = k;
+        a.In = pb.dims[n];
+        a.Ig = pb.dims[gmode];
+        a.stride_n = stride[n];
+        a.stride_g = stride[gmode];
+        a.ncols = ncols;
+        a.n_tiles = static_cast<int>(p.n_tiles);
+        a.n_kgroups = static_cast<int>(p.n_kgroups);
+        a.wk = p.wk;
+        a.O = 1;
+        for (int i = 0; i < k; ++i) a.O *= a.od.dim[i];
+        a.o_per_chunk = p.o_per_chunk;
+        const int64_t contig = kcontig ? a.Ig : a.In;  // extent of the contiguous mode
+        a.vec_ok = ((contig * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
+        a.P = static_cast<double *>(ws);
+        double *W = reinterpret_cast<double *>(static_cast<char *>(ws) + p.w_offset);
+        a.W = W;
+        a.ldw = cols_pad;
+        if (deinsum_status st = launch_outer_weights(a.od, a.O, pb.R, ncols, cols_pad, pb.prec, W, s)) return st;
+        if (deinsum_status st = launch_mttkrp_stream(*p.kernel, a, p.groups, p.waves, s)) return st;
+        if (deinsum_status st = launch_reduce_partials(a.P, p.parts, p.n_tiles, p.tile_rows, cols_pad, pb.dims[n],
+                                                       ncols, static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
+                                                       c.out_dtype, pb.R, s))
+            return st;
     }
     return DEINSUM_OK;
 }
@@ -249,8 +222,8 @@ void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p
     if (!r) return;
     std::memset(r, 0, sizeof(*r));
     r->plan_id = p.family;
-    r->tile_m = p.family == PLAN_MTTKRP_KCONTIG ? 16 : 16 * p.mt;
-    r->tile_k = p.family == PLAN_MTTKRP_KCONTIG ? 4 * p.kl : 4;
+    r->tile_m = p.tile_rows;
+    r->tile_k = p.slice;
     r->waves_per_group = p.waves;
     r->groups = p.groups * p.col_blocks;
     r->partials = p.parts;

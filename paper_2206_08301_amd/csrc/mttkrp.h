@@ -1,4 +1,4 @@
-// mttkrp.h -- launch arguments of the MTTKRP kernels (host <-> device).
+// mttkrp.h -- launch interface of the MTTKRP streaming kernel (host <-> device).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,43 +9,45 @@
 
 namespace deinsum {
 
-// K-contiguous form (free mode n < N-1); g = N-1.
-struct Mk1Args {
+enum StreamLayout {
+    L_KCONTIG = 0,  // free mode n < N-1, matrix-core K over the contiguous mode N-1
+    L_MCONTIG = 1,  // free mode n = N-1 (the contiguous one), K over mode N-2
+};
+
+// One launch processes one column block of the output.
+//   grid  = n_chunks * n_tiles * n_kgroups workgroups of `waves` waves;
+//   block b: kgroup = b % n_kgroups, tile = (b / n_kgroups) % n_tiles, chunk = rest;
+//   wave w: slice kgroup*wk + w % wk of mode g, outer sub-range w / wk of the chunk.
+struct StreamArgs {
     const void *X;
-    const void *Ug;      // U^{N-1}, column block applied; row stride ldu
+    const void *Ug;      // factor of mode g, column block applied; row stride ldu
     int64_t ldu;
-    OuterDesc od;        // modes other than n and N-1
-    int64_t In, stride_n, Ig;
+    OuterDesc od;        // modes other than n and g
+    int64_t In, Ig;      // sizes of the free mode and of mode g
+    int64_t stride_n;    // X stride of the free mode (K-contiguous layout)
+    int64_t stride_g;    // X stride of mode g (M-contiguous layout)
     int ncols;           // valid columns in this block (<= 16 * NT)
-    int n_tiles;         // ceil(In / 16)
-    int n_kgroups;       // ceil(Ig / (4 * KL * wk))
-    int wk, wo;          // per workgroup: k-slices and outer sub-ranges (wk * wo = waves)
+    int n_tiles;         // free-mode tiles (16 or 16*MT indices)
+    int n_kgroups;       // groups of wk slices of mode g
+    int wk;              // slices per workgroup
     int64_t O, o_per_chunk;
-    int vec_ok;          // X rows allow 16-byte aligned vector loads
-    double *P;           // partials [chunks * n_kgroups][n_tiles][16][16 * NT]
+    int vec_ok;          // X allows 16-byte aligned vector loads
+    const double *W;     // outer weights [O][ldw] (outer_weights_kernel)
+    int64_t ldw;         // = 16 * NT
+    double *P;           // partials [n_chunks * n_kgroups][n_tiles][tile_rows][16 * NT]
 };
 
-// M-contiguous form (free mode n = N-1); g = N-2.
-struct Mk2Args {
-    const void *X;
-    const void *Ug;      // U^{N-2}, column block applied
-    int64_t ldu;
-    OuterDesc od;        // modes 0..N-3
-    int64_t In, Ig, stride_g;
-    int ncols;
-    int n_tiles;         // ceil(In / (16 * MT))
-    int64_t O, o_per_chunk;
-    int64_t n_igchunks, ig_per_chunk;  // i_g split across workgroups
-    int vec_ok;
-    double *P;           // partials [ochunks * n_igchunks][n_tiles][16 * MT][16 * NT]
+struct StreamKernelInfo {
+    int prec, layout, nt, ni, mt, nbuf;
+    void (*fn)(const StreamArgs &, int64_t grid, int waves, hipStream_t s);
 };
 
-bool kcontig_available(int prec, int nt, int kl);
-bool mcontig_available(int prec, int nt, int mt);
-deinsum_status launch_mttkrp_kcontig(int prec, int nt, int kl, const Mk1Args &a, int64_t grid,
-                                     hipStream_t s);
-deinsum_status launch_mttkrp_mcontig(int prec, int nt, int mt, const Mk2Args &a, int64_t grid,
-                                     hipStream_t s);
+// Every compiled kernel variant.
+const StreamKernelInfo *stream_kernels(int *count);
+deinsum_status launch_mttkrp_stream(const StreamKernelInfo &k, const StreamArgs &a, int64_t grid, int waves,
+                                    hipStream_t s);
+deinsum_status launch_outer_weights(const OuterDesc &od, int64_t O, int64_t ldu, int ncols, int ldw, int prec,
+                                    double *W, hipStream_t s);
 deinsum_status launch_reduce_partials(const double *P, int64_t nparts, int64_t n_tiles, int tile_rows,
                                       int cols_pad, int64_t rows, int ncols, void *out, int out_dtype,
                                       int64_t ldo, hipStream_t s);

@@ -381,8 +381,10 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
     if (remaining) {
         p.z_bytes = static_cast<size_t>(zel) * 8;
         p.t_bytes = p.z_bytes;  // every later intermediate is no larger (ranks <= extents not assumed)
+        // Same order as run_ttmc: the remaining modes are contracted last mode first.
         int64_t cur = zel, mx = 0;
-        for (int m : p.slab_modes) {
+        for (auto it = p.slab_modes.rbegin(); it != p.slab_modes.rend(); ++it) {
+            const int m = *it;
             if (m == n) continue;
             cur = cur / p.I[m] * p.Rm[m];
             mx = std::max(mx, cur);
@@ -587,6 +589,8 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
             t.odim[d] = cur[d].extent;
             t.total *= cur[d].extent;
         }
+        if (!last && static_cast<size_t>(t.total) * 8 > p.t_bytes)
+            return fail(DEINSUM_ERR_NO_MEMORY, "ttmc: intermediate larger than its workspace slot");
         void *dst = last ? Y : static_cast<void *>((k % 2 == 0) ? T0 : T1);
         if (last) {
             for (int d = 0; d < t.nd; ++d) t.ostr[d] = ystr[cur[d].mode];

@@ -1,7 +1,7 @@
 """Seeded synthetic inputs (host side) for MTTKRP / TTMc workloads.
 
 This module holds the input recipe and none of the method's arithmetic.  It
-serves both the HIP path (through ``fill_x_device`` in the binding, whose
+serves both the HIP path (through ``synth_fill`` in the binding, whose
 device generator implements the same counter-based stream) and the CPU
 oracle (through the numpy functions here).
 
@@ -70,9 +70,21 @@ def x_tensor(seed: int, dims, dist: str = "uniform") -> np.ndarray:
     return x_values(seed, np.arange(n, dtype=np.uint64), dist).reshape(dims)
 
 
+def x_range(seed: int, start: int, count: int, dist: str = "uniform", chunk: int = 1 << 22) -> np.ndarray:
+    """Entries at linear indices [start, start + count), generated in chunks."""
+    out = np.empty(count, dtype=np.float64)
+    for c0 in range(0, count, chunk):
+        c1 = min(count, c0 + chunk)
+        out[c0:c1] = x_values(seed, np.arange(start + c0, start + c1, dtype=np.uint64), dist)
+    return out
+
+
 def x_slab(seed: int, dims, mode: int, index: int, dist: str = "uniform") -> np.ndarray:
     """The sub-tensor with ``i_mode == index`` (shape: dims with dims[mode] = 1)."""
     dims = [int(d) for d in dims]
+    if mode == 0:
+        inner = int(np.prod(dims[1:]))
+        return x_range(seed, index * inner, inner, dist).reshape([1] + dims[1:])
     strides = np.ones(len(dims), dtype=np.uint64)
     for m in range(len(dims) - 2, -1, -1):
         strides[m] = strides[m + 1] * np.uint64(dims[m + 1])
