@@ -176,7 +176,7 @@ def main():
                 Xb = torch.empty(DIMS, dtype=torch.bfloat16, device=dev)
                 dn.convert(X, Xb)
             Xp = Xb if prec == "bf16" else X32
-            modes = [0, 1, 2] if prec == "fp32" else [0, 1]
+            modes = [0, 1, 2]
             o32 = {n: torch.empty((DIMS[n], R), dtype=torch.float32, device=dev) for n in modes}
             for _ in range(2):
                 for n in modes:

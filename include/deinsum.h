@@ -109,6 +109,7 @@ typedef struct deinsum_report {
     double alg_bytes;           /* X once + factors once + output once           */
     double alg_flops;           /* flops of the two-stage method                 */
     char plan_name[48];
+    double tuned_us;            /* deinsum_tune_*: median time of the chosen plan */
 } deinsum_report;
 
 typedef struct deinsum_opts {
@@ -116,7 +117,9 @@ typedef struct deinsum_opts {
     int32_t out_dtype;        /* DEINSUM_F64 or DEINSUM_F32 (F64 required for FP64)  */
     void *workspace;          /* optional caller device buffer; NULL = library pool  */
     size_t workspace_bytes;   /* its size                                            */
-    int32_t plan_hint;        /* 0 = planner choice; else a plan id (tuning, tests)  */
+    int32_t plan_hint;        /* 0 = autotuned plan if cached, else the heuristic;
+                                 1 / 2 = heuristic, and the free mode must be
+                                 < N-1 / = N-1 (tests)                               */
     int32_t split_hint;       /* 0 = planner choice; else outer-chunk count          */
     deinsum_report *report;   /* optional host out-parameter                         */
 } deinsum_opts;
@@ -195,6 +198,150 @@ deinsum_status deinsum_synth_fill(void *X, int32_t dtype, int64_t count, uint64_
 /* Elementwise conversion f64 -> f32 / bf16 or f32 -> bf16, round to nearest even. */
 deinsum_status deinsum_convert(const void *src, int32_t src_dtype, void *dst, int32_t dst_dtype,
                                int64_t count, void *stream);
+
+/*
+ * Batched launch (many MTTKRP jobs of uneven shape and rank, e.g. the
+ * per-mode products of CP-ALS sweeps over many tensors).  Jobs added to a
+ * batch run in ONE persistent kernel inside a hipGraph that is captured once
+ * and replayed at every launch: descriptor upload -> outer-weight tables ->
+ * persistent kernel (workgroups pull units of all jobs from one device work
+ * queue) -> fixed-order reduction of every job.  A job's result depends only
+ * on its own shape and plan, so it is bitwise identical whether it runs alone
+ * or with other jobs.  FP64 and FP32 forms, ranks 1..64.
+ *
+ * Ownership and threading: the batch object is owned by the caller and used
+ * from one thread.  Device buffers of added jobs (X, U, M) must stay valid
+ * until the launch that uses them has completed on its stream.  The library
+ * owns the batch's descriptors, work queue and workspace arena.
+ */
+typedef struct deinsum_batch deinsum_batch;
+
+/* Create a batch with room for max_jobs column blocks (grows on demand). */
+deinsum_status deinsum_batch_create(int32_t max_jobs, deinsum_batch **out);
+
+/* Add one MTTKRP job (arguments as deinsum_mttkrp; opts->precision FP64 or
+ * FP32, opts->split_hint honoured, opts->workspace ignored).  *job_id (optional)
+ * receives the job's index in this batch.  Host only; nothing is enqueued. */
+deinsum_status deinsum_batch_add_mttkrp(deinsum_batch *b, const deinsum_spec *spec, const int64_t *dims, int64_t R,
+                                        const void *X, const void *const *U, void *M, const deinsum_opts *opts,
+                                        int32_t *job_id);
+
+/* Enqueue every added job on `stream` as one graph replay.  Returns without
+ * synchronising; a later launch first waits for this one's descriptor upload. */
+deinsum_status deinsum_batch_launch(deinsum_batch *b, void *stream);
+
+/* Forget the added jobs (the next adds start a new batch). */
+deinsum_status deinsum_batch_reset(deinsum_batch *b);
+
+/* Counters: jobs added, work units, graph captures so far, launches so far (any may be NULL). */
+deinsum_status deinsum_batch_info(const deinsum_batch *b, int32_t *jobs, int64_t *units, int32_t *graph_captures,
+                                  int64_t *launches);
+
+/* Wait for the batch's last launch and free its resources. */
+deinsum_status deinsum_batch_destroy(deinsum_batch *b);
+
+/*
+ * Request serving for CP-ALS on resident tensors.  A request (tensor t, mode n)
+ * asks for one alternating-least-squares factor update of t: M = the mode-n
+ * MTTKRP of t with its current factors, then U^n <- M V^{-1} with V the
+ * Hadamard product of the other factors' Gram matrices, columns normalised.
+ * Requests of one tensor are served in arrival order (each sees the factors
+ * the previous one wrote); requests of different tensors are independent.
+ *
+ * With batched=1 a native scheduler thread runs continuous batching: whenever
+ * one of `epochs_in_flight` (1 or 2) epoch slots is free it admits every ready
+ * request (head of its tensor's queue, tensor idle) in arrival order while the
+ * epoch has slots and the sum of the admitted requests' MTTKRP workspaces stays
+ * within hbm_budget_bytes, and runs the epoch as one batch launch
+ * (deinsum_batch_*) plus one batched update kernel on the slot's stream.  With
+ * batched=0 every request is launched on arrival (deinsum_mttkrp + one update
+ * kernel) on a single stream: the per-request baseline.
+ *
+ * Latency of a request = host clock when its completion is observed minus its
+ * arrival time; both are seconds since deinsum_server_start.
+ *
+ * Ownership and threading: the caller owns X and the factors (device memory,
+ * FP64 or FP32 by `precision`, factors row-major dims[m] x R) and keeps them
+ * valid until deinsum_server_destroy; the server overwrites the factors.
+ * add_tensor before start; submit may be called from any thread after start;
+ * results after drain.  The server uses the device current at create.
+ */
+typedef struct deinsum_server deinsum_server;
+
+typedef struct deinsum_server_config {
+    int32_t batched;            /* 1: continuous batching; 0: one launch per request */
+    int32_t max_jobs_per_epoch; /* requests admitted into one epoch, 1..65536         */
+    int32_t epochs_in_flight;   /* 1 or 2 epochs on the device at once                */
+    int32_t als_update;         /* 1: run the factor update after each MTTKRP         */
+    int64_t max_requests;       /* capacity of the request table                     */
+    size_t hbm_budget_bytes;    /* admission limit on summed MTTKRP workspace         */
+} deinsum_server_config;
+
+/* Defaults: batched, 256 jobs per epoch, 2 in flight, update on, 1<<20 requests, 4 GiB. */
+void deinsum_server_config_init(deinsum_server_config *cfg);
+
+deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_server **out);
+
+/* Register a tensor (order 2..8, rank 1..64, precision DEINSUM_PREC_FP64 or
+ * DEINSUM_PREC_FP32).  U holds `order` factor pointers, by mode. */
+deinsum_status deinsum_server_add_tensor(deinsum_server *s, int32_t order, const int64_t *dims, int64_t R,
+                                         int32_t precision, const void *X, void *const *U, int32_t *tensor_id);
+
+/* Start the clock and the scheduler thread. */
+deinsum_status deinsum_server_start(deinsum_server *s);
+
+/* Submit one request; arrival_s < 0 means "now".  Thread-safe.  Returns
+ * DEINSUM_ERR_BUSY when the request table is full. */
+deinsum_status deinsum_server_submit(deinsum_server *s, int32_t tensor_id, int32_t mode, double arrival_s,
+                                     int64_t *request_id);
+
+/* Submit n requests, each at its scheduled arrival time (seconds since start,
+ * non-decreasing), sleeping in between: an open-loop load generator. */
+deinsum_status deinsum_server_replay(deinsum_server *s, int64_t n, const double *arrival_s, const int32_t *tensor_id,
+                                     const int32_t *mode);
+
+/* Block until every submitted request has completed (or the server failed). */
+deinsum_status deinsum_server_drain(deinsum_server *s);
+
+/* Per request i < n: arrival, completion (seconds since start, -1 if not done)
+ * and the epoch (batched) or launch index that served it.  Arrays may be NULL. */
+deinsum_status deinsum_server_results(const deinsum_server *s, int64_t n, double *arrival_s, double *done_s,
+                                      int64_t *epoch);
+
+/* Requests completed, epochs (or launches) issued, largest epoch. */
+deinsum_status deinsum_server_stats(const deinsum_server *s, int64_t *completed, int64_t *epochs, int64_t *max_batch);
+
+/* Stop the scheduler after the submitted requests finish, free everything. */
+deinsum_status deinsum_server_destroy(deinsum_server *s);
+
+/*
+ * Autotuner.  deinsum_tune_mttkrp runs the MTTKRP on the caller's buffers
+ * (M is overwritten) once with every compiled tile shape for the problem's
+ * precision and free mode (column width 16*nt, rows per wave, slice of the
+ * contiguous mode) and a few outer-chunk counts around the heuristic's, times
+ * `reps` runs of each on `stream` with HIP events, and stores the fastest in a
+ * process-wide plan cache.  deinsum_mttkrp and deinsum_workspace_size consult
+ * that cache first when plan_hint = split_hint = 0, so a tuned problem keeps
+ * its plan.  deinsum_tune_batch_mttkrp does the same for a job of the batched
+ * launch (its column width and split), which deinsum_batch_add_mttkrp then
+ * uses.  *best (optional) describes the winner, tuned_us its median time.
+ * The cache is keyed by path, order, free mode, precision, rank and dims; when
+ * the environment variable DEINSUM_TUNE_CACHE names a file it is read on first
+ * use and rewritten after every tuning call.  Host-synchronous.
+ */
+deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R, const void *X,
+                                   const void *const *U, void *M, const deinsum_opts *opts, int32_t reps,
+                                   deinsum_report *best, void *stream);
+deinsum_status deinsum_tune_batch_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R, const void *X,
+                                         const void *const *U, void *M, const deinsum_opts *opts, int32_t reps,
+                                         deinsum_report *best, void *stream);
+/* Read entries from / write the whole cache to a text file (one entry per line). */
+deinsum_status deinsum_tune_load(const char *path);
+deinsum_status deinsum_tune_save(const char *path);
+/* Forget every cached plan. */
+deinsum_status deinsum_tune_clear(void);
+/* Number of cached plans. */
+deinsum_status deinsum_tune_entries(int64_t *entries);
 
 /* Release the library's device workspace pools and plan caches. */
 deinsum_status deinsum_shutdown(void);

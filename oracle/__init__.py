@@ -10,7 +10,11 @@ The arithmetic lives in ``oracle.c`` (plain loops, FP64, no FMA contraction):
                    (Sec. III-B, "tensor operations");
   * ``ttm``     -- one mode product (Sec. III-B);
   * ``ttmc``    -- the TTM chain over all modes but one (Sec. III-B).
-This module only marshals numpy arrays to that library.
+This module only marshals numpy arrays to that library, except for
+  * ``als_update`` -- one CP-ALS factor update built on ``mttkrp`` (numpy).
+    The paper names MTTKRP as the main kernel of the CP decomposition (Sec. I)
+    but does not state the update; this is the textbook alternating
+    least-squares step (Kolda & Bader, SIAM Review 51(3), 2009, Sec. 3.4).
 """
 from __future__ import annotations
 
@@ -136,3 +140,27 @@ def ttmc(X, U, n):
     if rc:
         raise RuntimeError(f"oracle_ttmc failed with {rc}")
     return Y
+
+
+def als_update(X, U, n):
+    """One CP-ALS update of the mode-n factor.
+
+    The least-squares problem  min_A || X_(n) - A (KR of the other factors)^T ||
+    has the normal-equations solution  A = M V^{-1}  with M the mode-n MTTKRP
+    and V the Hadamard product of the Gram matrices U[m]^T U[m], m != n.  The
+    columns of A are then scaled to unit 2-norm (zero columns are left as
+    they are).  ``U`` holds one matrix per mode; ``U[n]`` is ignored.
+    Returns the new factor (FP64).
+    """
+    X = _f64(X)
+    M = mttkrp(X, U, n)
+    R = M.shape[1]
+    V = np.ones((R, R), dtype=np.float64)
+    for m in range(X.ndim):
+        if m != n:
+            Um = _f64(U[m])
+            V = V * (Um.T @ Um)
+    A = np.linalg.solve(V, M.T).T
+    norms = np.sqrt(np.sum(A * A, axis=0))
+    norms[norms == 0] = 1.0
+    return A / norms

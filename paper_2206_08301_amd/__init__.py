@@ -130,6 +130,48 @@ def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=Non
     return out
 
 
+def tune_mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, reps=5, batched=False, stream=None):
+    """Autotune the MTTKRP plan for this problem (runs it; ``out`` is overwritten) and
+    cache the fastest; later calls with the same shape use it.  Returns the winner's Report."""
+    sp = _spec(spec)
+    if sp.kind != MTTKRP:
+        raise ValueError("spec is not an MTTKRP")
+    _check_tensor(X, _X_DTYPE[precision], "X")
+    R = U[0].shape[1]
+    for k, u in enumerate(U):
+        _check_tensor(u, _U_DTYPE[precision], f"U[{k}]")
+    out_dtype = out_dtype or (out.dtype if out is not None else _default_out_dtype(precision))
+    if out is None:
+        out = torch.empty((X.shape[sp.free_mode], R), dtype=out_dtype, device=X.device)
+    ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+    o = _opts(precision, out_dtype, None, 0, 0, None)
+    rep = Report()
+    fn = _lib.load().deinsum_tune_batch_mttkrp if batched else _lib.load().deinsum_tune_mttkrp
+    with torch.cuda.device(X.device):
+        _lib.check(fn(ctypes.byref(sp), _i64(X.shape), R, ctypes.c_void_p(X.data_ptr()), ptrs,
+                      ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), int(reps), ctypes.byref(rep),
+                      _stream(stream)))
+    return rep
+
+
+def tune_load(path: str):
+    _lib.check(_lib.load().deinsum_tune_load(str(path).encode()))
+
+
+def tune_save(path: str):
+    _lib.check(_lib.load().deinsum_tune_save(str(path).encode()))
+
+
+def tune_clear():
+    _lib.check(_lib.load().deinsum_tune_clear())
+
+
+def tune_entries() -> int:
+    n = ctypes.c_int64(0)
+    _lib.check(_lib.load().deinsum_tune_entries(ctypes.byref(n)))
+    return n.value
+
+
 def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None):
     """Mode-n TTMc.  ``U`` lists the factor operands in the spec's operand order."""
     sp = _spec(spec)
@@ -198,3 +240,161 @@ def shutdown():
 
 def last_error() -> str:
     return _lib.load().deinsum_last_error().decode()
+
+
+class Batch:
+    """Many MTTKRP jobs in one persistent, graph-replayed launch (deinsum_batch_*)."""
+
+    def __init__(self, max_jobs: int = 64):
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().deinsum_batch_create(int(max_jobs), ctypes.byref(self._h)))
+        self._keep = []
+
+    def add(self, spec, X, U, out=None, precision="fp64", out_dtype=None, split_hint=0):
+        """Queue M = MTTKRP(spec, X, U); returns (job_id, M).  Nothing runs until launch()."""
+        sp = _spec(spec)
+        if sp.kind != MTTKRP:
+            raise ValueError("spec is not an MTTKRP")
+        _check_tensor(X, _X_DTYPE[precision], "X")
+        R = U[0].shape[1]
+        for k, u in enumerate(U):
+            _check_tensor(u, _U_DTYPE[precision], f"U[{k}]")
+        out_dtype = out_dtype or (out.dtype if out is not None else _default_out_dtype(precision))
+        n = sp.free_mode
+        if out is None:
+            out = torch.empty((X.shape[n], R), dtype=out_dtype, device=X.device)
+        else:
+            _check_tensor(out, out_dtype, "out")
+        ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+        o = _opts(precision, out_dtype, None, 0, split_hint, None)
+        jid = ctypes.c_int32(-1)
+        _lib.check(_lib.load().deinsum_batch_add_mttkrp(self._h, ctypes.byref(sp), _i64(X.shape), R,
+                                                        ctypes.c_void_p(X.data_ptr()), ptrs,
+                                                        ctypes.c_void_p(out.data_ptr()), ctypes.byref(o),
+                                                        ctypes.byref(jid)))
+        self._keep.append((X, tuple(U), out))
+        return jid.value, out
+
+    def launch(self, stream=None):
+        _lib.check(_lib.load().deinsum_batch_launch(self._h, _stream(stream)))
+
+    def reset(self):
+        _lib.check(_lib.load().deinsum_batch_reset(self._h))
+        self._keep = []
+
+    def info(self) -> dict:
+        j, u, c, l_ = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _lib.check(_lib.load().deinsum_batch_info(self._h, ctypes.byref(j), ctypes.byref(u), ctypes.byref(c),
+                                                  ctypes.byref(l_)))
+        return {"jobs": j.value, "units": u.value, "graph_captures": c.value, "launches": l_.value}
+
+    def close(self):
+        if self._h:
+            _lib.load().deinsum_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """CP-ALS request server on resident tensors (deinsum_server_*).
+
+    Each request (tensor, mode) runs the mode's MTTKRP and the factor update
+    in the library; the factors registered with ``add_tensor`` are updated in
+    place.  ``batched=True`` runs continuous batching, ``False`` one launch
+    per request.
+    """
+
+    def __init__(self, batched=True, max_jobs_per_epoch=256, epochs_in_flight=2, als_update=True,
+                 max_requests=1 << 20, hbm_budget_bytes=4 << 30):
+        cfg = _lib.ServerConfig()
+        _lib.load().deinsum_server_config_init(ctypes.byref(cfg))
+        cfg.batched = int(bool(batched))
+        cfg.max_jobs_per_epoch = int(max_jobs_per_epoch)
+        cfg.epochs_in_flight = int(epochs_in_flight)
+        cfg.als_update = int(bool(als_update))
+        cfg.max_requests = int(max_requests)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        self._h = ctypes.c_void_p()
+        _lib.check(_lib.load().deinsum_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._keep = []
+        self._n = 0
+
+    def add_tensor(self, X, U, precision="fp64") -> int:
+        """Register X (order N) and its N factors (one per mode, dims[m] x R)."""
+        if precision not in ("fp64", "fp32"):
+            raise ValueError("the server takes fp64 or fp32 tensors")
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        _check_tensor(X, dt, "X")
+        if len(U) != X.dim():
+            raise ValueError("one factor per mode is required")
+        R = U[0].shape[1]
+        for m, u in enumerate(U):
+            _check_tensor(u, dt, f"U[{m}]")
+            if u.dim() != 2 or u.shape[0] != X.shape[m] or u.shape[1] != R:
+                raise ValueError(f"factor {m} must be {X.shape[m]} x {R}")
+        ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+        tid = ctypes.c_int32(-1)
+        _lib.check(_lib.load().deinsum_server_add_tensor(self._h, X.dim(), _i64(X.shape), R, PRECISIONS[precision],
+                                                         ctypes.c_void_p(X.data_ptr()), ptrs, ctypes.byref(tid)))
+        self._keep.append((X, tuple(U)))
+        return tid.value
+
+    def start(self):
+        _lib.check(_lib.load().deinsum_server_start(self._h))
+
+    def submit(self, tensor: int, mode: int, arrival: float = -1.0) -> int:
+        rid = ctypes.c_int64(-1)
+        _lib.check(_lib.load().deinsum_server_submit(self._h, int(tensor), int(mode), float(arrival),
+                                                     ctypes.byref(rid)))
+        self._n = max(self._n, rid.value + 1)
+        return rid.value
+
+    def replay(self, arrivals, tensors, modes):
+        """Open-loop submission at the given arrival times (seconds since start)."""
+        import numpy as np
+        a = np.ascontiguousarray(arrivals, dtype=np.float64)
+        t = np.ascontiguousarray(tensors, dtype=np.int32)
+        m = np.ascontiguousarray(modes, dtype=np.int32)
+        if not (len(a) == len(t) == len(m)):
+            raise ValueError("arrivals, tensors and modes must have one length")
+        _lib.check(_lib.load().deinsum_server_replay(
+            self._h, len(a), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        self._n += len(a)
+
+    def drain(self):
+        _lib.check(_lib.load().deinsum_server_drain(self._h))
+
+    def results(self):
+        """(arrival, done, epoch) numpy arrays over all submitted requests (after drain)."""
+        import numpy as np
+        n = self.stats()["completed"] if self._n == 0 else self._n
+        arr, done = np.zeros(n), np.zeros(n)
+        ep = np.zeros(n, dtype=np.int64)
+        _lib.check(_lib.load().deinsum_server_results(
+            self._h, n, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            done.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ep.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        return arr, done, ep
+
+    def stats(self) -> dict:
+        c, e, mb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _lib.check(_lib.load().deinsum_server_stats(self._h, ctypes.byref(c), ctypes.byref(e), ctypes.byref(mb)))
+        return {"completed": c.value, "epochs": e.value, "max_batch": mb.value}
+
+    def close(self):
+        if self._h:
+            _lib.load().deinsum_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

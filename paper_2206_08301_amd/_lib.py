@@ -53,6 +53,18 @@ class Report(ctypes.Structure):
         ("alg_bytes", ctypes.c_double),
         ("alg_flops", ctypes.c_double),
         ("plan_name", ctypes.c_char * 48),
+        ("tuned_us", ctypes.c_double),
+    ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("batched", ctypes.c_int32),
+        ("max_jobs_per_epoch", ctypes.c_int32),
+        ("epochs_in_flight", ctypes.c_int32),
+        ("als_update", ctypes.c_int32),
+        ("max_requests", ctypes.c_int64),
+        ("hbm_budget_bytes", ctypes.c_size_t),
     ]
 
 
@@ -72,7 +84,12 @@ class Opts(ctypes.Structure):
 EXPORTS = (
     "deinsum_opts_init", "deinsum_parse", "deinsum_workspace_size", "deinsum_mttkrp",
     "deinsum_ttmc", "deinsum_last_error", "deinsum_synth_fill", "deinsum_convert",
-    "deinsum_shutdown", "deinsum_version",
+    "deinsum_shutdown", "deinsum_version", "deinsum_batch_create", "deinsum_batch_add_mttkrp",
+    "deinsum_batch_launch", "deinsum_batch_reset", "deinsum_batch_info", "deinsum_batch_destroy",
+    "deinsum_server_config_init", "deinsum_server_create", "deinsum_server_add_tensor", "deinsum_server_start",
+    "deinsum_server_submit", "deinsum_server_replay", "deinsum_server_drain", "deinsum_server_results",
+    "deinsum_server_stats", "deinsum_server_destroy", "deinsum_tune_mttkrp", "deinsum_tune_batch_mttkrp",
+    "deinsum_tune_load", "deinsum_tune_save", "deinsum_tune_clear", "deinsum_tune_entries",
 )
 
 _lib = None
@@ -113,6 +130,56 @@ def load():
     lib.deinsum_shutdown.restype = ctypes.c_int
     lib.deinsum_version.argtypes = []
     lib.deinsum_version.restype = ctypes.c_char_p
+    lib.deinsum_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(vp)]
+    lib.deinsum_batch_create.restype = ctypes.c_int
+    lib.deinsum_batch_add_mttkrp.argtypes = [vp, ctypes.POINTER(Spec), i64p, ctypes.c_int64, vp,
+                                             ctypes.POINTER(vp), vp, ctypes.POINTER(Opts),
+                                             ctypes.POINTER(ctypes.c_int32)]
+    lib.deinsum_batch_add_mttkrp.restype = ctypes.c_int
+    lib.deinsum_batch_launch.argtypes = [vp, vp]
+    lib.deinsum_batch_launch.restype = ctypes.c_int
+    lib.deinsum_batch_reset.argtypes = [vp]
+    lib.deinsum_batch_reset.restype = ctypes.c_int
+    lib.deinsum_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    lib.deinsum_batch_info.restype = ctypes.c_int
+    lib.deinsum_batch_destroy.argtypes = [vp]
+    lib.deinsum_batch_destroy.restype = ctypes.c_int
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    lib.deinsum_server_config_init.argtypes = [ctypes.POINTER(ServerConfig)]
+    lib.deinsum_server_config_init.restype = None
+    lib.deinsum_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.deinsum_server_create.restype = ctypes.c_int
+    lib.deinsum_server_add_tensor.argtypes = [vp, ctypes.c_int32, i64p, ctypes.c_int64, ctypes.c_int32, vp,
+                                              ctypes.POINTER(vp), i32p]
+    lib.deinsum_server_add_tensor.restype = ctypes.c_int
+    lib.deinsum_server_start.argtypes = [vp]
+    lib.deinsum_server_start.restype = ctypes.c_int
+    lib.deinsum_server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, i64p]
+    lib.deinsum_server_submit.restype = ctypes.c_int
+    lib.deinsum_server_replay.argtypes = [vp, ctypes.c_int64, f64p, i32p, i32p]
+    lib.deinsum_server_replay.restype = ctypes.c_int
+    lib.deinsum_server_drain.argtypes = [vp]
+    lib.deinsum_server_drain.restype = ctypes.c_int
+    lib.deinsum_server_results.argtypes = [vp, ctypes.c_int64, f64p, f64p, i64p]
+    lib.deinsum_server_results.restype = ctypes.c_int
+    lib.deinsum_server_stats.argtypes = [vp, i64p, i64p, i64p]
+    lib.deinsum_server_stats.restype = ctypes.c_int
+    lib.deinsum_server_destroy.argtypes = [vp]
+    lib.deinsum_server_destroy.restype = ctypes.c_int
+    for name in ("deinsum_tune_mttkrp", "deinsum_tune_batch_mttkrp"):
+        f = getattr(lib, name)
+        f.argtypes = [ctypes.POINTER(Spec), i64p, ctypes.c_int64, vp, ctypes.POINTER(vp), vp, ctypes.POINTER(Opts),
+                      ctypes.c_int32, ctypes.POINTER(Report), vp]
+        f.restype = ctypes.c_int
+    for name in ("deinsum_tune_load", "deinsum_tune_save"):
+        getattr(lib, name).argtypes = [ctypes.c_char_p]
+        getattr(lib, name).restype = ctypes.c_int
+    lib.deinsum_tune_clear.argtypes = []
+    lib.deinsum_tune_clear.restype = ctypes.c_int
+    lib.deinsum_tune_entries.argtypes = [i64p]
+    lib.deinsum_tune_entries.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -7,12 +7,14 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 #include "kernels.h"
 #include "mttkrp.h"
 #include "plan.h"
 #include "ttmc.h"
+#include "tune.h"
 
 namespace deinsum {
 
@@ -240,6 +242,32 @@ void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p
     std::snprintf(r->plan_name, sizeof(r->plan_name), "%s", p.name.c_str());
 }
 
+// Median of the event-timed durations of `reps` back-to-back runs (one warm-up first).
+template <class F>
+deinsum_status time_median(F &&run, int reps, hipStream_t s, double *us)
+{
+    hipEvent_t ev[2];
+    if (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)
+        return fail(DEINSUM_ERR_DEVICE, "tune: event creation failed");
+    std::vector<float> t;
+    deinsum_status st = run();
+    for (int r = 0; r < reps && st == DEINSUM_OK; ++r) {
+        (void)hipEventRecord(ev[0], s);
+        st = run();
+        (void)hipEventRecord(ev[1], s);
+        if (hipEventSynchronize(ev[1]) != hipSuccess) st = fail(DEINSUM_ERR_DEVICE, "tune: event sync failed");
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (st) return st;
+    std::sort(t.begin(), t.end());
+    *us = 1e3 * t[t.size() / 2];
+    return DEINSUM_OK;
+}
+
 }  // namespace
 }  // namespace deinsum
 
@@ -325,6 +353,69 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     }
     fill_report(o.report, c.pb, c.plan, c.plan.workspace);
     if (deinsum_status st = run_mttkrp(c, ws, s)) return st;
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R, const void *X,
+                                   const void *const *U, void *M, const deinsum_opts *opts, int32_t reps,
+                                   deinsum_report *best, void *stream)
+{
+    if (reps < 1 || reps > 1000) return fail(DEINSUM_ERR_INVALID_ARG, "tune: reps must be 1..1000");
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    o.plan_hint = 0;
+    o.split_hint = 0;
+    o.workspace = nullptr;
+    o.workspace_bytes = 0;
+    o.report = nullptr;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // Validates every argument exactly as a plain call does.
+    if (deinsum_status st = deinsum_mttkrp(spec, dims, R, X, U, M, &o, stream)) return st;
+    MttkrpCall c{};
+    for (int m = 0; m < spec->order; ++m)
+        if (dims[m] == 0) return DEINSUM_OK;  // nothing to tune
+    if (deinsum_status st = prepare_mttkrp(spec, dims, R, o, &c)) return st;
+    for (int k = 0; k < spec->order - 1; ++k) c.U[spec->factor_mode[k]] = U[k];
+    c.X = X;
+    c.M = M;
+    const int layout = c.plan.family == PLAN_MTTKRP_KCONTIG ? L_KCONTIG : L_MCONTIG;
+    int count = 0;
+    const StreamKernelInfo *table = stream_kernels(&count);
+    double best_us = -1;
+    MttkrpPlan best_plan;
+    TuneChoice choice;
+    for (int i = 0; i < count; ++i) {
+        const StreamKernelInfo &k = table[i];
+        if (k.prec != c.pb.prec || k.layout != layout) continue;
+        MttkrpPlan p0;
+        if (plan_geometry(c.pb, &k, 0, &p0) != DEINSUM_OK) continue;
+        int splits[8];
+        const int ns = tune_splits(p0.n_chunks, p0.O, splits);
+        for (int si = 0; si < ns; ++si) {
+            MttkrpCall cc = c;
+            if (deinsum_status st = plan_geometry(c.pb, &k, splits[si], &cc.plan)) return st;
+            void *ws = nullptr;
+            if (deinsum_status st = pool_get(cc.plan.workspace, &ws)) return st;
+            double us = 0;
+            if (deinsum_status st = time_median([&] { return run_mttkrp(cc, ws, s); }, reps, s, &us)) return st;
+            if (best_us < 0 || us < best_us) {
+                best_us = us;
+                best_plan = cc.plan;
+                choice.nt = k.nt;
+                choice.ni = k.ni;
+                choice.mt = k.mt;
+                choice.split = splits[si];
+                choice.us = us;
+            }
+        }
+    }
+    if (best_us < 0) return fail(DEINSUM_ERR_UNSUPPORTED, "tune: no candidate plan");
+    tune_store(tune_key(TUNE_STREAM, c.pb), choice);
+    if (best) {
+        fill_report(best, c.pb, best_plan, best_plan.workspace);
+        best->tuned_us = best_us;
+    }
     clear_error();
     return DEINSUM_OK;
 }

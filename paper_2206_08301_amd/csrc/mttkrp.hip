@@ -25,388 +25,19 @@
 
 #include "kernels.h"
 #include "mttkrp.h"
+#include "stream.h"
 
 namespace deinsum {
 
 namespace {
 
-template <int P> struct PrecTypes;
-template <> struct PrecTypes<P_FP64> { using XT = double; using DT = f64x4; static constexpr int KE = 1; };
-template <> struct PrecTypes<P_FP32> { using XT = float;  using DT = f32x4; static constexpr int KE = 1; };
-template <> struct PrecTypes<P_BF16> { using XT = bf16_t; using DT = f32x4; static constexpr int KE = 8; };
-template <> struct PrecTypes<P_BF16X3> { using XT = float; using DT = f32x4; static constexpr int KE = 8; };
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ int64_t imax64(int64_t a, int64_t b) { return a > b ? a : b; }
-
-__device__ __forceinline__ double ld_u(const void *p, int64_t i, int prec)
-{
-    return prec == P_FP64 ? static_cast<const double *>(p)[i]
-                          : static_cast<double>(static_cast<const float *>(p)[i]);
-}
-
-// Load `n` contiguous elements; `vec` = whole 16-byte (or 8-byte) words allowed.
-template <typename T, int n>
-__device__ __forceinline__ void load_contig(T *dst, const T *__restrict__ src, bool vec, int64_t valid)
-{
-    if constexpr ((n * sizeof(T)) % 16 == 0) {
-        if (vec && valid >= n) {
-            constexpr int NV = n * sizeof(T) / 16;
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                const u32x4 v = reinterpret_cast<const u32x4 *>(src)[i];
-                __builtin_memcpy(dst + i * (16 / sizeof(T)), &v, 16);
-            }
-            return;
-        }
-    } else if constexpr (n * sizeof(T) == 8) {
-        if (vec && valid >= n) {
-            const uint64_t v = *reinterpret_cast<const uint64_t *>(src);
-            __builtin_memcpy(dst, &v, 8);
-            return;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < n; ++i) dst[i] = (i < valid) ? src[i] : T{};
-}
-
-// Outer-index odometer over the X offset only (no loads): the per-mode loop is
-// unrolled over the maximum number of outer modes so the indices stay in
-// registers and the walk adds no memory waits to the streaming loop.
-struct Odometer {
-    int64_t idx[kMaxOuter];
-    int64_t off;
-    __device__ __forceinline__ void init(const OuterDesc &od, int64_t o)
-    {
-        off = 0;
-#pragma unroll
-        for (int m = kMaxOuter - 1; m >= 0; --m) {
-            idx[m] = 0;
-            if (m < od.n_outer) {
-                idx[m] = o % od.dim[m];
-                o /= od.dim[m];
-                off += idx[m] * od.xstride[m];
-            }
-        }
-    }
-    __device__ __forceinline__ void next(const OuterDesc &od)
-    {
-        bool carry = true;
-#pragma unroll
-        for (int m = kMaxOuter - 1; m >= 0; --m) {
-            if (m < od.n_outer && carry) {
-                off += od.xstride[m];
-                if (++idx[m] < od.dim[m]) {
-                    carry = false;
-                } else {
-                    off -= idx[m] * od.xstride[m];
-                    idx[m] = 0;
-                }
-            }
-        }
-    }
-};
-
-// Geometry of one wave's tile.
-//   NI : matrix-core K-instructions per column tile per step; KE k-values each.
-//   SLICE = 4 * NI * KE positions of mode g per wave.
-//   K-contiguous: the lane's run of NI*KE elements is cut into chunks of VE
-//     contiguous elements; chunk j of lane group g starts at slice position
-//     j*4*VE + g*VE, so the four lanes of a row read 4*VE contiguous elements
-//     per load instruction.  Run element t sits at
-//         pos(t, g) = (t / VE) * 4 * VE + g * VE + t % VE.
-//   M-contiguous: instruction q, lane group g, element e reads row
-//         pos(q, g, e) = q * 4 * KE + g * KE + e
-//     of the slice, MT contiguous output indices per lane.
-template <int P, int L, int NI, int MT>
-struct Tile {
-    using XT = typename PrecTypes<P>::XT;
-    static constexpr int KE = PrecTypes<P>::KE;
-    static constexpr int SLICE = 4 * NI * KE;
-    static constexpr int VE = (P == P_BF16X3) ? 8 : static_cast<int>(16 / sizeof(XT));
-    static constexpr int XN = (L == L_KCONTIG) ? NI * KE : NI * KE * MT;  // X elements per lane per step
-    static_assert(L == L_MCONTIG || (NI * KE) % VE == 0, "K-contiguous runs must be whole chunks");
-
-    __device__ static int pos_k(int t, int g) { return (t / VE) * 4 * VE + g * VE + t % VE; }
-    __device__ static int pos_m(int q, int g, int e) { return q * 4 * KE + g * KE + e; }
-    // slice position of the K slot (g, e) of instruction q
-    __device__ static int slot_pos(int q, int g, int e)
-    {
-        return (L == L_KCONTIG) ? pos_k(q * KE + e, g) : pos_m(q, g, e);
-    }
-};
-
-template <typename T, int n>
-__device__ __forceinline__ void load_vec(T *dst, const T *__restrict__ src)
-{
-    static_assert((n * sizeof(T)) % 8 == 0, "vector runs are whole 8-byte words");
-    if constexpr ((n * sizeof(T)) % 16 == 0) {
-#pragma unroll
-        for (int i = 0; i < static_cast<int>(n * sizeof(T) / 16); ++i) {
-            const u32x4 v = reinterpret_cast<const u32x4 *>(src)[i];
-            __builtin_memcpy(dst + i * (16 / sizeof(T)), &v, 16);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < static_cast<int>(n * sizeof(T) / 8); ++i) {
-            const uint64_t v = reinterpret_cast<const uint64_t *>(src)[i];
-            __builtin_memcpy(dst + i * (8 / sizeof(T)), &v, 8);
-        }
-    }
-}
-
-// One step's X tile of a lane.  FULL: every element in range and aligned, so
-// the tile is a fixed sequence of vector loads (a static load count lets the
-// compiler wait for exactly the oldest tile); otherwise masked element loads.
-template <int P, int L, int NI, int MT, bool FULL>
-__device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
-                                          const typename Tile<P, L, NI, MT>::XT *__restrict__ base,
-                                          const StreamArgs &a, int g, int64_t lim, int ivalid)
-{
-    using TL = Tile<P, L, NI, MT>;
-    using XT = typename TL::XT;
-    if constexpr (L == L_KCONTIG) {
-        // base = row start + slice start + g*VE; lim = slice elements available from there
-        constexpr int NCH = (NI * TL::KE) / TL::VE;
-#pragma unroll
-        for (int j = 0; j < NCH; ++j) {
-            if constexpr (FULL) load_vec<XT, TL::VE>(x + j * TL::VE, base + j * 4 * TL::VE);
-            else load_contig<XT, TL::VE>(x + j * TL::VE, base + j * 4 * TL::VE, false, lim - j * 4 * TL::VE);
-        }
-    } else {
-        // base = slice row 0 + first output index of the lane; lim = slice rows available
-#pragma unroll
-        for (int q = 0; q < NI; ++q)
-#pragma unroll
-            for (int e = 0; e < TL::KE; ++e) {
-                const int r = TL::pos_m(q, g, e);
-                const XT *src = base + static_cast<int64_t>(r) * a.stride_g;
-                XT *dst = x + (q * TL::KE + e) * MT;
-                if constexpr (FULL && (MT * sizeof(XT)) % 8 == 0) {
-                    load_vec<XT, MT>(dst, src);
-                } else if constexpr (FULL) {
-#pragma unroll
-                    for (int i = 0; i < MT; ++i) dst[i] = src[i];
-                } else {
-                    load_contig<XT, MT>(dst, src, false, r < lim ? ivalid : 0);
-                }
-            }
-    }
-}
+using namespace dev;
 
 template <int P, int L, int NT, int NI, int MT, int NBUF>
 __global__ void __launch_bounds__(256, 2) mttkrp_stream_kernel(const StreamArgs a)
 {
-    using TL = Tile<P, L, NI, MT>;
-    using XT = typename TL::XT;
-    using DT = typename PrecTypes<P>::DT;
-    constexpr int KE = TL::KE;
-    constexpr int XN = TL::XN;
-    constexpr int TROWS = (L == L_KCONTIG) ? 16 : 16 * MT;
-    constexpr int TCOLS = 16 * NT;
-    __shared__ double lds[TROWS * TCOLS];
-
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index: uniform in the wave
-    const int nwaves = blockDim.x >> 6;
-    const int g = lane >> 4, c = lane & 15;
-    const int64_t b = blockIdx.x;
-    const int kgroup = static_cast<int>(b % a.n_kgroups);
-    const int tile = static_cast<int>((b / a.n_kgroups) % a.n_tiles);
-    const int64_t chunk = b / (static_cast<int64_t>(a.n_kgroups) * a.n_tiles);
-    const int ks = kgroup * a.wk + (w % a.wk);
-    const int osub = w / a.wk;
-    const int64_t s0 = static_cast<int64_t>(ks) * TL::SLICE;  // slice start in mode g
-    const int64_t slice_avail = a.Ig - s0;                     // <= 0: empty slice
-
-    // Lane geometry.  `full` (wave-uniform): the wave's whole tile is in range
-    // and X allows aligned vector loads.
-    int64_t xlane;  // offset of this lane's first element (excluding the outer offset)
-    int64_t lim;    // K-contig: run elements available; M-contig: slice rows available
-    int ivalid = 0;
-    bool full;
-    if constexpr (L == L_KCONTIG) {
-        const int64_t row = static_cast<int64_t>(tile) * 16 + c;
-        xlane = row * a.stride_n + s0 + g * TL::VE;
-        lim = (row < a.In) ? slice_avail - g * TL::VE : 0;
-        full = a.vec_ok && (static_cast<int64_t>(tile) + 1) * 16 <= a.In && slice_avail >= TL::SLICE;
-    } else {
-        const int64_t ibase = static_cast<int64_t>(tile) * 16 * MT + MT * c;
-        ivalid = static_cast<int>(imin64(MT, imax64(0, a.In - ibase)));
-        xlane = s0 * a.stride_g + ibase;
-        lim = slice_avail;
-        full = a.vec_ok && (static_cast<int64_t>(tile) + 1) * 16 * MT <= a.In && slice_avail >= TL::SLICE;
-    }
-
-    // Register-resident slice of U^g for every K slot of every instruction.
-    double fr64[(P == P_FP64) ? NI * NT : 1];
-    float fr32[(P == P_FP32) ? NI * NT : 1];
-    u16x8 frh[(P >= P_BF16) ? NI * NT : 1];
-    u16x8 frl[(P == P_BF16X3) ? NI * NT : 1];
-#pragma unroll
-    for (int q = 0; q < NI; ++q)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int col = nt * 16 + c;
-            if constexpr (KE == 1) {
-                const int pos = TL::slot_pos(q, g, 0);
-                const double v = (pos < slice_avail && col < a.ncols) ? ld_u(a.Ug, (s0 + pos) * a.ldu + col, P) : 0.0;
-                if constexpr (P == P_FP64) fr64[q * NT + nt] = v;
-                else fr32[q * NT + nt] = static_cast<float>(v);
-            } else {
-                u16x8 hi, lo;
-#pragma unroll
-                for (int e = 0; e < KE; ++e) {
-                    const int pos = TL::slot_pos(q, g, e);
-                    const float v = (pos < slice_avail && col < a.ncols)
-                                        ? static_cast<const float *>(a.Ug)[(s0 + pos) * a.ldu + col] : 0.0f;
-                    const uint16_t h = f32_to_bf16_bits(v);
-                    hi[e] = h;
-                    lo[e] = f32_to_bf16_bits(v - bf16_bits_to_f32(h));
-                }
-                frh[q * NT + nt] = hi;
-                if constexpr (P == P_BF16X3) frl[q * NT + nt] = lo;
-            }
-        }
-
-    double acc[MT][NT][4];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[mt][nt][v] = 0.0;
-
-    // One step: stage 1 on the matrix cores, then the Hadamard fold (stage 2).
-    auto step = [&](const XT *x, const double *wv) {
-        DT d[MT][NT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) d[mt][nt] = DT{0, 0, 0, 0};
-#pragma unroll
-        for (int q = 0; q < NI; ++q)
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                // A operand of instruction q for M tile mt: element e of the K slot.
-                auto xe = [&](int e) -> XT {
-                    return (L == L_KCONTIG) ? x[q * KE + e] : x[(q * KE + e) * MT + mt];
-                };
-                if constexpr (P == P_FP64 || P == P_FP32) {
-                    const XT xa = xe(0);
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        if constexpr (P == P_FP64) d[mt][nt] = mfma_f64(xa, fr64[q * NT + nt], d[mt][nt]);
-                        else d[mt][nt] = mfma_f32(xa, fr32[q * NT + nt], d[mt][nt]);
-                    }
-                } else if constexpr (P == P_BF16) {
-                    u16x8 xa;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) xa[e] = xe(e).u;
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) d[mt][nt] = mfma_bf16(xa, frh[q * NT + nt], d[mt][nt]);
-                } else {
-                    u16x8 xh, xl;
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const float xv = xe(e);
-                        const uint16_t h = f32_to_bf16_bits(xv);
-                        xh[e] = h;
-                        xl[e] = f32_to_bf16_bits(xv - bf16_bits_to_f32(h));
-                    }
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        d[mt][nt] = mfma_bf16(xh, frh[q * NT + nt], d[mt][nt]);
-                        d[mt][nt] = mfma_bf16(xh, frl[q * NT + nt], d[mt][nt]);
-                        d[mt][nt] = mfma_bf16(xl, frh[q * NT + nt], d[mt][nt]);
-                    }
-                }
-            }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[mt][nt][v] += static_cast<double>(d[mt][nt][v]) * wv[nt];
-    };
-
-    // Outer range of this wave.
-    const int64_t c0 = chunk * a.o_per_chunk;
-    const int64_t c1 = imin64(a.O, c0 + a.o_per_chunk);
-    const int wo = nwaves / a.wk;
-    const int64_t per = (c1 - c0 + wo - 1) / wo;
-    const int64_t o0 = imin64(c1, c0 + osub * per);
-    const int64_t o1 = imin64(c1, o0 + per);
-    const XT *__restrict__ X = static_cast<const XT *>(a.X);
-
-    // Walk of the outer range with an NBUF-deep register ring: the tile and the
-    // Hadamard weights of step t+NBUF-1 are loaded while step t computes.
-    auto walk = [&](auto full_tag) {
-        constexpr bool FULL = decltype(full_tag)::value;
-        XT xb[NBUF][XN];
-        double wb[NBUF][NT];
-        Odometer od;
-        od.init(a.od, o0);
-        int64_t lo = o0;  // outer index of the next load
-        auto issue = [&](int slot) {
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) wb[slot][nt] = a.W[lo * a.ldw + nt * 16 + c];
-            load_tile<P, L, NI, MT, FULL>(xb[slot], X + od.off + xlane, a, g, lim, ivalid);
-            od.next(a.od);
-            ++lo;
-        };
-        const int64_t nsteps = o1 - o0;
-#pragma unroll
-        for (int u = 0; u < NBUF - 1; ++u)
-            if (u < nsteps) issue(u);
-        // Steady state: every load of the iteration is in range, so the loop
-        // body issues a fixed sequence of loads and the compiler can wait for
-        // exactly the oldest slot.
-        int64_t t = 0;
-        for (; t + 2 * NBUF - 2 < nsteps; t += NBUF) {
-#pragma unroll
-            for (int u = 0; u < NBUF; ++u) {
-                issue((u + NBUF - 1) % NBUF);
-                step(xb[u], wb[u]);
-            }
-        }
-        // Tail: the last < 2*NBUF-1 steps with guarded prefetch.
-        for (; t < nsteps; t += NBUF) {
-#pragma unroll
-            for (int u = 0; u < NBUF; ++u) {
-                if (t + u < nsteps) {
-                    if (t + u + NBUF - 1 < nsteps) issue((u + NBUF - 1) % NBUF);
-                    step(xb[u], wb[u]);
-                }
-            }
-        }
-    };
-    if (o0 < o1 && slice_avail > 0) {
-        if (full) walk(std::true_type{});
-        else walk(std::false_type{});
-    }
-
-    // Workgroup reduction in wave order through LDS, then one partial tile.
-    for (int ww = 0; ww < nwaves; ++ww) {
-        if (w == ww) {
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int r = (L == L_KCONTIG) ? tile_row<P>(lane, v) : MT * tile_row<P>(lane, v) + mt;
-                        const int i = r * TCOLS + nt * 16 + c;
-                        lds[i] = (ww == 0) ? acc[mt][nt][v] : lds[i] + acc[mt][nt][v];
-                    }
-        }
-        __syncthreads();
-    }
-    const int64_t part = chunk * a.n_kgroups + kgroup;
-    double *out = a.P + (part * a.n_tiles + tile) * (TROWS * TCOLS);
-    for (int i = threadIdx.x; i < TROWS * TCOLS; i += blockDim.x) out[i] = lds[i];
+    __shared__ double lds[unit_lds_elems<L, NT, MT>()];
+    stream_unit<P, L, NT, NI, MT, NBUF>(a, blockIdx.x, lds);
 }
 
 // Hadamard weights of the outer modes: W[o, col] = prod_outer U^m[i_m, col]
@@ -465,7 +96,7 @@ void launch_stream(const StreamArgs &a, int64_t grid, int waves, hipStream_t s)
 static const StreamKernelInfo kStreamTable[] = {
     // K-contiguous: per-lane run NI*KE elements (128 bytes by default; 80-element slices for dims of 80)
     SK(P_FP64, L_KCONTIG, 1, 16, 1, 3), SK(P_FP64, L_KCONTIG, 2, 16, 1, 3), SK(P_FP64, L_KCONTIG, 4, 8, 1, 2),
-    SK(P_FP64, L_KCONTIG, 1, 20, 1, 3), SK(P_FP64, L_KCONTIG, 2, 20, 1, 2), SK(P_FP64, L_KCONTIG, 4, 20, 1, 2),
+    SK(P_FP64, L_KCONTIG, 1, 20, 1, 3), SK(P_FP64, L_KCONTIG, 2, 20, 1, 2), SK(P_FP64, L_KCONTIG, 4, 10, 1, 2),
     SK(P_FP64, L_KCONTIG, 1, 8, 1, 3),  SK(P_FP64, L_KCONTIG, 2, 8, 1, 3),
     SK(P_FP32, L_KCONTIG, 1, 32, 1, 3), SK(P_FP32, L_KCONTIG, 2, 32, 1, 3), SK(P_FP32, L_KCONTIG, 4, 16, 1, 2),
     SK(P_FP32, L_KCONTIG, 1, 20, 1, 3), SK(P_FP32, L_KCONTIG, 2, 20, 1, 3), SK(P_FP32, L_KCONTIG, 4, 20, 1, 2),
@@ -477,10 +108,10 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16X3, L_KCONTIG, 1, 3, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 3, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 3, 1, 2),
     SK(P_BF16X3, L_KCONTIG, 1, 1, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 1, 1, 3),
     // M-contiguous: NI K-steps of 4*KE rows; MT output indices per lane
-    SK(P_FP64, L_MCONTIG, 1, 8, 2, 3), SK(P_FP64, L_MCONTIG, 2, 8, 2, 2), SK(P_FP64, L_MCONTIG, 4, 8, 2, 2),
+    SK(P_FP64, L_MCONTIG, 1, 8, 2, 3), SK(P_FP64, L_MCONTIG, 2, 8, 2, 2), SK(P_FP64, L_MCONTIG, 4, 8, 1, 2),
     SK(P_FP32, L_MCONTIG, 1, 8, 4, 3), SK(P_FP32, L_MCONTIG, 2, 8, 2, 3), SK(P_FP32, L_MCONTIG, 4, 8, 2, 2),
-    SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 2, 2),
-    SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 2, 2),
+    SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 1, 2),
+    SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
 };
 #undef SK
 

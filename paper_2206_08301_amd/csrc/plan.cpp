@@ -13,6 +13,7 @@
 #include "kernels.h"
 #include "mttkrp.h"
 #include "plan.h"
+#include "tune.h"
 
 namespace deinsum {
 
@@ -27,39 +28,25 @@ int ke_of(int prec) { return (prec == P_BF16 || prec == P_BF16X3) ? 8 : 1; }
 
 }  // namespace
 
-deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hint, MttkrpPlan *out)
+deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *kernel, int split_hint, MttkrpPlan *out)
 {
     MttkrpPlan p;
     p.prec = pb.prec;
     const int N = pb.N, n = pb.n;
-    p.nt = pb.R <= 16 ? 1 : (pb.R <= 32 ? 2 : 4);
+    p.kernel = kernel;
+    p.nt = kernel->nt;
     p.col_blocks = cdiv(pb.R, 16 * p.nt);
-    p.family = (n == N - 1) ? PLAN_MTTKRP_MCONTIG : PLAN_MTTKRP_KCONTIG;
-    if (plan_hint != 0 && plan_hint != p.family)
-        return fail(DEINSUM_ERR_UNSUPPORTED, "plan_hint does not match the free mode");
-    const int layout = (p.family == PLAN_MTTKRP_KCONTIG) ? L_KCONTIG : L_MCONTIG;
+    const int layout = kernel->layout;
+    p.family = (layout == L_KCONTIG) ? PLAN_MTTKRP_KCONTIG : PLAN_MTTKRP_MCONTIG;
+    if ((layout == L_MCONTIG) != (n == N - 1))
+        return fail(DEINSUM_ERR_UNSUPPORTED, "kernel layout does not match the free mode");
     const int g = (layout == L_KCONTIG) ? N - 1 : N - 2;
     const int64_t Ig = pb.dims[g], In = pb.dims[n];
     int64_t O = 1;
     for (int m = 0; m < N; ++m)
         if (m != n && m != g) O *= pb.dims[m];
-
-    int count = 0;
-    const StreamKernelInfo *table = stream_kernels(&count);
-    int64_t best_padded = 0;
-    for (int i = 0; i < count; ++i) {
-        const StreamKernelInfo &k = table[i];
-        if (k.prec != pb.prec || k.layout != layout || k.nt != p.nt) continue;
-        const int64_t slice = 4LL * k.ni * ke_of(pb.prec);
-        const int64_t padded = cdiv(Ig, slice) * slice;
-        if (!p.kernel || padded < best_padded) {
-            p.kernel = &k;
-            best_padded = padded;
-        }
-    }
-    if (!p.kernel) return fail(DEINSUM_ERR_UNSUPPORTED, "no compiled MTTKRP kernel for this precision and rank");
-    p.ni = p.kernel->ni;
-    p.mt = p.kernel->mt;
+    p.ni = kernel->ni;
+    p.mt = kernel->mt;
     p.slice = 4 * p.ni * ke_of(pb.prec);
     p.tile_rows = (layout == L_KCONTIG) ? 16 : 16 * p.mt;
     const int64_t nks = cdiv(Ig, p.slice);
@@ -91,6 +78,43 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
     p.name = buf;
     *out = p;
     return DEINSUM_OK;
+}
+
+deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hint, MttkrpPlan *out)
+{
+    const int N = pb.N, n = pb.n;
+    const int nt = pb.R <= 16 ? 1 : (pb.R <= 32 ? 2 : 4);
+    const int family = (n == N - 1) ? PLAN_MTTKRP_MCONTIG : PLAN_MTTKRP_KCONTIG;
+    if (plan_hint != 0 && plan_hint != family)
+        return fail(DEINSUM_ERR_UNSUPPORTED, "plan_hint does not match the free mode");
+    const int layout = (family == PLAN_MTTKRP_KCONTIG) ? L_KCONTIG : L_MCONTIG;
+    const int g = (layout == L_KCONTIG) ? N - 1 : N - 2;
+    const int64_t Ig = pb.dims[g];
+    int count = 0;
+    const StreamKernelInfo *table = stream_kernels(&count);
+    TuneChoice tc;
+    if (plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc)) {
+        for (int i = 0; i < count; ++i) {
+            const StreamKernelInfo &k = table[i];
+            if (k.prec == pb.prec && k.layout == layout && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt)
+                return plan_geometry(pb, &k, tc.split, out);
+        }
+        // An entry for a variant that is no longer compiled falls back to the heuristic.
+    }
+    const StreamKernelInfo *best = nullptr;
+    int64_t best_padded = 0;
+    for (int i = 0; i < count; ++i) {
+        const StreamKernelInfo &k = table[i];
+        if (k.prec != pb.prec || k.layout != layout || k.nt != nt) continue;
+        const int64_t slice = 4LL * k.ni * ke_of(pb.prec);
+        const int64_t padded = cdiv(Ig, slice) * slice;
+        if (!best || padded < best_padded) {
+            best = &k;
+            best_padded = padded;
+        }
+    }
+    if (!best) return fail(DEINSUM_ERR_UNSUPPORTED, "no compiled MTTKRP kernel for this precision and rank");
+    return plan_geometry(pb, best, split_hint, out);
 }
 
 }  // namespace deinsum

@@ -40,7 +40,10 @@ struct MttkrpProblem {
     int prec = 0;
 };
 
-// Heuristic plan; split_hint > 0 forces the number of outer chunks.
+// Launch geometry for a given kernel variant; split_hint > 0 forces the number of outer chunks.
+deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *kernel, int split_hint, MttkrpPlan *out);
+
+// Heuristic plan (kernel variant with the least padding of mode g, then plan_geometry).
 deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hint, MttkrpPlan *out);
 
 }  // namespace deinsum

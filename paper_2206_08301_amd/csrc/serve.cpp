@@ -1,0 +1,546 @@
+// serve.cpp -- request loop for CP-ALS MTTKRP requests on resident tensors.
+//
+// Requests (tensor, mode) arrive over time.  A scheduler thread keeps, per
+// tensor, a FIFO of its requests (the mode-n update of a sweep must see the
+// factors the previous request wrote) and serves them in one of two ways:
+//   * batched: continuous batching.  Whenever an epoch slot is free, every
+//     ready request (its tensor idle, it is the head of the tensor's FIFO)
+//     is admitted, in arrival order, while its workspace fits the HBM budget
+//     and the epoch has slots; the epoch runs as one persistent batch launch
+//     (deinsum_batch_*) followed by one batched CP-ALS update kernel.  Up to
+//     two epochs are in flight on two streams, so requests that arrive while
+//     one epoch runs start on the device before it finishes.
+//   * per request: each request is launched on arrival (MTTKRP, then the
+//     update) on one stream, in arrival order.
+// Latency of a request = host clock when its completion is observed minus its
+// scheduled arrival time.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "als.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace deinsum;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct STensor {
+    int order = 0;
+    int64_t dims[DEINSUM_MAX_ORDER] = {0};
+    int64_t R = 0;
+    int prec = 0;
+    const void *X = nullptr;
+    void *U[DEINSUM_MAX_ORDER] = {nullptr};
+    double *M = nullptr;      // FP64 MTTKRP output, max dim x R (server-owned, one allocation ...)
+    double *Xs = nullptr;     // ... unnormalised update, max dim x R
+    double *Gp = nullptr;     // ... partial Grams, als_blocks(max dim) x R x R
+    double *G = nullptr;      // ... Gram cache, order x R x R
+    size_t ws[DEINSUM_MAX_ORDER] = {0};
+    bool busy = false;
+    std::deque<int64_t> fifo; // pending requests of this tensor, arrival order
+};
+
+AlsJob als_job_for(const STensor &t, int mode)
+{
+    AlsJob aj;
+    std::memset(&aj, 0, sizeof(aj));
+    aj.order = t.order;
+    aj.mode = mode;
+    aj.R = static_cast<int32_t>(t.R);
+    aj.prec = t.prec;
+    for (int m = 0; m < t.order; ++m) {
+        aj.dims[m] = t.dims[m];
+        aj.U[m] = t.U[m];
+    }
+    aj.M = t.M;
+    aj.Xs = t.Xs;
+    aj.Gp = t.Gp;
+    aj.G = t.G;
+    return aj;
+}
+
+struct SRequest {
+    int32_t tensor = 0, mode = 0;
+    double arrival = 0, done = -1;
+    int64_t epoch = -1;
+};
+
+struct Epoch {
+    bool active = false;
+    std::vector<int64_t> reqs;
+    size_t footprint = 0;
+};
+
+deinsum_spec mttkrp_spec_for(int order, int mode)
+{
+    deinsum_spec sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.kind = DEINSUM_MTTKRP;
+    sp.order = order;
+    sp.free_mode = mode;
+    sp.n_factors = order - 1;
+    int k = 0;
+    for (int m = 0; m < order; ++m) {
+        sp.operand_of_mode[m] = -1;
+        if (m == mode) continue;
+        sp.factor_mode[k] = m;
+        sp.operand_of_mode[m] = k;
+        ++k;
+    }
+    return sp;
+}
+
+}  // namespace
+
+struct deinsum_server {
+    deinsum_server_config cfg{};
+    std::vector<STensor> tensors;
+    std::vector<SRequest> reqs;
+    std::mutex mu;                    // guards reqs growth and `submitted`
+    std::deque<int64_t> submitted;
+    std::thread sched;
+    std::atomic<bool> stop{false};
+    std::atomic<bool> failed{false};
+    std::string error;
+    std::atomic<int64_t> completed{0};
+    int64_t nsubmitted = 0;
+    Clock::time_point t0;
+    bool started = false;
+    int device = 0;
+    // batched
+    deinsum_batch *batch[2] = {nullptr, nullptr};
+    hipStream_t stream[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    AlsJob *als_pinned[2] = {nullptr, nullptr};
+    AlsJob *als_dev[2] = {nullptr, nullptr};
+    Epoch epoch[2];
+    size_t footprint_used = 0;
+    int64_t epochs = 0, max_batch = 0;
+    // per request
+    std::deque<std::pair<int64_t, hipEvent_t>> inflight;
+    std::vector<hipEvent_t> event_pool;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+void set_failed(deinsum_server *s, const std::string &msg)
+{
+    s->error = msg;
+    s->failed = true;
+}
+
+bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
+{
+    Epoch &ep = s->epoch[e];
+    ep.reqs.clear();
+    ep.footprint = 0;
+    const size_t cap = static_cast<size_t>(std::max(1, s->cfg.max_jobs_per_epoch));
+    for (auto it = pending.begin(); it != pending.end() && ep.reqs.size() < cap;) {
+        const int64_t r = *it;
+        STensor &t = s->tensors[s->reqs[r].tensor];
+        const size_t ws = t.ws[s->reqs[r].mode];
+        const bool head = !t.fifo.empty() && t.fifo.front() == r;
+        if (!t.busy && head && (s->footprint_used + ep.footprint + ws <= s->cfg.hbm_budget_bytes || ep.reqs.empty())) {
+            t.busy = true;
+            ep.reqs.push_back(r);
+            ep.footprint += ws;
+            it = pending.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    if (ep.reqs.empty()) return false;
+    deinsum_batch_reset(s->batch[e]);
+    int64_t als_total = 0;
+    for (size_t k = 0; k < ep.reqs.size(); ++k) {
+        SRequest &rq = s->reqs[ep.reqs[k]];
+        STensor &t = s->tensors[rq.tensor];
+        const deinsum_spec sp = mttkrp_spec_for(t.order, rq.mode);
+        const void *ops[DEINSUM_MAX_ORDER];
+        for (int q = 0; q < t.order - 1; ++q) ops[q] = t.U[sp.factor_mode[q]];
+        deinsum_opts o;
+        deinsum_opts_init(&o);
+        o.precision = t.prec;
+        o.out_dtype = DEINSUM_F64;
+        if (deinsum_batch_add_mttkrp(s->batch[e], &sp, t.dims, t.R, t.X, ops, t.M, &o, nullptr) != DEINSUM_OK) {
+            set_failed(s, std::string("serve: batch_add: ") + deinsum_last_error());
+            return false;
+        }
+        AlsJob &aj = s->als_pinned[e][k];
+        aj = als_job_for(t, rq.mode);
+        aj.block_begin = als_total;
+        als_total += als_blocks(t.dims[rq.mode]);
+        rq.epoch = s->epochs;
+    }
+    if (deinsum_batch_launch(s->batch[e], s->stream[e]) != DEINSUM_OK) {
+        set_failed(s, std::string("serve: batch_launch: ") + deinsum_last_error());
+        return false;
+    }
+    if (s->cfg.als_update) {
+        (void)hipMemcpyAsync(s->als_dev[e], s->als_pinned[e], sizeof(AlsJob) * ep.reqs.size(), hipMemcpyHostToDevice,
+                             s->stream[e]);
+        if (launch_als_batch(s->als_dev[e], static_cast<int>(ep.reqs.size()), als_total, s->stream[e]) != DEINSUM_OK) {
+            set_failed(s, std::string("serve: ") + deinsum_last_error());
+            return false;
+        }
+    }
+    if (hipEventRecord(s->ev[e], s->stream[e]) != hipSuccess) {
+        set_failed(s, "serve: event record failed");
+        return false;
+    }
+    ep.active = true;
+    s->footprint_used += ep.footprint;
+    ++s->epochs;
+    s->max_batch = std::max<int64_t>(s->max_batch, static_cast<int64_t>(ep.reqs.size()));
+    return true;
+}
+
+void complete_epoch(deinsum_server *s, int e)
+{
+    Epoch &ep = s->epoch[e];
+    const double t = s->now();
+    for (int64_t r : ep.reqs) {
+        SRequest &rq = s->reqs[r];
+        rq.done = t;
+        STensor &tn = s->tensors[rq.tensor];
+        tn.busy = false;
+        if (!tn.fifo.empty() && tn.fifo.front() == r) tn.fifo.pop_front();
+    }
+    s->completed += static_cast<int64_t>(ep.reqs.size());
+    s->footprint_used -= ep.footprint;
+    ep.active = false;
+    ep.reqs.clear();
+}
+
+bool launch_one(deinsum_server *s, int64_t r)
+{
+    SRequest &rq = s->reqs[r];
+    STensor &t = s->tensors[rq.tensor];
+    const deinsum_spec sp = mttkrp_spec_for(t.order, rq.mode);
+    const void *ops[DEINSUM_MAX_ORDER];
+    for (int q = 0; q < t.order - 1; ++q) ops[q] = t.U[sp.factor_mode[q]];
+    deinsum_opts o;
+    deinsum_opts_init(&o);
+    o.precision = t.prec;
+    o.out_dtype = DEINSUM_F64;
+    if (deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]) != DEINSUM_OK) {
+        set_failed(s, std::string("serve: mttkrp: ") + deinsum_last_error());
+        return false;
+    }
+    if (s->cfg.als_update) {
+        if (launch_als_one(als_job_for(t, rq.mode), s->stream[0]) != DEINSUM_OK) {
+            set_failed(s, std::string("serve: ") + deinsum_last_error());
+            return false;
+        }
+    }
+    hipEvent_t ev;
+    if (!s->event_pool.empty()) {
+        ev = s->event_pool.back();
+        s->event_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        set_failed(s, "serve: event creation failed");
+        return false;
+    }
+    (void)hipEventRecord(ev, s->stream[0]);
+    s->inflight.emplace_back(r, ev);
+    rq.epoch = s->epochs++;
+    return true;
+}
+
+void scheduler(deinsum_server *s)
+{
+    (void)hipSetDevice(s->device);
+    std::deque<int64_t> pending;  // arrival order
+    for (;;) {
+        bool progress = false;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            while (!s->submitted.empty()) {
+                const int64_t r = s->submitted.front();
+                s->submitted.pop_front();
+                s->tensors[s->reqs[r].tensor].fifo.push_back(r);
+                pending.push_back(r);
+                progress = true;
+            }
+        }
+        if (s->failed) return;
+        if (s->cfg.batched) {
+            for (int e = 0; e < 2; ++e)
+                if (s->epoch[e].active && hipEventQuery(s->ev[e]) == hipSuccess) {
+                    complete_epoch(s, e);
+                    progress = true;
+                }
+            const int slots = std::max(1, std::min(2, s->cfg.epochs_in_flight));
+            for (int e = 0; e < slots && !pending.empty(); ++e)
+                if (!s->epoch[e].active && launch_epoch(s, e, pending)) progress = true;
+        } else {
+            while (!pending.empty()) {
+                const int64_t r = pending.front();
+                pending.pop_front();
+                if (!launch_one(s, r)) return;
+                progress = true;
+            }
+            while (!s->inflight.empty() && hipEventQuery(s->inflight.front().second) == hipSuccess) {
+                const int64_t r = s->inflight.front().first;
+                s->reqs[r].done = s->now();
+                STensor &tn = s->tensors[s->reqs[r].tensor];
+                if (!tn.fifo.empty() && tn.fifo.front() == r) tn.fifo.pop_front();
+                s->event_pool.push_back(s->inflight.front().second);
+                s->inflight.pop_front();
+                ++s->completed;
+                progress = true;
+            }
+        }
+        if (s->failed) return;
+        if (s->stop && pending.empty()) {
+            bool idle = s->inflight.empty() && !s->epoch[0].active && !s->epoch[1].active;
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (idle && s->submitted.empty()) return;
+        }
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(5));
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void deinsum_server_config_init(deinsum_server_config *cfg)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->batched = 1;
+    cfg->max_jobs_per_epoch = 256;
+    cfg->epochs_in_flight = 2;
+    cfg->als_update = 1;
+    cfg->max_requests = int64_t(1) << 20;
+    cfg->hbm_budget_bytes = size_t(4) << 30;
+}
+
+deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_server **out)
+{
+    if (!out) return fail(DEINSUM_ERR_INVALID_ARG, "server_create: null out");
+    *out = nullptr;
+    auto *s = new deinsum_server();
+    deinsum_server_config_init(&s->cfg);
+    if (cfg) s->cfg = *cfg;
+    if (s->cfg.max_jobs_per_epoch < 1 || s->cfg.max_jobs_per_epoch > 65536) {
+        delete s;
+        return fail(DEINSUM_ERR_INVALID_ARG, "server_create: max_jobs_per_epoch must be 1..65536");
+    }
+    if (s->cfg.max_requests < 1 || s->cfg.max_requests > (int64_t(1) << 28)) {
+        delete s;
+        return fail(DEINSUM_ERR_INVALID_ARG, "server_create: max_requests must be 1..2^28");
+    }
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(DEINSUM_ERR_DEVICE, "server_create: no current device");
+    }
+    for (int e = 0; e < 2; ++e) {
+        if (hipStreamCreateWithFlags(&s->stream[e], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s->ev[e], hipEventDisableTiming) != hipSuccess) {
+            deinsum_server_destroy(s);
+            return fail(DEINSUM_ERR_DEVICE, "server_create: stream/event creation failed");
+        }
+        if (s->cfg.batched) {
+            if (deinsum_batch_create(s->cfg.max_jobs_per_epoch, &s->batch[e]) != DEINSUM_OK) {
+                deinsum_server_destroy(s);
+                return DEINSUM_ERR_DEVICE;
+            }
+            const size_t bytes = sizeof(AlsJob) * static_cast<size_t>(s->cfg.max_jobs_per_epoch);
+            if (hipHostMalloc(reinterpret_cast<void **>(&s->als_pinned[e]), bytes, hipHostMallocDefault) != hipSuccess ||
+                hipMalloc(reinterpret_cast<void **>(&s->als_dev[e]), bytes) != hipSuccess) {
+                deinsum_server_destroy(s);
+                return fail(DEINSUM_ERR_NO_MEMORY, "server_create: job table allocation failed");
+            }
+        }
+    }
+    *out = s;
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_add_tensor(deinsum_server *s, int32_t order, const int64_t *dims, int64_t R,
+                                         int32_t precision, const void *X, void *const *U, int32_t *tensor_id)
+{
+    if (!s || !dims || !X || !U) return fail(DEINSUM_ERR_INVALID_ARG, "server_add_tensor: null argument");
+    if (s->started) return fail(DEINSUM_ERR_BUSY, "server_add_tensor: server already started");
+    if (order < 2 || order > DEINSUM_MAX_ORDER) return fail(DEINSUM_ERR_SHAPE, "server_add_tensor: order 2..8");
+    if (R < 1 || R > kAlsMaxRank) return fail(DEINSUM_ERR_SHAPE, "server_add_tensor: rank 1..64");
+    if (precision != DEINSUM_PREC_FP64 && precision != DEINSUM_PREC_FP32)
+        return fail(DEINSUM_ERR_UNSUPPORTED, "server_add_tensor: FP64 or FP32 tensors");
+    STensor t;
+    t.order = order;
+    t.R = R;
+    t.prec = precision;
+    t.X = X;
+    int64_t maxd = 0;
+    for (int m = 0; m < order; ++m) {
+        if (dims[m] < 1) return fail(DEINSUM_ERR_SHAPE, "server_add_tensor: dims >= 1");
+        if (!U[m]) return fail(DEINSUM_ERR_INVALID_ARG, "server_add_tensor: null factor");
+        t.dims[m] = dims[m];
+        t.U[m] = U[m];
+        maxd = std::max(maxd, dims[m]);
+    }
+    const size_t rows_bytes = sizeof(double) * static_cast<size_t>(maxd * R);
+    const size_t gp_bytes = sizeof(double) * static_cast<size_t>(als_blocks(maxd) * R * R);
+    const size_t g_bytes = sizeof(double) * static_cast<size_t>(order * R * R);
+    char *buf = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&buf), 2 * rows_bytes + gp_bytes + g_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DEINSUM_ERR_NO_MEMORY, "server_add_tensor: state allocation failed");
+    }
+    t.M = reinterpret_cast<double *>(buf);
+    t.Xs = reinterpret_cast<double *>(buf + rows_bytes);
+    t.Gp = reinterpret_cast<double *>(buf + 2 * rows_bytes);
+    t.G = reinterpret_cast<double *>(buf + 2 * rows_bytes + gp_bytes);
+    // The caller's X and factors must be ready; the Gram cache starts from them.
+    if (hipDeviceSynchronize() != hipSuccess || launch_als_grams(als_job_for(t, 0), s->stream[0]) != DEINSUM_OK ||
+        hipStreamSynchronize(s->stream[0]) != hipSuccess) {
+        (void)hipFree(buf);
+        return fail(DEINSUM_ERR_DEVICE, "server_add_tensor: Gram set-up failed");
+    }
+    deinsum_opts o;
+    deinsum_opts_init(&o);
+    o.precision = precision;
+    for (int m = 0; m < order; ++m) {
+        const deinsum_spec sp = mttkrp_spec_for(order, m);
+        size_t ws = 0;
+        const int64_t r = R;
+        if (deinsum_workspace_size(&sp, dims, &r, &o, &ws) != DEINSUM_OK) ws = 0;
+        t.ws[m] = ws;
+    }
+    if (tensor_id) *tensor_id = static_cast<int32_t>(s->tensors.size());
+    s->tensors.push_back(std::move(t));
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_start(deinsum_server *s)
+{
+    if (!s) return fail(DEINSUM_ERR_INVALID_ARG, "server_start: null server");
+    if (s->started) return fail(DEINSUM_ERR_BUSY, "server_start: already started");
+    s->reqs.reserve(static_cast<size_t>(s->cfg.max_requests));
+    s->t0 = Clock::now();
+    s->started = true;
+    s->sched = std::thread(scheduler, s);
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_submit(deinsum_server *s, int32_t tensor_id, int32_t mode, double arrival_s,
+                                     int64_t *request_id)
+{
+    if (!s || !s->started) return fail(DEINSUM_ERR_INVALID_ARG, "server_submit: server not started");
+    if (tensor_id < 0 || tensor_id >= static_cast<int32_t>(s->tensors.size()))
+        return fail(DEINSUM_ERR_INVALID_ARG, "server_submit: unknown tensor");
+    if (mode < 0 || mode >= s->tensors[tensor_id].order) return fail(DEINSUM_ERR_INVALID_ARG, "server_submit: bad mode");
+    if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server_submit: server failed: " + s->error);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->reqs.size() == s->reqs.capacity())
+        return fail(DEINSUM_ERR_BUSY, "server_submit: request table full");  // reqs must not reallocate while served
+    SRequest rq;
+    rq.tensor = tensor_id;
+    rq.mode = mode;
+    rq.arrival = arrival_s >= 0 ? arrival_s : s->now();
+    s->reqs.push_back(rq);
+    const int64_t id = static_cast<int64_t>(s->reqs.size()) - 1;
+    s->submitted.push_back(id);
+    ++s->nsubmitted;
+    if (request_id) *request_id = id;
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_replay(deinsum_server *s, int64_t n, const double *arrival_s, const int32_t *tensor_id,
+                                     const int32_t *mode)
+{
+    if (!s || !s->started || !arrival_s || !tensor_id || !mode || n < 0)
+        return fail(DEINSUM_ERR_INVALID_ARG, "server_replay: bad argument");
+    const Clock::time_point base = s->t0;
+    for (int64_t i = 0; i < n; ++i) {
+        const Clock::time_point due = base + std::chrono::duration_cast<Clock::duration>(
+                                                 std::chrono::duration<double>(arrival_s[i]));
+        while (Clock::now() < due) {
+            const auto left = due - Clock::now();
+            if (left > std::chrono::microseconds(200)) std::this_thread::sleep_for(left - std::chrono::microseconds(150));
+        }
+        if (deinsum_status st = deinsum_server_submit(s, tensor_id[i], mode[i], arrival_s[i], nullptr)) return st;
+    }
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_drain(deinsum_server *s)
+{
+    if (!s || !s->started) return fail(DEINSUM_ERR_INVALID_ARG, "server_drain: server not started");
+    for (;;) {
+        if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server failed: " + s->error);
+        int64_t nsub;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            nsub = s->nsubmitted;
+        }
+        if (s->completed >= nsub) break;
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_results(const deinsum_server *s, int64_t n, double *arrival_s, double *done_s,
+                                      int64_t *epoch)
+{
+    if (!s) return fail(DEINSUM_ERR_INVALID_ARG, "server_results: null server");
+    if (n > static_cast<int64_t>(s->reqs.size())) return fail(DEINSUM_ERR_INVALID_ARG, "server_results: n too large");
+    for (int64_t i = 0; i < n; ++i) {
+        if (arrival_s) arrival_s[i] = s->reqs[i].arrival;
+        if (done_s) done_s[i] = s->reqs[i].done;
+        if (epoch) epoch[i] = s->reqs[i].epoch;
+    }
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_stats(const deinsum_server *s, int64_t *completed, int64_t *epochs, int64_t *max_batch)
+{
+    if (!s) return fail(DEINSUM_ERR_INVALID_ARG, "server_stats: null server");
+    if (completed) *completed = s->completed;
+    if (epochs) *epochs = s->epochs;
+    if (max_batch) *max_batch = s->max_batch;
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_destroy(deinsum_server *s)
+{
+    if (!s) return DEINSUM_OK;
+    s->stop = true;
+    if (s->sched.joinable()) s->sched.join();
+    for (int e = 0; e < 2; ++e) {
+        if (s->stream[e]) (void)hipStreamSynchronize(s->stream[e]);
+        if (s->batch[e]) deinsum_batch_destroy(s->batch[e]);
+        if (s->als_pinned[e]) (void)hipHostFree(s->als_pinned[e]);
+        if (s->als_dev[e]) (void)hipFree(s->als_dev[e]);
+        if (s->ev[e]) (void)hipEventDestroy(s->ev[e]);
+        if (s->stream[e]) (void)hipStreamDestroy(s->stream[e]);
+    }
+    for (auto &p : s->inflight) (void)hipEventDestroy(p.second);
+    for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+    for (auto &t : s->tensors)
+        if (t.M) (void)hipFree(t.M);
+    delete s;
+    return DEINSUM_OK;
+}
+
+}  // extern "C"

@@ -15,10 +15,8 @@ namespace deinsum {
 // where c = N-1 is the contiguous mode and `slab` enumerates the other modes.
 struct TkArgs {
     const void *X;
-    const void *Ua;
-    int64_t ldua;
-    const void *Uc;
-    int64_t lduc;
+    const double *Ua;        // U^a zero-padded to 16*NTA columns (FP64 copy)
+    const double *Uc;        // U^c zero-padded to 16*NTC columns (FP64 copy), stage 2 only
     int64_t Ia, Ic, stride_a;
     OuterDesc od;            // slab modes (X strides only)
     int64_t n_slabs, slabs_per_group;

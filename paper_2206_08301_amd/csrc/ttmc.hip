@@ -18,6 +18,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -45,57 +46,77 @@ __device__ __forceinline__ double ldu_p(const void *p, int64_t i, int prec)
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-template <typename T, int MT>
-__device__ __forceinline__ void load_m(T (&dst)[MT], const T *__restrict__ src, bool vec, int valid)
+template <typename T, int n>
+__device__ __forceinline__ void load_vec_n(T *dst, const T *__restrict__ src)
 {
-    if constexpr ((MT * sizeof(T)) % 16 == 0) {
-        if (vec && valid >= MT) {
-            constexpr int NV = MT * sizeof(T) / 16;
-            const v4u *s = reinterpret_cast<const v4u *>(src);
-            v4u tmp[NV];
+    static_assert((n * sizeof(T)) % 8 == 0, "whole 8-byte words");
+    if constexpr ((n * sizeof(T)) % 16 == 0) {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) tmp[i] = __builtin_nontemporal_load(s + i);
-            __builtin_memcpy(dst, tmp, sizeof(dst));
-            return;
+        for (int i = 0; i < static_cast<int>(n * sizeof(T) / 16); ++i) {
+            const v4u v = reinterpret_cast<const v4u *>(src)[i];
+            __builtin_memcpy(dst + i * (16 / sizeof(T)), &v, 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < static_cast<int>(n * sizeof(T) / 8); ++i) {
+            const uint64_t v = reinterpret_cast<const uint64_t *>(src)[i];
+            __builtin_memcpy(dst + i * (8 / sizeof(T)), &v, 8);
         }
     }
-#pragma unroll
-    for (int i = 0; i < MT; ++i) dst[i] = (i < valid) ? src[i] : T{};
 }
 
+// Slab odometer over the X offset, unrolled over the maximum number of slab
+// modes so the indices stay in registers.
 struct SlabWalk {
     int64_t idx[kMaxOuter];
     int64_t off;
-    __device__ void init(const OuterDesc &od, int64_t o)
+    __device__ __forceinline__ void init(const OuterDesc &od, int64_t o)
     {
         off = 0;
-        for (int m = od.n_outer - 1; m >= 0; --m) {
-            idx[m] = o % od.dim[m];
-            o /= od.dim[m];
-            off += idx[m] * od.xstride[m];
+#pragma unroll
+        for (int m = kMaxOuter - 1; m >= 0; --m) {
+            idx[m] = 0;
+            if (m < od.n_outer) {
+                idx[m] = o % od.dim[m];
+                o /= od.dim[m];
+                off += idx[m] * od.xstride[m];
+            }
         }
     }
-    __device__ void next(const OuterDesc &od)
+    __device__ __forceinline__ void next(const OuterDesc &od)
     {
-        for (int m = od.n_outer - 1; m >= 0; --m) {
-            off += od.xstride[m];
-            if (++idx[m] < od.dim[m]) return;
-            off -= idx[m] * od.xstride[m];
-            idx[m] = 0;
+        bool carry = true;
+#pragma unroll
+        for (int m = kMaxOuter - 1; m >= 0; --m) {
+            if (m < od.n_outer && carry) {
+                off += od.xstride[m];
+                if (++idx[m] < od.dim[m]) {
+                    carry = false;
+                } else {
+                    off -= idx[m] * od.xstride[m];
+                    idx[m] = 0;
+                }
+            }
         }
     }
 };
 
+// Fused two-mode pass.  Per slab, the K loop over i_a runs in ring steps of
+// UB K-steps (4*UB rows), prefetched NBUF-1 steps ahead; complete steps issue
+// a fixed sequence of unmasked loads (the factors are zero-padded to whole
+// column tiles), so the compiler waits for exactly the oldest step.
 template <int P, int NTA, int NTC, int MT, bool STAGE2>
-__global__ void __launch_bounds__(256) ttmc_fused_kernel(const TkArgs a)
+__global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
 {
     using XT = typename TkTypes<P>::XT;
     using DT = typename TkTypes<P>::DT;
-    constexpr int UB = 4;
+    constexpr int UB = 2;     // K-steps (of 4 rows) per ring step
+    constexpr int NBUF = 4;   // ring depth
     constexpr int TA = 16 * NTA, TC = 16 * NTC;
-    __shared__ double lds[STAGE2 ? 4 * TA * TC : 1];
+    __shared__ double lds[STAGE2 ? TA * TC : 1];
 
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, c = lane & 15;
     const int64_t b = blockIdx.x;
     const int cgroup = static_cast<int>(b % a.n_cgroups);
@@ -104,12 +125,13 @@ __global__ void __launch_bounds__(256) ttmc_fused_kernel(const TkArgs a)
     const int64_t cbase = static_cast<int64_t>(ctile) * 16 * MT;
     const int64_t ibase = cbase + MT * c;
     const int ivalid = (ctile < a.n_ctiles) ? static_cast<int>(tmin(MT, tmax(0, a.Ic - ibase))) : 0;
+    const bool full = a.vec_ok && ctile < a.n_ctiles && cbase + 16 * MT <= a.Ic && (MT * sizeof(XT)) % 8 == 0;
     const int64_t s0 = sg * a.slabs_per_group;
     const int64_t s1 = tmin(a.n_slabs, s0 + a.slabs_per_group);
     const XT *__restrict__ X = static_cast<const XT *>(a.X);
-    const bool vec = a.vec_ok != 0;
-    const int64_t nsteps = (a.Ia + 3) / 4;
-    const int tile_elems = TA * TC;
+    const double *__restrict__ Ua = a.Ua;  // zero-padded FP64 copy, row stride TA
+    const int64_t nsteps = (a.Ia + 4 * UB - 1) / (4 * UB);
+    const int64_t nfull = a.Ia / (4 * UB);  // ring steps whose rows are all in range
 
     SlabWalk walk;
     walk.init(a.od, s0);
@@ -120,42 +142,68 @@ __global__ void __launch_bounds__(256) ttmc_fused_kernel(const TkArgs a)
 #pragma unroll
             for (int nt = 0; nt < NTA; ++nt) d[mt][nt] = DT{0, 0, 0, 0};
         const XT *xs = X + walk.off + ibase;
-        XT xbuf[2][UB][MT];
-        double ubuf[2][UB][NTA];
-        auto load_block = [&](int s, int64_t st0) {
+
+        auto run = [&](auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            XT xb[NBUF][UB][MT];
+            double ub[NBUF][UB][NTA];
+            // Complete ring step: unmasked loads (FULL) or column-masked loads.
+            auto issue = [&](int slot, int64_t st, bool guard) {
 #pragma unroll
-            for (int u = 0; u < UB; ++u) {
-                const int64_t r = (st0 + u) * 4 + g;
-                const bool rv = r < a.Ia;
-                load_m<XT, MT>(xbuf[s][u], xs + r * a.stride_a, vec, rv ? ivalid : 0);
+                for (int u = 0; u < UB; ++u) {
+                    const int64_t r = (st * UB + u) * 4 + g;
+                    const bool rv = !guard || r < a.Ia;
 #pragma unroll
-                for (int nt = 0; nt < NTA; ++nt) {
-                    const int col = nt * 16 + c;
-                    ubuf[s][u][nt] = (rv && col < a.ra) ? ldu_p(a.Ua, r * a.ldua + col, P) : 0.0;
+                    for (int nt = 0; nt < NTA; ++nt)
+                        ub[slot][u][nt] = rv ? Ua[r * TA + nt * 16 + c] : 0.0;
+                    if constexpr (FULL && (MT * sizeof(XT)) % 8 == 0) {
+                        if (rv) load_vec_n<XT, MT>(xb[slot][u], xs + r * a.stride_a);
+                        else {
+#pragma unroll
+                            for (int i = 0; i < MT; ++i) xb[slot][u][i] = XT{};
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < MT; ++i) xb[slot][u][i] = (rv && i < ivalid) ? xs[r * a.stride_a + i] : XT{};
+                    }
+                }
+            };
+            auto mac = [&](int slot) {
+#pragma unroll
+                for (int u = 0; u < UB; ++u)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < NTA; ++nt) {
+                            if constexpr (P == P_FP64)
+                                d[mt][nt] = mfma_f64(xb[slot][u][mt], ub[slot][u][nt], d[mt][nt]);
+                            else
+                                d[mt][nt] = mfma_f32(xb[slot][u][mt], static_cast<float>(ub[slot][u][nt]), d[mt][nt]);
+                        }
+            };
+#pragma unroll
+            for (int u = 0; u < NBUF - 1; ++u)
+                if (u < nsteps) issue(u, u, u >= nfull);
+            int64_t t = 0;
+            for (; t + 2 * NBUF - 2 < nfull; t += NBUF) {
+#pragma unroll
+                for (int u = 0; u < NBUF; ++u) {
+                    issue((u + NBUF - 1) % NBUF, t + u + NBUF - 1, false);
+                    mac(u);
+                }
+            }
+            for (; t < nsteps; t += NBUF) {
+#pragma unroll
+                for (int u = 0; u < NBUF; ++u) {
+                    if (t + u < nsteps) {
+                        if (t + u + NBUF - 1 < nsteps) issue((u + NBUF - 1) % NBUF, t + u + NBUF - 1, true);
+                        mac(u);
+                    }
                 }
             }
         };
-        auto mac_block = [&](int s) {
-#pragma unroll
-            for (int u = 0; u < UB; ++u)
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int nt = 0; nt < NTA; ++nt) {
-                        if constexpr (P == P_FP64)
-                            d[mt][nt] = mfma_f64(xbuf[s][u][mt], ubuf[s][u][nt], d[mt][nt]);
-                        else
-                            d[mt][nt] = mfma_f32(xbuf[s][u][mt], static_cast<float>(ubuf[s][u][nt]), d[mt][nt]);
-                    }
-        };
-        load_block(0, 0);
-        for (int64_t st = 0; st < nsteps; st += 2 * UB) {
-            if (st + UB < nsteps) load_block(1, st + UB);
-            mac_block(0);
-            if (st + UB >= nsteps) break;
-            if (st + 2 * UB < nsteps) load_block(0, st + 2 * UB);
-            mac_block(1);
-        }
+        if (full) run(std::true_type{});
+        else run(std::false_type{});
 
         if constexpr (STAGE2) {
             // Z[r_c, r_a] = sum_{i_c} U^c[i_c, r_c] D[i_c, r_a]: K-step v pairs slot g
@@ -170,11 +218,10 @@ __global__ void __launch_bounds__(256) ttmc_fused_kernel(const TkArgs a)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int64_t rowc = cbase + MT * tile_row<P>(lane, v) + mt;
+                    const bool rv = ctile < a.n_ctiles && rowc < a.Ic;
 #pragma unroll
                     for (int tc = 0; tc < NTC; ++tc) {
-                        const int col = tc * 16 + c;
-                        const double u = (ctile < a.n_ctiles && rowc < a.Ic && col < a.rc)
-                                             ? ldu_p(a.Uc, rowc * a.lduc + col, P) : 0.0;
+                        const double u = rv ? a.Uc[rowc * TC + tc * 16 + c] : 0.0;
 #pragma unroll
                         for (int ta = 0; ta < NTA; ++ta) {
                             if constexpr (P == P_FP64)
@@ -184,22 +231,24 @@ __global__ void __launch_bounds__(256) ttmc_fused_kernel(const TkArgs a)
                         }
                     }
                 }
-            // Fixed-order reduction over the workgroup's c-tiles.
+            // Fixed-order reduction over the workgroup's c-tiles (wave order).
+            for (int ww = 0; ww < a.nwaves; ++ww) {
+                if (w == ww) {
 #pragma unroll
-            for (int tc = 0; tc < NTC; ++tc)
+                    for (int tc = 0; tc < NTC; ++tc)
 #pragma unroll
-                for (int ta = 0; ta < NTA; ++ta)
+                        for (int ta = 0; ta < NTA; ++ta)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        lds[w * tile_elems + (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v)] =
-                            static_cast<double>(z[tc][ta][v]);
-            __syncthreads();
-            double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * tile_elems;
-            for (int i = threadIdx.x; i < tile_elems; i += 64 * a.nwaves) {
-                double s = lds[i];
-                for (int ww = 1; ww < a.nwaves; ++ww) s += lds[ww * tile_elems + i];
-                out[i] = s;
+                            for (int v = 0; v < 4; ++v) {
+                                const int i = (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v);
+                                const double zv = static_cast<double>(z[tc][ta][v]);
+                                lds[i] = (ww == 0) ? zv : lds[i] + zv;
+                            }
+                }
+                __syncthreads();
             }
+            double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * (TA * TC);
+            for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) out[i] = lds[i];
             __syncthreads();
         } else {
             const int64_t rows = static_cast<int64_t>(a.n_ctiles) * 16 * MT;
@@ -217,6 +266,17 @@ __global__ void __launch_bounds__(256) ttmc_fused_kernel(const TkArgs a)
         }
         walk.next(a.od);
     }
+}
+
+// Zero-padded FP64 copy of a factor: dst[i][j] = src[i][j] for j < r, 0 up to ldd.
+__global__ void __launch_bounds__(256) pad_factor_kernel(const void *src, int prec, int64_t rows, int r, int ldd,
+                                                         double *dst)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= rows * ldd) return;
+    const int64_t i = e / ldd;
+    const int j = static_cast<int>(e % ldd);
+    dst[e] = (j < r) ? ldu_p(src, i * r + j, prec) : 0.0;
 }
 
 // Sum `parts` padded partial tensors and scatter into a strided destination.
@@ -295,18 +355,30 @@ void launch_tk(const TkArgs &a, int64_t grid, hipStream_t s)
 }
 
 using TkLaunch = void (*)(const TkArgs &, int64_t, hipStream_t);
-#define TK(P, A, C) {P, A, C, true, &launch_tk<P, A, C, 4, true>}
-#define TK1(P, A) {P, A, 0, false, &launch_tk<P, A, 1, 4, false>}
-const struct { int p, nta, ntc; bool s2; TkLaunch fn; } kTkTable[] = {
-    TK(P_FP64, 1, 1), TK(P_FP64, 1, 2), TK(P_FP64, 1, 4), TK(P_FP64, 2, 1), TK(P_FP64, 2, 2),
-    TK(P_FP64, 2, 4), TK(P_FP64, 4, 1), TK(P_FP64, 4, 2), TK(P_FP64, 4, 4),
-    TK(P_FP32, 1, 1), TK(P_FP32, 1, 2), TK(P_FP32, 1, 4), TK(P_FP32, 2, 1), TK(P_FP32, 2, 2),
-    TK(P_FP32, 2, 4), TK(P_FP32, 4, 1), TK(P_FP32, 4, 2), TK(P_FP32, 4, 4),
-    TK1(P_FP64, 1), TK1(P_FP64, 2), TK1(P_FP64, 4), TK1(P_FP32, 1), TK1(P_FP32, 2), TK1(P_FP32, 4),
+struct TkEntry {
+    int p, nta, ntc, mt;
+    bool s2;
+    TkLaunch fn;
+};
+// M tiles per wave shrink as the rank tiles grow, to stay within 2 waves per SIMD.
+#define TK(P, A, C, MT) {P, A, C, MT, true, &launch_tk<P, A, C, MT, true>}
+#define TK1(P, A, MT) {P, A, 0, MT, false, &launch_tk<P, A, 1, MT, false>}
+const TkEntry kTkTable[] = {
+    TK(P_FP64, 1, 1, 4), TK(P_FP64, 1, 2, 4), TK(P_FP64, 1, 4, 4), TK(P_FP64, 2, 1, 2), TK(P_FP64, 2, 2, 2),
+    TK(P_FP64, 2, 4, 2), TK(P_FP64, 4, 1, 1), TK(P_FP64, 4, 2, 1), TK(P_FP64, 4, 4, 1),
+    TK(P_FP32, 1, 1, 4), TK(P_FP32, 1, 2, 4), TK(P_FP32, 1, 4, 4), TK(P_FP32, 2, 1, 4), TK(P_FP32, 2, 2, 4),
+    TK(P_FP32, 2, 4, 4), TK(P_FP32, 4, 1, 2), TK(P_FP32, 4, 2, 2), TK(P_FP32, 4, 4, 2),
+    TK1(P_FP64, 1, 4), TK1(P_FP64, 2, 2), TK1(P_FP64, 4, 1), TK1(P_FP32, 1, 4), TK1(P_FP32, 2, 4), TK1(P_FP32, 4, 2),
 };
 #undef TK
 #undef TK1
-constexpr int kTkMT = 4;
+
+const TkEntry *find_tk(int prec, int nta, int ntc, bool s2)
+{
+    for (const auto &e : kTkTable)
+        if (e.p == prec && e.nta == nta && e.s2 == s2 && (!s2 || e.ntc == ntc)) return &e;
+    return nullptr;
+}
 
 int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int ntiles_for(int64_t r) { return r <= 16 ? 1 : (r <= 32 ? 2 : 4); }
@@ -321,12 +393,13 @@ struct TtmcPlan {
     int N = 0, n = 0, a = -1, c = -1;
     bool stage2 = true, via_mttkrp = false;
     int64_t I[DEINSUM_MAX_ORDER] = {0}, Rm[DEINSUM_MAX_ORDER] = {0};
-    int nta = 1, ntc = 1;
+    int nta = 1, ntc = 1, mt = 4;
+    const TkEntry *kernel = nullptr;
     std::vector<int> slab_modes;
     int64_t n_slabs = 1;
     int n_ctiles = 1, nwaves = 1, n_cgroups = 1;
     int64_t spg = 1, groups = 0;
-    size_t p_bytes = 0, z_bytes = 0, t_bytes = 0, total = 0;
+    size_t p_bytes = 0, z_bytes = 0, t_bytes = 0, pad_bytes = 0, total = 0;
 };
 
 deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, int prec,
@@ -366,7 +439,10 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
             p.slab_modes.push_back(m);
             p.n_slabs *= p.I[m];
         }
-    p.n_ctiles = static_cast<int>(cdivl(p.I[p.c], 16 * kTkMT));
+    p.kernel = find_tk(prec, p.nta, p.ntc, p.stage2);
+    if (!p.kernel) return fail(DEINSUM_ERR_UNSUPPORTED, "no fused TTMc kernel for this precision and ranks");
+    p.mt = p.kernel->mt;
+    p.n_ctiles = static_cast<int>(cdivl(p.I[p.c], 16 * p.mt));
     p.nwaves = std::min(4, p.n_ctiles);
     p.n_cgroups = static_cast<int>(cdivl(p.n_ctiles, p.nwaves));
     if (!p.stage2) p.n_cgroups = static_cast<int>(cdivl(p.n_ctiles, p.nwaves));
@@ -374,7 +450,7 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
     p.groups = p.n_cgroups * cdivl(p.n_slabs, p.spg);
     const int64_t TA = 16 * p.nta, TC = 16 * p.ntc;
     if (p.stage2) p.p_bytes = static_cast<size_t>(p.n_cgroups * p.n_slabs * TA * TC) * 8;
-    else p.p_bytes = static_cast<size_t>(p.n_slabs * p.n_ctiles * 16 * kTkMT * TA) * 8;
+    else p.p_bytes = static_cast<size_t>(p.n_slabs * p.n_ctiles * 16 * p.mt * TA) * 8;
     // Intermediate after the fused pass, then ping-pong buffers for the remaining products.
     int64_t zel = p.n_slabs * p.Rm[p.a] * (p.stage2 ? p.Rm[p.c] : p.I[n]);
     const bool remaining = p.slab_modes.size() > (p.stage2 ? 1u : 0u);
@@ -392,7 +468,8 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
         p.t_bytes = static_cast<size_t>(mx) * 8;
     }
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
-    p.total = align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes);
+    p.pad_bytes = align(static_cast<size_t>(p.I[p.a]) * TA * 8) + (p.stage2 ? align(static_cast<size_t>(p.I[p.c]) * TC * 8) : 0);
+    p.total = align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes) + p.pad_bytes;
     *out = p;
     return DEINSUM_OK;
 }
@@ -475,14 +552,28 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     double *Z = reinterpret_cast<double *>(base + align(p.p_bytes));
     double *T0 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes));
     double *T1 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes) + align(p.t_bytes));
+    double *Ua_pad = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes));
+    double *Uc_pad = reinterpret_cast<double *>(reinterpret_cast<char *>(Ua_pad) +
+                                                align(static_cast<size_t>(p.I[p.a]) * 16 * p.nta * 8));
+    {
+        const int lda = 16 * p.nta;
+        const int64_t na = p.I[p.a] * lda;
+        pad_factor_kernel<<<static_cast<unsigned>(cdivl(na, 256)), 256, 0, s>>>(Um[p.a], o.precision, p.I[p.a],
+                                                                              static_cast<int>(p.Rm[p.a]), lda, Ua_pad);
+        if (p.stage2) {
+            const int ldc = 16 * p.ntc;
+            const int64_t nc = p.I[p.c] * ldc;
+            pad_factor_kernel<<<static_cast<unsigned>(cdivl(nc, 256)), 256, 0, s>>>(
+                Um[p.c], o.precision, p.I[p.c], static_cast<int>(p.Rm[p.c]), ldc, Uc_pad);
+        }
+        if (deinsum_status st = check_launch("ttmc_pad_factor")) return st;
+    }
 
     // ---- fused pass
     TkArgs a{};
     a.X = X;
-    a.Ua = Um[p.a];
-    a.ldua = p.Rm[p.a];
-    a.Uc = p.stage2 ? Um[p.c] : nullptr;
-    a.lduc = p.stage2 ? p.Rm[p.c] : 0;
+    a.Ua = Ua_pad;
+    a.Uc = p.stage2 ? Uc_pad : nullptr;
     a.Ia = p.I[p.a];
     a.Ic = p.I[p.c];
     a.stride_a = stride[p.a];
@@ -499,16 +590,9 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     a.n_cgroups = p.n_cgroups;
     a.ra = static_cast<int>(p.Rm[p.a]);
     a.rc = p.stage2 ? static_cast<int>(p.Rm[p.c]) : 0;
-    a.vec_ok = ((p.I[p.c] * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    a.vec_ok = ((p.I[p.c] * xb) % 8 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
     a.P = P;
-    bool launched = false;
-    for (const auto &e : kTkTable)
-        if (e.p == o.precision && e.nta == p.nta && e.s2 == p.stage2 && (!p.stage2 || e.ntc == p.ntc)) {
-            e.fn(a, p.groups, s);
-            launched = true;
-            break;
-        }
-    if (!launched) return fail(DEINSUM_ERR_UNSUPPORTED, "no fused TTMc kernel for this precision and ranks");
+    p.kernel->fn(a, p.groups, s);
     if (deinsum_status st = check_launch("ttmc_fused")) return st;
 
     // ---- logical dims of the intermediate: slab modes, then (a, c) or (n, a)
@@ -533,7 +617,7 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         r.parts = 1;
         r.part_stride = 0;
         r.X1 = p.I[p.c];
-        r.PX = static_cast<int64_t>(p.n_ctiles) * 16 * kTkMT;
+        r.PX = static_cast<int64_t>(p.n_ctiles) * 16 * p.mt;
         r.Y1 = p.Rm[p.a];
         r.PY = TA;
     }

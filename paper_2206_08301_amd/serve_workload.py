@@ -1,0 +1,126 @@
+"""Synthetic CP-ALS serving workload and its measurement (continuous batching vs
+one launch per request), driven through the library's request server.
+
+Workload: ``n_requests`` mode-n CP-ALS updates (MTTKRP + factor update) over
+ceil(n_requests / (order * sweeps)) resident order-3 tensors.  Each dim is
+uniform on [32, 512], the rank uniform on {8, 16, 32, 64}, FP32 with
+probability 0.7 else FP64; X ~ U[-1, 1] from the counter generator, factors
+N(0, 1).  Request q goes to tensor q mod T and cycles through that tensor's
+modes.  Arrivals are a Poisson process of rate ``rate`` per second.
+
+Latency = host-observed completion - scheduled arrival.  Two runs per server
+mode: open loop at the Poisson arrivals (p50/p99 latency, median of
+``repeats``), and saturation with every request released at t = 0
+(throughput in requests/s and algorithmic GB/s).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import synth as _synth
+
+ARRIVAL_SEED = 2206083599
+TENSOR_SEED = 2206090000
+RANKS = (8, 16, 32, 64)
+
+
+def make_workload(n_requests=4096, rate=2000.0, sweeps=10, order=3, lo=32, hi=512, fp32_share=0.7,
+                  seed=ARRIVAL_SEED):
+    rng = np.random.default_rng(seed)
+    n_tensors = math.ceil(n_requests / (order * sweeps))
+    tensors = []
+    for t in range(n_tensors):
+        dims = tuple(int(d) for d in rng.integers(lo, hi + 1, order))
+        R = int(rng.choice(RANKS))
+        prec = "fp32" if rng.random() < fp32_share else "fp64"
+        tensors.append({"dims": dims, "R": R, "prec": prec, "seed": TENSOR_SEED + 10 * t})
+    q = np.arange(n_requests)
+    tensor_of = (q % n_tensors).astype(np.int32)
+    mode_of = ((q // n_tensors) % order).astype(np.int32)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    return {"tensors": tensors, "tensor_of": tensor_of, "mode_of": mode_of, "arrivals": arrivals,
+            "rate": rate, "order": order}
+
+
+def materialise(dn, wl, device="cuda"):
+    """Device X and initial factors for every tensor (X from the counter generator)."""
+    state = []
+    for t in wl["tensors"]:
+        dt = torch.float64 if t["prec"] == "fp64" else torch.float32
+        X = torch.empty(t["dims"], dtype=dt, device=device)
+        dn.synth_fill(X, t["seed"])
+        U0 = [torch.from_numpy(_synth.normal_factor(t["seed"] + 1 + m, d, t["R"])).to(dt).to(device)
+              for m, d in enumerate(t["dims"])]
+        state.append({"X": X, "U0": U0, "U": [u.clone() for u in U0], "prec": t["prec"]})
+    torch.cuda.synchronize()
+    return state
+
+
+def request_bytes(wl):
+    """Algorithmic HBM bytes of each request's MTTKRP: X once, the other factors, the output."""
+    out = np.zeros(len(wl["tensor_of"]))
+    for q, (t, n) in enumerate(zip(wl["tensor_of"], wl["mode_of"])):
+        spec = wl["tensors"][t]
+        e = 8 if spec["prec"] == "fp64" else 4
+        vol = int(np.prod(spec["dims"]))
+        fac = sum(spec["dims"][m] for m in range(len(spec["dims"])) if m != n) * spec["R"] * e
+        out[q] = vol * e + fac + spec["dims"][n] * spec["R"] * 8
+    return out
+
+
+def serve_once(dn, wl, state, batched, open_loop, max_jobs=256, epochs_in_flight=2):
+    for s in state:
+        for u, u0 in zip(s["U"], s["U0"]):
+            u.copy_(u0)
+    torch.cuda.synchronize()
+    n = len(wl["tensor_of"])
+    srv = dn.Server(batched=batched, max_jobs_per_epoch=max_jobs, epochs_in_flight=epochs_in_flight,
+                    max_requests=n + 16)
+    for s in state:
+        srv.add_tensor(s["X"], s["U"], precision=s["prec"])
+    srv.start()
+    arrivals = wl["arrivals"] if open_loop else np.zeros(n)
+    srv.replay(arrivals, wl["tensor_of"], wl["mode_of"])
+    srv.drain()
+    arr, done, ep = srv.results()
+    stats = srv.stats()
+    srv.close()
+    lat = done - arr
+    span = float(done.max() - arr.min())
+    return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "max_ms": float(lat.max() * 1e3), "req_per_s": n / span, "span_s": span,
+            "epochs": stats["epochs"], "max_batch": stats["max_batch"], "completed": stats["completed"]}
+
+
+def measure(dn, n_requests=4096, rate=2000.0, sweeps=10, repeats=3, log=None):
+    wl = make_workload(n_requests=n_requests, rate=rate, sweeps=sweeps)
+    state = materialise(dn, wl)
+    total_bytes = float(request_bytes(wl).sum())
+    out = {"workload": f"{n_requests} CP-ALS requests (MTTKRP + factor update), {len(wl['tensors'])} order-3 "
+                       f"tensors, dims U[32,512], R in {{8,16,32,64}}, 70% FP32, Poisson {rate:g}/s, "
+                       f"{sweeps} sweeps",
+           "resident_gb": sum(s["X"].numel() * s["X"].element_size() for s in state) / 1e9}
+    for name, batched in (("batched", True), ("per_request", False)):
+        runs = []
+        for r in range(repeats):
+            runs.append(serve_once(dn, wl, state, batched, open_loop=True))
+            if log:
+                log(f"serving {name} open-loop run {r}: p50 {runs[-1]['p50_ms']:.3f} ms "
+                    f"p99 {runs[-1]['p99_ms']:.3f} ms epochs {runs[-1]['epochs']}")
+        runs.sort(key=lambda d: d["p99_ms"])
+        ol = runs[len(runs) // 2]
+        sat = serve_once(dn, wl, state, batched, open_loop=False)
+        if log:
+            log(f"serving {name} saturation: {sat['req_per_s']:.0f} req/s, max batch {sat['max_batch']}")
+        out[name] = {"p50_ms": ol["p50_ms"], "p99_ms": ol["p99_ms"], "open_loop_req_per_s": ol["req_per_s"],
+                     "epochs": ol["epochs"],
+                     "saturation_req_per_s": sat["req_per_s"],
+                     "saturation_GBps": total_bytes / sat["span_s"] / 1e9,
+                     "saturation_p99_ms": sat["p99_ms"], "saturation_max_batch": sat["max_batch"]}
+    b, p = out["batched"], out["per_request"]
+    out["p99_ratio"] = p["p99_ms"] / b["p99_ms"]
+    out["throughput_ratio"] = b["saturation_req_per_s"] / p["saturation_req_per_s"]
+    return out

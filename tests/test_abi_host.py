@@ -140,3 +140,55 @@ def test_synth_and_convert_argument_errors(dn):
     assert lib.deinsum_synth_fill(ctypes.c_void_p(0x1000), 0, 10, 1, 0, 7, None) == -1
     assert lib.deinsum_synth_fill(None, 0, 0, 1, 0, 0, None) == 0  # nothing to do
     assert lib.deinsum_convert(ctypes.c_void_p(0x1000), 0, ctypes.c_void_p(0x1008), 1, 10, None) == -1
+
+
+# ---------------------------------------------------------------- autotuner plan cache (host side)
+KEY_1024_M0 = "s:N3:n0:p0:R24:1024x1024x1024"
+
+
+def test_tune_cache_drives_the_planner(dn, tmp_path):
+    spec, dims = "ijk,ja,ka->ia", [1024, 1024, 1024]
+    dn.tune_clear()
+    heuristic = dn.workspace_size(spec, dims, [24])
+    forced = dn.workspace_size(spec, dims, [24], split_hint=1)  # hints bypass the cache
+    assert forced < heuristic
+    f = tmp_path / "cache.txt"
+    f.write_text(f"# comment\n{KEY_1024_M0} 2 16 1 1 123.5\n")
+    dn.tune_load(f)
+    assert dn.tune_entries() == 1
+    assert dn.workspace_size(spec, dims, [24]) == forced
+    assert dn.workspace_size(spec, dims, [24], split_hint=4) != forced
+    out = tmp_path / "saved.txt"
+    dn.tune_save(out)
+    assert f"{KEY_1024_M0} 2 16 1 1 123.5" in out.read_text()
+    dn.tune_clear()
+    assert dn.tune_entries() == 0
+    assert dn.workspace_size(spec, dims, [24]) == heuristic
+
+
+def test_tune_cache_stale_variant_falls_back(dn, tmp_path):
+    spec, dims = "ijk,ja,ka->ia", [1024, 1024, 1024]
+    dn.tune_clear()
+    heuristic = dn.workspace_size(spec, dims, [24])
+    f = tmp_path / "stale.txt"
+    f.write_text(f"{KEY_1024_M0} 2 99 1 1 1.0\n")
+    dn.tune_load(f)
+    assert dn.workspace_size(spec, dims, [24]) == heuristic
+    dn.tune_clear()
+
+
+def test_tune_rejects_bad_input(dn, tmp_path):
+    f = tmp_path / "bad.txt"
+    f.write_text("s:N3:n0:p0:R24:8x8x8 two 16 1 1 1.0\n")
+    with pytest.raises(dn.DeinsumError) as e:
+        dn.tune_load(f)
+    assert e.value.status == -2
+    with pytest.raises(dn.DeinsumError):
+        dn.tune_load(tmp_path / "missing.txt")
+    lib = dn._lib.load()
+    s = dn.parse("ijk,ja,ka->ia")
+    d = (ctypes.c_int64 * 3)(8, 8, 8)
+    ptrs = (ctypes.c_void_p * 2)(None, None)
+    for fn in (lib.deinsum_tune_mttkrp, lib.deinsum_tune_batch_mttkrp):
+        assert fn(ctypes.byref(s), d, 4, None, ptrs, None, None, 0, None, None) == -1  # reps = 0
+    dn.tune_clear()

@@ -93,12 +93,10 @@ def test_operand_order_is_respected(dn, oracle_mod):
     assert nrel(got, ref) <= 1e-12
 
 
-FORMS_LAST_OK = {"fp64", "fp32"}
-
-
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "bf16x3"])
-@pytest.mark.parametrize("dims", [(37, 64, 96), (16, 21, 130), (6, 5, 7, 48), (64, 64, 64)])
-def test_integer_inputs_exact_every_form(dn, synth, oracle_mod, precision, dims):
+@pytest.mark.parametrize("dims,R", [((37, 64, 96), 20), ((16, 21, 130), 20), ((6, 5, 7, 48), 20), ((64, 64, 64), 20),
+                                    ((40, 33, 80), 50), ((24, 96, 64), 64)])
+def test_integer_inputs_exact_every_form(dn, synth, oracle_mod, precision, dims, R):
     """Entries in {-2..2}: every partial sum is an integer below 2^24, exact in all forms."""
     rng = np.random.default_rng(len(dims) * 7 + dims[0])
     X = synth.x_tensor(77, dims, "int5")
@@ -106,10 +104,8 @@ def test_integer_inputs_exact_every_form(dn, synth, oracle_mod, precision, dims)
     udt = torch.float64 if precision == "fp64" else torch.float32
     Xd = to_dev(X, xdt)
     for n in range(len(dims)):
-        if n == len(dims) - 1 and precision not in FORMS_LAST_OK:
-            continue
         flush(f"int {precision} dims={dims} n={n}")
-        U = [None if m == n else rng.integers(-2, 3, (d, 20)).astype(np.float64) for m, d in enumerate(dims)]
+        U = [None if m == n else rng.integers(-2, 3, (d, R)).astype(np.float64) for m, d in enumerate(dims)]
         ref = oracle_mod.mttkrp(X, U, n)
         got = run(dn, mttkrp_spec(len(dims), n), Xd, [to_dev(u, udt) for u in operands(U, n)],
                   precision=precision, out_dtype=torch.float64)
@@ -136,8 +132,6 @@ def test_mixed_precision_error(dn, synth, oracle_mod, precision, tol):
     xdt = torch.bfloat16 if precision == "bf16" else torch.float32
     Xd = to_dev(X, torch.float32) if xdt == torch.float32 else to_dev(X, torch.float32).to(torch.bfloat16)
     for n in range(3):
-        if n == 2 and precision not in FORMS_LAST_OK:
-            continue
         U = factors_for(rng, dims, R, n)
         ref = oracle_mod.mttkrp(X, U, n)
         got = run(dn, SPEC3[n], Xd, [to_dev(u, torch.float32) for u in operands(U, n)], precision=precision)

@@ -1,0 +1,188 @@
+"""GPU tests of the CP-ALS request server (deinsum_server_*): results against the
+oracle's ALS update, per-tensor ordering, and that a tensor's results are the
+same alone and in any mix of concurrent requests."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import flush, nrel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2206_08301_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    m._lib.load()
+    return m
+
+
+def host_tensor(seed, dims, R, prec):
+    """Seeded X ~ U[-1,1] and N(0,1) factors, rounded to the storage precision."""
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, dims)
+    U = [rng.standard_normal((d, R)) for d in dims]
+    if prec == "fp32":
+        X = X.astype(np.float32).astype(np.float64)
+        U = [u.astype(np.float32).astype(np.float64) for u in U]
+    return X, U
+
+
+def device_copy(X, U, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    return (torch.from_numpy(X).to(dt).cuda().contiguous(),
+            [torch.from_numpy(u).to(dt).cuda().contiguous() for u in U])
+
+
+def oracle_sweeps(oracle_mod, X, U, modes):
+    U = [u.copy() for u in U]
+    for n in modes:
+        U[n] = oracle_mod.als_update(X, [None if m == n else U[m] for m in range(X.ndim)], n)
+    return U
+
+
+def run_server(dn, tensors, requests, batched=True, arrivals=None, max_jobs=64):
+    """tensors: list of (X, U, prec) host arrays; requests: list of (tensor, mode).
+    Returns the device factors after serving, the server's results and stats."""
+    srv = dn.Server(batched=batched, max_jobs_per_epoch=max_jobs, max_requests=len(requests) + 8)
+    dev = []
+    for X, U, prec in tensors:
+        Xd, Ud = device_copy(X, U, prec)
+        srv.add_tensor(Xd, Ud, precision=prec)
+        dev.append(Ud)
+    srv.start()
+    if arrivals is None:
+        for t, n in requests:
+            srv.submit(t, n)
+    else:
+        srv.replay(arrivals, [t for t, _ in requests], [n for _, n in requests])
+    srv.drain()
+    arr, done, ep = srv.results()
+    stats = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    return [[u.double().cpu().numpy() for u in Ud] for Ud in dev], (arr, done, ep), stats
+
+
+def round_robin(order_of, sweeps):
+    """Requests assigned round-robin over tensors, each tensor cycling through its modes."""
+    reqs = []
+    for s in range(sweeps):
+        for n in range(max(order_of)):
+            for t, N in enumerate(order_of):
+                if n < N:
+                    reqs.append((t, n))
+    return reqs
+
+
+SPECS_FP64 = [((40, 33, 50), 8), ((64, 48, 36), 16), ((90, 100, 120), 64), ((20, 18, 16, 22), 6)]
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_server_matches_oracle_fp64(dn, oracle_mod, batched):
+    tensors = []
+    for k, (dims, R) in enumerate(SPECS_FP64):
+        X, U = host_tensor(500 + k, dims, R, "fp64")
+        tensors.append((X, U, "fp64"))
+    reqs = round_robin([len(d) for d, _ in SPECS_FP64], 2)
+    flush(f"server fp64 batched={batched}: {len(reqs)} requests")
+    got, (arr, done, ep), stats = run_server(dn, tensors, reqs, batched=batched)
+    assert stats["completed"] == len(reqs)
+    for k, (X, U, _) in enumerate(tensors):
+        modes = [n for t, n in reqs if t == k]
+        ref = oracle_sweeps(oracle_mod, X, U, modes)
+        for m in range(X.ndim):
+            err = nrel(got[k][m], ref[m])
+            flush(f"  tensor {k} dims={X.shape} mode {m}: {err:.2e}")
+            assert err <= 1e-10
+
+
+def test_server_matches_oracle_fp32(dn, oracle_mod):
+    specs = [((48, 40, 56), 8), ((64, 60, 50), 32)]
+    tensors = [(*host_tensor(600 + k, d, R, "fp32"), "fp32") for k, (d, R) in enumerate(specs)]
+    reqs = round_robin([3, 3], 1)
+    got, _, stats = run_server(dn, tensors, reqs)
+    assert stats["completed"] == len(reqs)
+    for k, (X, U, _) in enumerate(tensors):
+        ref = oracle_sweeps(oracle_mod, X, U, [0, 1, 2])
+        for m in range(3):
+            err = nrel(got[k][m], ref[m])
+            flush(f"  fp32 tensor {k} mode {m}: {err:.2e}")
+            assert err <= 2e-4
+
+
+def c5_like(seed, count):
+    """Uneven tensors as in the serving workload, scaled down: R in {8,16,32,64}, each dim
+    between R+16 and R+80 (so the normal equations stay well conditioned), 70% FP32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        R = int(rng.choice([8, 16, 32, 64]))
+        dims = tuple(int(d) for d in rng.integers(max(32, R + 16), R + 81, 3))
+        prec = "fp32" if rng.random() < 0.7 else "fp64"
+        X, U = host_tensor(seed * 100 + k, dims, R, prec)
+        out.append((X, U, prec))
+    return out
+
+
+def test_server_alone_vs_mix_bitwise(dn):
+    """Each tensor's factors after its requests are bitwise the same served alone, in the
+    full mix submitted at once, and in the mix arriving over time (different epochs)."""
+    tensors = c5_like(7, 10)
+    reqs = round_robin([3] * len(tensors), 2)
+    mix, (_, _, ep_mix), st_mix = run_server(dn, tensors, reqs)
+    arrivals = np.arange(len(reqs)) * 2e-4
+    spread, (_, _, ep_sp), st_sp = run_server(dn, tensors, reqs, arrivals=arrivals)
+    flush(f"mix epochs={st_mix['epochs']} max_batch={st_mix['max_batch']}; "
+          f"spread epochs={st_sp['epochs']} max_batch={st_sp['max_batch']}")
+    assert st_mix["max_batch"] > 1
+    for k in (0, 3, 9):
+        alone, _, _ = run_server(dn, [tensors[k]], [(0, n) for t, n in reqs if t == k])
+        for m in range(3):
+            assert np.array_equal(alone[0][m], mix[k][m]), (k, m)
+    for k in range(len(tensors)):
+        for m in range(3):
+            assert np.array_equal(spread[k][m], mix[k][m]), (k, m)
+
+
+def test_server_batched_matches_per_request(dn):
+    tensors = c5_like(8, 6)
+    reqs = round_robin([3] * len(tensors), 1)
+    a, _, _ = run_server(dn, tensors, reqs, batched=True)
+    b, _, _ = run_server(dn, tensors, reqs, batched=False)
+    for k, (_, _, prec) in enumerate(tensors):
+        tol = 1e-10 if prec == "fp64" else 1e-4
+        for m in range(3):
+            assert nrel(a[k][m], b[k][m]) <= tol, (k, m, prec)
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_server_fifo_per_tensor(dn, batched):
+    tensors = c5_like(9, 5)
+    reqs = round_robin([3] * len(tensors), 2)
+    arrivals = np.arange(len(reqs)) * 1e-4
+    _, (arr, done, ep), stats = run_server(dn, tensors, reqs, batched=batched, arrivals=arrivals)
+    assert stats["completed"] == len(reqs)
+    assert np.all(done >= arr)
+    for k in range(len(tensors)):
+        idx = [i for i, (t, _) in enumerate(reqs) if t == k]
+        assert np.all(np.diff(ep[idx]) > 0), k
+        assert np.all(np.diff(done[idx]) >= 0), k
+
+
+def test_server_rejects_bad_input(dn):
+    srv = dn.Server()
+    X = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    U = [torch.zeros((8, 65), dtype=torch.float64, device="cuda") for _ in range(3)]
+    with pytest.raises(dn.DeinsumError):
+        srv.add_tensor(X, U)
+    U = [torch.ones((8, 4), dtype=torch.float64, device="cuda") for _ in range(3)]
+    t = srv.add_tensor(X, U)
+    srv.start()
+    with pytest.raises(dn.DeinsumError):
+        srv.submit(t, 3)
+    with pytest.raises(dn.DeinsumError):
+        srv.submit(t + 1, 0)
+    srv.drain()
+    srv.close()

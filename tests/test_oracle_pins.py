@@ -6,6 +6,9 @@ not by re-running the oracle's own formula.
   * rank-1 and Kruskal closed forms, order-2 = GEMM, linearity
   * cross-mode invariant, MTTKRP vs TTMc relation, TTMc special cases
   * exact integer arithmetic, and the long-double bound on the oracle's own error
+  * CP-ALS update: exact recovery of a Kruskal tensor's factor, and the same
+    least-squares problem solved by numpy.linalg.lstsq on the explicit
+    Khatri-Rao matrix (no normal equations)
 """
 import itertools
 import json
@@ -329,3 +332,46 @@ def test_slab_matches_full_tensor(synth):
         for i in (0, dims[mode] - 1):
             slab = synth.x_slab(99, dims, mode, i)
             assert np.array_equal(slab, np.take(full, [i], axis=mode))
+
+
+# ---------------------------------------------------------------- CP-ALS update
+def _unit_columns(A):
+    return A / np.sqrt(np.sum(A * A, axis=0))
+
+
+def _khatri_rao_rows(U, skip):
+    """Rows of the Khatri-Rao product of the factors other than ``skip``, indexed by the
+    other modes' indices flattened in increasing mode order (C order)."""
+    mats = [U[m] for m in range(len(U)) if m != skip]
+    K = mats[0]
+    for B in mats[1:]:
+        K = (K[:, None, :] * B[None, :, :]).reshape(-1, K.shape[1])
+    return K
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_als_update_recovers_kruskal_factor(oracle_mod, n):
+    """X = [[A, B, C]] exactly: the update with the true other factors returns the true
+    factor of mode n with unit columns."""
+    rng = np.random.default_rng(40 + n)
+    dims, R = (9, 8, 10), 4
+    F = [rng.standard_normal((d, R)) for d in dims]
+    X = np.einsum("ir,jr,kr->ijk", *F)
+    U = [None if m == n else F[m] for m in range(3)]
+    got = oracle_mod.als_update(X, U, n)
+    assert nrel(got, _unit_columns(F[n])) <= 1e-10
+
+
+@pytest.mark.parametrize("dims,n", [((6, 5, 7), 0), ((6, 5, 7), 2), ((4, 3, 5, 4), 1), ((4, 3, 5, 4), 3)])
+def test_als_update_matches_lstsq(oracle_mod, dims, n):
+    """General X: the update solves min ||X_(n) - A KR^T||; lstsq on the explicit KR matrix."""
+    rng = np.random.default_rng(sum(dims) + n)
+    R = 3
+    X = rng.standard_normal(dims)
+    U = [rng.standard_normal((d, R)) for d in dims]
+    Xn = np.moveaxis(X, n, 0).reshape(dims[n], -1)
+    KR = _khatri_rao_rows(U, n)
+    A = np.linalg.lstsq(KR, Xn.T, rcond=None)[0].T
+    got = oracle_mod.als_update(X, [None if m == n else U[m] for m in range(len(dims))], n)
+    assert nrel(got, _unit_columns(A)) <= 1e-10
+    assert np.allclose(np.sqrt(np.sum(got * got, axis=0)), 1.0, rtol=0, atol=1e-14)
