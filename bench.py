@@ -36,7 +36,10 @@ def parse_args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="skip the mixed-precision and TTMc fields")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="profiling: run just one form (fp64|fp32|bf16|bf16x3|ttmc)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the CP-ALS serving measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="profiling: run one plain 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--only", default="", help="profiling: run just one form (fp64|fp32|bf16|bf16x3|ttmc|serving)")
     return ap.parse_args()
 
 
@@ -70,6 +73,13 @@ def main():
     stream = torch.cuda.current_stream()
     seed = synth.config_seed(2, 0)
 
+    if args.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] generating X {DIMS} fp64 on the device", file=sys.stderr, flush=True)
     X = torch.empty(DIMS, dtype=torch.float64, device=dev)
     dn.synth_fill(X, seed)
@@ -234,24 +244,39 @@ def main():
                               "GFLOP/s": round(f / (t / 1e3) / 1e9, 1), "max_rel_err_sampled": max(errs)}
     result["checks"] = checks
 
-    # ---- CPU oracle on a bounded sample of the same workload (mode 0, some output rows)
+    # ---- CP-ALS serving: continuous batching vs one launch per request (extras)
+    if not args.no_extras and not args.no_serving and (not args.only or args.only == "serving"):
+        from paper_2206_08301_amd import serve_workload
+        del X
+        torch.cuda.empty_cache()
+        result["serving"] = serve_workload.measure(
+            dn, repeats=int(os.environ.get("BENCH_SERVE_REPEATS", "3")),
+            log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
+
+    # ---- CPU oracle on a bounded sample of the same workload: all three modes over
+    # 64-row slabs of a 1024^3 X until about BENCH_CPU_SECONDS of oracle time.
     if not args.no_cpu:
-        rows = int(os.environ.get("BENCH_CPU_ROWS", "512"))
-        Un = [None, U[1], U[2]]
-        t = 0.0
-        for r0 in range(0, rows, 64):  # generate 64 output rows' slab at a time; time only the oracle
-            r1 = min(rows, r0 + 64)
-            X_sample = synth.x_range(seed, r0 * 1024 * 1024, (r1 - r0) * 1024 * 1024).reshape(r1 - r0, 1024, 1024)
-            t0 = time.perf_counter()
-            oracle.mttkrp(X_sample, Un, 0)
-            t += time.perf_counter() - t0
-            del X_sample
-        f = alg_counts((rows, 1024, 1024), R, 0, 8)[1]
+        budget = float(os.environ.get("BENCH_CPU_SECONDS", "12"))
+        rng = np.random.default_rng(2206083010)
+        t, rows, f = 0.0, 0, 0
+        while rows < DIMS[0] and t < budget:
+            # Same shape and distribution as the GPU's X; drawn with numpy's PCG64 because the
+            # counter generator runs at a few million values per second in numpy.
+            Xs = rng.uniform(-1.0, 1.0, (64, DIMS[1], DIMS[2]))
+            for n in range(3):
+                Un = [None if m == n else U[m][:64] if m == 0 else U[m] for m in range(3)]
+                t0 = time.perf_counter()
+                oracle.mttkrp(Xs, Un, n)
+                t += time.perf_counter() - t0
+                f += alg_counts((64, DIMS[1], DIMS[2]), R, n, 8)[1]
+            rows += 64
+            del Xs
         result["cpu_baseline"] = {"value": round(f / t / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
                                   "kind": "oracle",
-                                  "sample": f"MTTKRP mode 0 on {rows} of the 1024 output rows of the same X and "
-                                            f"factors ({rows}x1024x1024 of X in host RAM, 64 rows at a time, generation excluded), "
-                                            f"{t:.1f} s; flops counted as for the GPU"}
+                                  "sample": f"MTTKRP modes 0, 1 and 2 of the 1024^3 R=24 FP64 step restricted to "
+                                            f"{rows} of the 1024 mode-0 slices (64 at a time, X uniform [-1,1) in "
+                                            f"host RAM, generation excluded), {t:.1f} s of oracle time; flops "
+                                            f"counted as for the GPU"}
     print(json.dumps(result), flush=True)
 
 
