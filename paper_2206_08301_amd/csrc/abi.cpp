@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -203,6 +205,10 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
         a.O = 1;
         for (int i = 0; i < k; ++i) a.O *= a.od.dim[i];
         a.o_per_chunk = p.o_per_chunk;
+        a.order = p.order;
+        a.xcd_remap = p.xcd;
+        a.n_chunks = p.n_chunks;
+        a.n_groups = p.groups;
         const int64_t contig = kcontig ? a.Ig : a.In;  // extent of the contiguous mode
         a.vec_ok = ((contig * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
         a.P = static_cast<double *>(ws);
@@ -239,7 +245,8 @@ void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p
     // Two-stage flops: GEMM over one mode (2 nX R) + Hadamard of each stage-1 row.
     const int g = (pb.n == pb.N - 1) ? pb.N - 2 : pb.N - 1;
     r->alg_flops = 2.0 * nx * pb.R + 2.0 * (nx / static_cast<double>(pb.dims[g])) * pb.R * std::max(1, pb.N - 2);
-    std::snprintf(r->plan_name, sizeof(r->plan_name), "%s", p.name.c_str());
+    std::snprintf(r->plan_name, sizeof(r->plan_name), "%s c%lld o%d x%d", p.name.c_str(),
+                  static_cast<long long>(p.n_chunks), p.order, p.xcd);
 }
 
 // Median of the event-timed durations of `reps` back-to-back runs (one warm-up first).
@@ -380,6 +387,8 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
     c.X = X;
     c.M = M;
     const int layout = c.plan.family == PLAN_MTTKRP_KCONTIG ? L_KCONTIG : L_MCONTIG;
+    const char *vb = std::getenv("DEINSUM_TUNE_VERBOSE");
+    const bool verbose = vb && vb[0] && vb[0] != '0';
     int count = 0;
     const StreamKernelInfo *table = stream_kernels(&count);
     double best_us = -1;
@@ -392,23 +401,31 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
         if (plan_geometry(c.pb, &k, 0, &p0) != DEINSUM_OK) continue;
         int splits[8];
         const int ns = tune_splits(p0.n_chunks, p0.O, splits);
-        for (int si = 0; si < ns; ++si) {
-            MttkrpCall cc = c;
-            if (deinsum_status st = plan_geometry(c.pb, &k, splits[si], &cc.plan)) return st;
-            void *ws = nullptr;
-            if (deinsum_status st = pool_get(cc.plan.workspace, &ws)) return st;
-            double us = 0;
-            if (deinsum_status st = time_median([&] { return run_mttkrp(cc, ws, s); }, reps, s, &us)) return st;
-            if (best_us < 0 || us < best_us) {
-                best_us = us;
-                best_plan = cc.plan;
-                choice.nt = k.nt;
-                choice.ni = k.ni;
-                choice.mt = k.mt;
-                choice.split = splits[si];
-                choice.us = us;
+        for (int si = 0; si < ns; ++si)
+            for (int variant = 0; variant < 4; ++variant) {
+                MttkrpCall cc = c;
+                if (deinsum_status st = plan_geometry(c.pb, &k, splits[si], &cc.plan)) return st;
+                cc.plan.order = variant & 1;
+                cc.plan.xcd = variant >> 1;
+                void *ws = nullptr;
+                if (deinsum_status st = pool_get(cc.plan.workspace, &ws)) return st;
+                double us = 0;
+                if (deinsum_status st = time_median([&] { return run_mttkrp(cc, ws, s); }, reps, s, &us)) return st;
+                if (verbose)
+                    std::fprintf(stderr, "[deinsum tune] %s split %d order %d xcd %d: %.1f us\n", cc.plan.name.c_str(),
+                                 splits[si], cc.plan.order, cc.plan.xcd, us);
+                if (best_us < 0 || us < best_us) {
+                    best_us = us;
+                    best_plan = cc.plan;
+                    choice.nt = k.nt;
+                    choice.ni = k.ni;
+                    choice.mt = k.mt;
+                    choice.split = splits[si];
+                    choice.order = cc.plan.order;
+                    choice.xcd = cc.plan.xcd;
+                    choice.us = us;
+                }
             }
-        }
     }
     if (best_us < 0) return fail(DEINSUM_ERR_UNSUPPORTED, "tune: no candidate plan");
     tune_store(tune_key(TUNE_STREAM, c.pb), choice);

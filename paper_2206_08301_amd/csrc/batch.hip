@@ -139,7 +139,15 @@ __global__ void __launch_bounds__(256) batch_reduce_kernel(const BatchHeader *h,
         const double *p = j.a.P + t * tile_elems + ir * j.cols_pad + col;
         const int64_t part_stride = j.n_tiles * tile_elems;
         double s = 0.0;
-        for (int64_t q = 0; q < j.parts; ++q) s += p[q * part_stride];
+        int64_t q = 0;
+        for (; q + 8 <= j.parts; q += 8) {  // index order, eight loads in flight
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[(q + u) * part_stride];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; q < j.parts; ++q) s += p[q * part_stride];
         if (j.out_dtype == DEINSUM_F64) static_cast<double *>(j.out)[i * j.ldo + col] = s;
         else static_cast<float *>(j.out)[i * j.ldo + col] = static_cast<float>(s);
     }
@@ -391,6 +399,10 @@ deinsum_status batch_add(deinsum_batch *b, const deinsum_spec *spec, const int64
         a.wk = p.wk;
         a.O = p.O;
         a.o_per_chunk = p.o_per_chunk;
+        a.order = 0;  // units come from the work queue in index order
+        a.xcd_remap = 0;
+        a.n_chunks = p.n_chunks;
+        a.n_groups = p.groups;
         const int64_t contig = kcontig ? a.Ig : a.In;
         a.vec_ok = ((contig * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
         a.ldw = cols_pad;

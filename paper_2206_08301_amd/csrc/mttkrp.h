@@ -16,7 +16,12 @@ enum StreamLayout {
 
 // One launch processes one column block of the output.
 //   grid  = n_chunks * n_tiles * n_kgroups workgroups of `waves` waves;
-//   block b: kgroup = b % n_kgroups, tile = (b / n_kgroups) % n_tiles, chunk = rest;
+//   block b -> unit u: b itself, or with xcd_remap the b-th workgroup dispatched
+//     to XCD b % 8 takes the next unit of that XCD's contiguous range of units
+//     (workgroups are handed to the 8 XCDs round-robin), so each XCD's L2 and
+//     TLB see one region of X;
+//   unit u: kgroup = u % n_kgroups, then (order 0) tile = (u / n_kgroups) % n_tiles,
+//     chunk = rest, or (order 1) chunk = (u / n_kgroups) % n_chunks, tile = rest;
 //   wave w: slice kgroup*wk + w % wk of mode g, outer sub-range w / wk of the chunk.
 struct StreamArgs {
     const void *X;
@@ -28,6 +33,10 @@ struct StreamArgs {
     int64_t stride_g;    // X stride of mode g (M-contiguous layout)
     int ncols;           // valid columns in this block (<= 16 * NT)
     int n_tiles;         // free-mode tiles (16 or 16*MT indices)
+    int order;           // unit order: 0 tile-major within a chunk, 1 chunk-major within a tile
+    int xcd_remap;       // 1: contiguous unit range per XCD (needs n_groups)
+    int64_t n_chunks;    // outer chunks
+    int64_t n_groups;    // workgroups of this launch
     int n_kgroups;       // groups of wk slices of mode g
     int wk;              // slices per workgroup
     int64_t O, o_per_chunk;

@@ -77,8 +77,17 @@ reduce_partials_kernel(const double *__restrict__ P, int64_t nparts, int64_t n_t
     const int64_t tile_elems = static_cast<int64_t>(tile_rows) * cols_pad;
     const double *p = P + t * tile_elems + ir * cols_pad + col;
     const int64_t part_stride = n_tiles * tile_elems;
+    // Index order; eight loads in flight per step.
     double s = 0.0;
-    for (int64_t q = 0; q < nparts; ++q) s += p[q * part_stride];
+    int64_t q = 0;
+    for (; q + 8 <= nparts; q += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(q + u) * part_stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; q < nparts; ++q) s += p[q * part_stride];
     out[i * ldo + col] = from_f64<OT>(s);
 }
 

@@ -2,7 +2,7 @@
 //
 // The tile is the compiled variant whose slice of mode g pads that mode the
 // least (ties: the first, largest variant of the table).  The split targets
-// enough workgroups to cover the 256 compute units several times over while
+// enough workgroups to cover the 256 compute units a few times over while
 // keeping every wave's walk over the outer indices long enough to amortise
 // loading its factor slice and filling its prefetch ring, and the partial
 // workspace a small fraction of X.
@@ -19,7 +19,7 @@ namespace deinsum {
 
 namespace {
 
-constexpr int64_t kTargetGroups = 4096;  // 16 per compute unit
+constexpr int64_t kTargetGroups = 2048;  // 8 per compute unit
 constexpr int64_t kMinSteps = 8;         // outer steps per wave
 constexpr int kWaves = 4;
 
@@ -69,6 +69,10 @@ deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *ke
     p.groups = p.n_chunks * per_chunk;
     p.parts = p.n_chunks * p.n_kgroups;
     p.O = O;
+    // Chunk-major units keep the workgroups in flight on few rows of X (fewer
+    // pages per XCD); the M-contiguous walk also gains from the XCD remap.
+    p.order = 1;
+    p.xcd = (layout == L_MCONTIG) ? 1 : 0;
     const size_t part_bytes = static_cast<size_t>(p.parts * p.n_tiles) * p.tile_rows * 16 * p.nt * sizeof(double);
     p.w_offset = (part_bytes + 255) / 256 * 256;
     p.workspace = p.w_offset + static_cast<size_t>(O) * 16 * p.nt * sizeof(double);
@@ -96,8 +100,12 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
     if (plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc)) {
         for (int i = 0; i < count; ++i) {
             const StreamKernelInfo &k = table[i];
-            if (k.prec == pb.prec && k.layout == layout && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt)
-                return plan_geometry(pb, &k, tc.split, out);
+            if (k.prec == pb.prec && k.layout == layout && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt) {
+                if (deinsum_status st = plan_geometry(pb, &k, tc.split, out)) return st;
+                out->order = tc.order;
+                out->xcd = tc.xcd;
+                return DEINSUM_OK;
+            }
         }
         // An entry for a variant that is no longer compiled falls back to the heuristic.
     }

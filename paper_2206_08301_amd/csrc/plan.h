@@ -24,6 +24,8 @@ struct MttkrpPlan {
     int tile_rows = 16;
     int64_t n_tiles = 0, n_kgroups = 1, n_chunks = 1;
     int64_t o_per_chunk = 1;
+    int order = 0;            // unit order (StreamArgs::order)
+    int xcd = 0;              // XCD-aware unit remap (StreamArgs::xcd_remap)
     int64_t col_blocks = 1;
     int64_t groups = 0;       // workgroups per column block
     int64_t parts = 0;        // partial tiles per output tile

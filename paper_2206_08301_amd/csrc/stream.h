@@ -202,9 +202,21 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave index: uniform in the wave
     const int nwaves = blockDim.x >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const int kgroup = static_cast<int>(b % a.n_kgroups);
-    const int tile = static_cast<int>((b / a.n_kgroups) % a.n_tiles);
-    const int64_t chunk = b / (static_cast<int64_t>(a.n_kgroups) * a.n_tiles);
+    int64_t u = b;
+    if (a.xcd_remap) {
+        const int64_t q = a.n_groups >> 3, r = a.n_groups & 7, x = b & 7;
+        u = x * q + (x < r ? x : r) + (b >> 3);
+    }
+    const int kgroup = static_cast<int>(u % a.n_kgroups);
+    int tile;
+    int64_t chunk;
+    if (a.order == 0) {
+        tile = static_cast<int>((u / a.n_kgroups) % a.n_tiles);
+        chunk = u / (static_cast<int64_t>(a.n_kgroups) * a.n_tiles);
+    } else {
+        chunk = (u / a.n_kgroups) % a.n_chunks;
+        tile = static_cast<int>(u / (a.n_kgroups * a.n_chunks));
+    }
     const int ks = kgroup * a.wk + (w % a.wk);
     const int osub = w / a.wk;
     const int64_t s0 = static_cast<int64_t>(ks) * TL::SLICE;  // slice start in mode g

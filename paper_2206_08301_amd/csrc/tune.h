@@ -13,7 +13,8 @@ enum TunePath { TUNE_STREAM = 0, TUNE_BATCH = 1 };
 struct TuneChoice {
     int nt = 0, ni = 0, mt = 0;
     int split = 0;
-    double us = 0;  // measured median time of the winner
+    int order = 0, xcd = 0;  // unit order and XCD remap of the per-call kernel
+    double us = 0;           // measured median time of the winner
 };
 
 std::string tune_key(int path, const MttkrpProblem &pb);
