@@ -14,8 +14,10 @@ on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 import time
@@ -42,6 +44,30 @@ def parse_args():
                     help="profiling: run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     ap.add_argument("--only", default="", help="profiling: run just one form (fp64|fp32|bf16|bf16x3|ttmc|serving)")
     return ap.parse_args()
+
+
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mttkrp_1024cubed_R24_fp64_hbm_traffic.txt")
+KERNEL_SOURCES = ("paper_2206_08301_amd/csrc/stream.h", "paper_2206_08301_amd/csrc/mttkrp.hip",
+                  "paper_2206_08301_amd/csrc/mttkrp.h", "paper_2206_08301_amd/csrc/kernels.h")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed PMC summary (FETCH_SIZE
+    and WRITE_SIZE, copy-calibrated), or None once the kernel sources differ from the ones
+    the counters were taken with."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    mb = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    mh = re.search(r"^kernel_sources_sha256: ([0-9a-f]{64})", text, re.M)
+    if not (mb and mh):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return int(mb.group(1)) if h.hexdigest() == mh.group(1) else None
 
 
 def alg_counts(dims, R, n, xbytes):
@@ -154,7 +180,7 @@ def main():
         dom_ms = (med[0] + med[1]) / 2
         dom_gbs = bytes_mode[0] / (dom_ms / 1e3) / 1e9
         result["roofline"] = {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                              "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                               "kernel": "mttkrp_kcontig (FP64, modes 0 and 1; duration includes the fixed-order reduce)"}
         result["modes"] = {str(n): {"ms": round(med[n], 4), "GB/s": round(gbs[n], 1),
                                      "frac_hbm": round(gbs[n] / HBM_PEAK_GBS, 4),
