@@ -117,9 +117,11 @@ typedef struct deinsum_opts {
     int32_t out_dtype;        /* DEINSUM_F64 or DEINSUM_F32 (F64 required for FP64)  */
     void *workspace;          /* optional caller device buffer; NULL = library pool  */
     size_t workspace_bytes;   /* its size                                            */
-    int32_t plan_hint;        /* 0 = autotuned plan if cached, else the heuristic;
-                                 1 / 2 = heuristic, and the free mode must be
-                                 < N-1 / = N-1 (tests)                               */
+    int32_t plan_hint;        /* MTTKRP: 0 = autotuned plan if cached, else the
+                                 heuristic; 1 / 2 = heuristic, and the free mode
+                                 must be < N-1 / = N-1 (tests).
+                                 TTMc: k >= 0 picks the k-th compiled fused-kernel
+                                 variant for the ranks (0 = default; tests, tuning) */
     int32_t split_hint;       /* 0 = planner choice; else outer-chunk count          */
     deinsum_report *report;   /* optional host out-parameter                         */
 } deinsum_opts;

@@ -172,8 +172,10 @@ def tune_entries() -> int:
     return n.value
 
 
-def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None):
-    """Mode-n TTMc.  ``U`` lists the factor operands in the spec's operand order."""
+def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None,
+         variant=0):
+    """Mode-n TTMc.  ``U`` lists the factor operands in the spec's operand order; ``variant``
+    picks an alternative compiled fused kernel for the ranks (0 = default)."""
     sp = _spec(spec)
     if sp.kind != TTMC:
         raise ValueError("spec is not a TTMc")
@@ -197,7 +199,7 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
         if list(out.shape) != shape:
             raise ValueError("out has the wrong shape")
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
-    o = _opts(precision, out_dtype, workspace, 0, 0, report)
+    o = _opts(precision, out_dtype, workspace, variant, 0, report)
     with torch.cuda.device(X.device):
         _lib.check(_lib.load().deinsum_ttmc(ctypes.byref(sp), _i64(X.shape), _i64(ranks), ctypes.c_void_p(X.data_ptr()),
                                             ptrs, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), _stream(stream)))

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libdeinsum.so")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
-CFLAGS = [
+CFLAGS = [*os.environ.get("DEINSUM_EXTRA_CFLAGS", "").split(),
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas",

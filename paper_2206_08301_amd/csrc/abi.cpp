@@ -420,6 +420,7 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
                     choice.nt = k.nt;
                     choice.ni = k.ni;
                     choice.mt = k.mt;
+                    choice.xnt = k.xnt;
                     choice.split = splits[si];
                     choice.order = cc.plan.order;
                     choice.xcd = cc.plan.xcd;

@@ -340,7 +340,7 @@ deinsum_status batch_add(deinsum_batch *b, const deinsum_spec *spec, const int64
     for (int i = 0; i < vcount; ++i)
         if (vars[i].prec == pb.prec && vars[i].layout == layout && vars[i].nt == nt) vi = i;
     if (vi < 0) return fail(DEINSUM_ERR_UNSUPPORTED, "batch_add: no batched variant");
-    StreamKernelInfo k{vars[vi].prec, vars[vi].layout, vars[vi].nt, vars[vi].ni, vars[vi].mt, kBatchNBUF, nullptr};
+    StreamKernelInfo k{vars[vi].prec, vars[vi].layout, vars[vi].nt, vars[vi].ni, vars[vi].mt, kBatchNBUF, 0, nullptr};
     MttkrpPlan p;
     if (deinsum_status st = plan_geometry(pb, &k, split, &p)) return st;
     p.kernel = nullptr;  // points at the local k; not used past this call
@@ -480,7 +480,7 @@ deinsum_status deinsum_tune_batch_mttkrp(const deinsum_spec *spec, const int64_t
     for (int vi = 0; vi < vcount && st == DEINSUM_OK; ++vi) {
         const BatchVariant &v = vars[vi];
         if (v.prec != pb.prec || v.layout != layout) continue;
-        StreamKernelInfo k{v.prec, v.layout, v.nt, v.ni, v.mt, kBatchNBUF, nullptr};
+        StreamKernelInfo k{v.prec, v.layout, v.nt, v.ni, v.mt, kBatchNBUF, 0, nullptr};
         MttkrpPlan p0;
         if (plan_geometry(pb, &k, 0, &p0) != DEINSUM_OK) continue;
         int splits[8];

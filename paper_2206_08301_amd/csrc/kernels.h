@@ -29,6 +29,16 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
+// Streaming loads of X.  NTL marks them non-temporal: each element is read
+// once, and the hint keeps the re-read factor rows in the caches (a kernel
+// variant property; it pays for some layouts and costs for others).
+template <bool NTL, typename V>
+__device__ __forceinline__ V ld_stream(const V *p)
+{
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 enum PrecisionId { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2, P_BF16X3 = 3 };
 
 // Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).

@@ -48,6 +48,7 @@ struct StreamArgs {
 
 struct StreamKernelInfo {
     int prec, layout, nt, ni, mt, nbuf;
+    int xnt;  // X loads non-temporal
     void (*fn)(const StreamArgs &, int64_t grid, int waves, hipStream_t s);
 };
 

@@ -33,11 +33,11 @@ namespace {
 
 using namespace dev;
 
-template <int P, int L, int NT, int NI, int MT, int NBUF>
+template <int P, int L, int NT, int NI, int MT, int NBUF, bool XNT>
 __global__ void __launch_bounds__(256, 2) mttkrp_stream_kernel(const StreamArgs a)
 {
     __shared__ double lds[unit_lds_elems<L, NT, MT>()];
-    stream_unit<P, L, NT, NI, MT, NBUF>(a, blockIdx.x, lds);
+    stream_unit<P, L, NT, NI, MT, NBUF, XNT>(a, blockIdx.x, lds);
 }
 
 // Hadamard weights of the outer modes: W[o, col] = prod_outer U^m[i_m, col]
@@ -91,17 +91,18 @@ reduce_partials_kernel(const double *__restrict__ P, int64_t nparts, int64_t n_t
     out[i * ldo + col] = from_f64<OT>(s);
 }
 
-template <int P, int L, int NT, int NI, int MT, int NBUF>
+template <int P, int L, int NT, int NI, int MT, int NBUF, bool XNT>
 void launch_stream(const StreamArgs &a, int64_t grid, int waves, hipStream_t s)
 {
-    mttkrp_stream_kernel<P, L, NT, NI, MT, NBUF><<<static_cast<unsigned>(grid), 64 * waves, 0, s>>>(a);
+    mttkrp_stream_kernel<P, L, NT, NI, MT, NBUF, XNT><<<static_cast<unsigned>(grid), 64 * waves, 0, s>>>(a);
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------------------------
 // Kernel table: (precision, layout, column tiles, instructions per step, M tiles) -> launcher.
-#define SK(P, L, NT, NI, MT, NB) {P, L, NT, NI, MT, NB, &launch_stream<P, L, NT, NI, MT, NB>}
+#define SK(P, L, NT, NI, MT, NB) {P, L, NT, NI, MT, NB, 0, &launch_stream<P, L, NT, NI, MT, NB, false>}
+#define SKN(P, L, NT, NI, MT, NB) {P, L, NT, NI, MT, NB, 1, &launch_stream<P, L, NT, NI, MT, NB, true>}
 static const StreamKernelInfo kStreamTable[] = {
     // K-contiguous: per-lane run NI*KE elements (128 bytes by default; 80-element slices for dims of 80)
     SK(P_FP64, L_KCONTIG, 1, 16, 1, 3), SK(P_FP64, L_KCONTIG, 2, 16, 1, 3), SK(P_FP64, L_KCONTIG, 4, 8, 1, 2),
@@ -117,12 +118,18 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16X3, L_KCONTIG, 1, 3, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 3, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 3, 1, 2),
     SK(P_BF16X3, L_KCONTIG, 1, 1, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 1, 1, 3),
     // M-contiguous: NI K-steps of 4*KE rows; MT output indices per lane
+    // (FP64: non-temporal X loads first -- they keep the per-K-step factor rows cached, 1.50 -> 1.37 ms
+    //  for the 1024^3 R=24 last mode; the K-contiguous kernels lose with them and keep plain loads.)
+    SKN(P_FP64, L_MCONTIG, 1, 8, 2, 3), SKN(P_FP64, L_MCONTIG, 2, 8, 2, 2), SKN(P_FP64, L_MCONTIG, 4, 8, 1, 2),
     SK(P_FP64, L_MCONTIG, 1, 8, 2, 3), SK(P_FP64, L_MCONTIG, 2, 8, 2, 2), SK(P_FP64, L_MCONTIG, 4, 8, 1, 2),
     SK(P_FP32, L_MCONTIG, 1, 8, 4, 3), SK(P_FP32, L_MCONTIG, 2, 8, 2, 3), SK(P_FP32, L_MCONTIG, 4, 8, 2, 2),
+    SKN(P_FP32, L_MCONTIG, 1, 8, 4, 3), SKN(P_FP32, L_MCONTIG, 2, 8, 2, 3), SKN(P_FP32, L_MCONTIG, 4, 8, 2, 2),
     SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
+    SKN(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SKN(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SKN(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
 };
 #undef SK
+#undef SKN
 
 const StreamKernelInfo *stream_kernels(int *count)
 {

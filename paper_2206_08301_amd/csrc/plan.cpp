@@ -77,8 +77,8 @@ deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *ke
     p.w_offset = (part_bytes + 255) / 256 * 256;
     p.workspace = p.w_offset + static_cast<size_t>(O) * 16 * p.nt * sizeof(double);
     char buf[96];
-    std::snprintf(buf, sizeof(buf), "mttkrp_%s<p%d,nt%d,ni%d,mt%d> wk%d", layout == L_KCONTIG ? "kcontig" : "mcontig",
-                  pb.prec, p.nt, p.ni, p.mt, p.wk);
+    std::snprintf(buf, sizeof(buf), "mttkrp_%s<p%d,nt%d,ni%d,mt%d%s> wk%d", layout == L_KCONTIG ? "kcontig" : "mcontig",
+                  pb.prec, p.nt, p.ni, p.mt, kernel->xnt ? ",nt" : "", p.wk);
     p.name = buf;
     *out = p;
     return DEINSUM_OK;
@@ -100,7 +100,8 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
     if (plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc)) {
         for (int i = 0; i < count; ++i) {
             const StreamKernelInfo &k = table[i];
-            if (k.prec == pb.prec && k.layout == layout && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt) {
+            if (k.prec == pb.prec && k.layout == layout && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt &&
+                k.xnt == tc.xnt) {
                 if (deinsum_status st = plan_geometry(pb, &k, tc.split, out)) return st;
                 out->order = tc.order;
                 out->xcd = tc.xcd;

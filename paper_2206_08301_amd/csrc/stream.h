@@ -33,7 +33,7 @@ __device__ __forceinline__ double ld_u(const void *p, int64_t i, int prec)
 }
 
 // Load `n` contiguous elements; `vec` = whole 16-byte (or 8-byte) words allowed.
-template <typename T, int n>
+template <typename T, int n, bool NTL = false>
 __device__ __forceinline__ void load_contig(T *dst, const T *__restrict__ src, bool vec, int64_t valid)
 {
     if constexpr ((n * sizeof(T)) % 16 == 0) {
@@ -41,14 +41,14 @@ __device__ __forceinline__ void load_contig(T *dst, const T *__restrict__ src, b
             constexpr int NV = n * sizeof(T) / 16;
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
-                const u32x4 v = reinterpret_cast<const u32x4 *>(src)[i];
+                const u32x4 v = ld_stream<NTL>(reinterpret_cast<const u32x4 *>(src) + i);
                 __builtin_memcpy(dst + i * (16 / sizeof(T)), &v, 16);
             }
             return;
         }
     } else if constexpr (n * sizeof(T) == 8) {
         if (vec && valid >= n) {
-            const uint64_t v = *reinterpret_cast<const uint64_t *>(src);
+            const uint64_t v = ld_stream<NTL>(reinterpret_cast<const uint64_t *>(src));
             __builtin_memcpy(dst, &v, 8);
             return;
         }
@@ -123,20 +123,20 @@ struct Tile {
     }
 };
 
-template <typename T, int n>
+template <typename T, int n, bool NTL = false>
 __device__ __forceinline__ void load_vec(T *dst, const T *__restrict__ src)
 {
     static_assert((n * sizeof(T)) % 8 == 0, "vector runs are whole 8-byte words");
     if constexpr ((n * sizeof(T)) % 16 == 0) {
 #pragma unroll
         for (int i = 0; i < static_cast<int>(n * sizeof(T) / 16); ++i) {
-            const u32x4 v = reinterpret_cast<const u32x4 *>(src)[i];
+            const u32x4 v = ld_stream<NTL>(reinterpret_cast<const u32x4 *>(src) + i);
             __builtin_memcpy(dst + i * (16 / sizeof(T)), &v, 16);
         }
     } else {
 #pragma unroll
         for (int i = 0; i < static_cast<int>(n * sizeof(T) / 8); ++i) {
-            const uint64_t v = reinterpret_cast<const uint64_t *>(src)[i];
+            const uint64_t v = ld_stream<NTL>(reinterpret_cast<const uint64_t *>(src) + i);
             __builtin_memcpy(dst + i * (8 / sizeof(T)), &v, 8);
         }
     }
@@ -145,7 +145,7 @@ __device__ __forceinline__ void load_vec(T *dst, const T *__restrict__ src)
 // One step's X tile of a lane.  FULL: every element in range and aligned, so
 // the tile is a fixed sequence of vector loads (a static load count lets the
 // compiler wait for exactly the oldest tile); otherwise masked element loads.
-template <int P, int L, int NI, int MT, bool FULL>
+template <int P, int L, int NI, int MT, bool FULL, bool NTL>
 __device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
                                           const typename Tile<P, L, NI, MT>::XT *__restrict__ base,
                                           const StreamArgs &a, int g, int64_t lim, int ivalid)
@@ -157,7 +157,7 @@ __device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
         constexpr int NCH = (NI * TL::KE) / TL::VE;
 #pragma unroll
         for (int j = 0; j < NCH; ++j) {
-            if constexpr (FULL) load_vec<XT, TL::VE>(x + j * TL::VE, base + j * 4 * TL::VE);
+            if constexpr (FULL) load_vec<XT, TL::VE, NTL>(x + j * TL::VE, base + j * 4 * TL::VE);
             else load_contig<XT, TL::VE>(x + j * TL::VE, base + j * 4 * TL::VE, false, lim - j * 4 * TL::VE);
         }
     } else {
@@ -170,7 +170,7 @@ __device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
                 const XT *src = base + static_cast<int64_t>(r) * a.stride_g;
                 XT *dst = x + (q * TL::KE + e) * MT;
                 if constexpr (FULL && (MT * sizeof(XT)) % 8 == 0) {
-                    load_vec<XT, MT>(dst, src);
+                    load_vec<XT, MT, NTL>(dst, src);
                 } else if constexpr (FULL) {
 #pragma unroll
                     for (int i = 0; i < MT; ++i) dst[i] = src[i];
@@ -186,8 +186,9 @@ constexpr int unit_lds_elems() { return ((L == L_KCONTIG) ? 16 : 16 * MT) * 16 *
 
 // One workgroup unit: block index b of the launch geometry in `a` (see
 // StreamArgs).  `lds` holds unit_lds_elems() doubles.  Called by the
-// per-call kernel below and by the persistent batch kernel.
-template <int P, int L, int NT, int NI, int MT, int NBUF>
+// per-call kernel below and by the persistent batch kernel.  XNT: X loads
+// are non-temporal.
+template <int P, int L, int NT, int NI, int MT, int NBUF, bool XNT = false>
 __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, double *lds)
 {
     using TL = Tile<P, L, NI, MT>;
@@ -354,7 +355,7 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
         auto issue = [&](int slot) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) wb[slot][nt] = a.W[lo * a.ldw + nt * 16 + c];
-            load_tile<P, L, NI, MT, FULL>(xb[slot], X + od.off + xlane, a, g, lim, ivalid);
+            load_tile<P, L, NI, MT, FULL, XNT>(xb[slot], X + od.off + xlane, a, g, lim, ivalid);
             od.next(a.od);
             ++lo;
         };

@@ -53,13 +53,13 @@ __device__ __forceinline__ void load_vec_n(T *dst, const T *__restrict__ src)
     if constexpr ((n * sizeof(T)) % 16 == 0) {
 #pragma unroll
         for (int i = 0; i < static_cast<int>(n * sizeof(T) / 16); ++i) {
-            const v4u v = reinterpret_cast<const v4u *>(src)[i];
+            const v4u v = ld_stream<false>(reinterpret_cast<const v4u *>(src) + i);
             __builtin_memcpy(dst + i * (16 / sizeof(T)), &v, 16);
         }
     } else {
 #pragma unroll
         for (int i = 0; i < static_cast<int>(n * sizeof(T) / 8); ++i) {
-            const uint64_t v = reinterpret_cast<const uint64_t *>(src)[i];
+            const uint64_t v = ld_stream<false>(reinterpret_cast<const uint64_t *>(src) + i);
             __builtin_memcpy(dst + i * (8 / sizeof(T)), &v, 8);
         }
     }
@@ -105,13 +105,12 @@ struct SlabWalk {
 // UB K-steps (4*UB rows), prefetched NBUF-1 steps ahead; complete steps issue
 // a fixed sequence of unmasked loads (the factors are zero-padded to whole
 // column tiles), so the compiler waits for exactly the oldest step.
-template <int P, int NTA, int NTC, int MT, bool STAGE2>
+template <int P, int NTA, int NTC, int MT, bool STAGE2, int UB, int NBUF>
 __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
 {
+    // UB: K-steps (of 4 rows) per ring step; NBUF: ring depth.
     using XT = typename TkTypes<P>::XT;
     using DT = typename TkTypes<P>::DT;
-    constexpr int UB = 2;     // K-steps (of 4 rows) per ring step
-    constexpr int NBUF = 4;   // ring depth
     constexpr int TA = 16 * NTA, TC = 16 * NTC;
     __shared__ double lds[STAGE2 ? TA * TC : 1];
 
@@ -348,35 +347,44 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
     else static_cast<float *>(a.out)[ooff] = static_cast<float>(acc);
 }
 
-template <int P, int NTA, int NTC, int MT, bool S2>
+template <int P, int NTA, int NTC, int MT, bool S2, int UB, int NB>
 void launch_tk(const TkArgs &a, int64_t grid, hipStream_t s)
 {
-    ttmc_fused_kernel<P, NTA, NTC, MT, S2><<<static_cast<unsigned>(grid), 64 * a.nwaves, 0, s>>>(a);
+    ttmc_fused_kernel<P, NTA, NTC, MT, S2, UB, NB><<<static_cast<unsigned>(grid), 64 * a.nwaves, 0, s>>>(a);
 }
 
 using TkLaunch = void (*)(const TkArgs &, int64_t, hipStream_t);
 struct TkEntry {
-    int p, nta, ntc, mt;
+    int p, nta, ntc, mt, ub, nbuf;
     bool s2;
     TkLaunch fn;
 };
-// M tiles per wave shrink as the rank tiles grow, to stay within 2 waves per SIMD.
-#define TK(P, A, C, MT) {P, A, C, MT, true, &launch_tk<P, A, C, MT, true>}
-#define TK1(P, A, MT) {P, A, 0, MT, false, &launch_tk<P, A, 1, MT, false>}
+// M tiles per wave and ring depth are chosen per rank tile to stay within
+// 2 waves per SIMD without spills.  Wider M tiles read each factor row for
+// more X (the factor rows come from L2: a 16*NTA-wide row per 16*MT X values).
+// For each (precision, NTA, NTC) the first entry is the default; later ones
+// are alternatives selectable by plan_hint.
+#define TK(P, A, C, MT, UB, NB) {P, A, C, MT, UB, NB, true, &launch_tk<P, A, C, MT, true, UB, NB>}
+#define TK1(P, A, MT, UB, NB) {P, A, 0, MT, UB, NB, false, &launch_tk<P, A, 1, MT, false, UB, NB>}
 const TkEntry kTkTable[] = {
-    TK(P_FP64, 1, 1, 4), TK(P_FP64, 1, 2, 4), TK(P_FP64, 1, 4, 4), TK(P_FP64, 2, 1, 2), TK(P_FP64, 2, 2, 2),
-    TK(P_FP64, 2, 4, 2), TK(P_FP64, 4, 1, 1), TK(P_FP64, 4, 2, 1), TK(P_FP64, 4, 4, 1),
-    TK(P_FP32, 1, 1, 4), TK(P_FP32, 1, 2, 4), TK(P_FP32, 1, 4, 4), TK(P_FP32, 2, 1, 4), TK(P_FP32, 2, 2, 4),
-    TK(P_FP32, 2, 4, 4), TK(P_FP32, 4, 1, 2), TK(P_FP32, 4, 2, 2), TK(P_FP32, 4, 4, 2),
-    TK1(P_FP64, 1, 4), TK1(P_FP64, 2, 2), TK1(P_FP64, 4, 1), TK1(P_FP32, 1, 4), TK1(P_FP32, 2, 4), TK1(P_FP32, 4, 2),
+    TK(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 2, 4), TK(P_FP64, 1, 4, 4, 2, 4),
+    TK(P_FP64, 2, 1, 4, 2, 3), TK(P_FP64, 2, 2, 4, 2, 3), TK(P_FP64, 2, 4, 2, 2, 4),
+    TK(P_FP64, 4, 1, 2, 2, 3), TK(P_FP64, 4, 2, 2, 2, 3), TK(P_FP64, 4, 4, 1, 2, 4),
+    TK(P_FP64, 2, 1, 2, 2, 4), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 4, 1, 1, 2, 4), TK(P_FP64, 4, 2, 1, 2, 4),
+    TK(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
+    TK(P_FP32, 2, 2, 4, 2, 4), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
+    TK(P_FP32, 4, 4, 2, 2, 4),
+    TK1(P_FP64, 1, 4, 2, 4), TK1(P_FP64, 2, 2, 2, 4), TK1(P_FP64, 4, 1, 2, 4),
+    TK1(P_FP32, 1, 4, 2, 4), TK1(P_FP32, 2, 4, 2, 4), TK1(P_FP32, 4, 2, 2, 4),
 };
 #undef TK
 #undef TK1
 
-const TkEntry *find_tk(int prec, int nta, int ntc, bool s2)
+// The variant-th compiled kernel (0 = default) for this precision and rank tiles.
+const TkEntry *find_tk(int prec, int nta, int ntc, bool s2, int variant)
 {
     for (const auto &e : kTkTable)
-        if (e.p == prec && e.nta == nta && e.s2 == s2 && (!s2 || e.ntc == ntc)) return &e;
+        if (e.p == prec && e.nta == nta && e.s2 == s2 && (!s2 || e.ntc == ntc) && variant-- == 0) return &e;
     return nullptr;
 }
 
@@ -403,7 +411,7 @@ struct TtmcPlan {
 };
 
 deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, int prec,
-                         TtmcPlan *out)
+                         int variant, TtmcPlan *out)
 {
     TtmcPlan p;
     p.N = spec->order;
@@ -439,8 +447,11 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
             p.slab_modes.push_back(m);
             p.n_slabs *= p.I[m];
         }
-    p.kernel = find_tk(prec, p.nta, p.ntc, p.stage2);
-    if (!p.kernel) return fail(DEINSUM_ERR_UNSUPPORTED, "no fused TTMc kernel for this precision and ranks");
+    p.kernel = find_tk(prec, p.nta, p.ntc, p.stage2, variant);
+    if (!p.kernel)
+        return fail(variant ? DEINSUM_ERR_INVALID_ARG : DEINSUM_ERR_UNSUPPORTED,
+                    variant ? "plan_hint names no compiled TTMc kernel variant"
+                            : "no fused TTMc kernel for this precision and ranks");
     p.mt = p.kernel->mt;
     p.n_ctiles = static_cast<int>(cdivl(p.I[p.c], 16 * p.mt));
     p.nwaves = std::min(4, p.n_ctiles);
@@ -484,12 +495,15 @@ deinsum_status ttmc_workspace_size(const deinsum_spec *spec, const int64_t *dims
     for (int m = 0; m < spec->order; ++m)
         if (dims[m] < 1) return fail(DEINSUM_ERR_SHAPE, "TTMc dims must be >= 1");
     TtmcPlan p;
-    if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, &p)) return st;
+    if (o.plan_hint < 0) return fail(DEINSUM_ERR_INVALID_ARG, "TTMc plan_hint must be >= 0");
+    if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, o.plan_hint, &p)) return st;
     if (p.via_mttkrp) {
         const int64_t R = ranks[0];
         deinsum_spec ms = *spec;
         ms.kind = DEINSUM_MTTKRP;
-        return deinsum_workspace_size(&ms, dims, &R, &o, bytes);
+        deinsum_opts o2 = o;
+        o2.plan_hint = 0;  // the TTMc variant index means nothing to the MTTKRP planner
+        return deinsum_workspace_size(&ms, dims, &R, &o2, bytes);
     }
     *bytes = p.total;
     return DEINSUM_OK;
@@ -503,7 +517,8 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     for (int m = 0; m < spec->order; ++m)
         if (dims[m] < 1) return fail(DEINSUM_ERR_SHAPE, "TTMc dims must be >= 1");
     TtmcPlan p;
-    if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, &p)) return st;
+    if (o.plan_hint < 0) return fail(DEINSUM_ERR_INVALID_ARG, "TTMc plan_hint must be >= 0");
+    if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, o.plan_hint, &p)) return st;
     const int N = p.N, n = p.n;
     const size_t xb = o.precision == P_FP64 ? 8 : 4, ub = xb;
     const size_t ob = o.out_dtype == DEINSUM_F64 ? 8 : 4;
@@ -534,6 +549,7 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         deinsum_opts o2 = o;
         o2.workspace = ws;
         o2.workspace_bytes = ws_bytes;
+        o2.plan_hint = 0;
         return deinsum_mttkrp(&ms, dims, R, X, U, Y, &o2, s);
     }
     int64_t stride[DEINSUM_MAX_ORDER], ystr[DEINSUM_MAX_ORDER];

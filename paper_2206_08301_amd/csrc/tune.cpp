@@ -2,7 +2,7 @@
 //
 // Keys name the path (per-call kernel or batched job), the problem's order,
 // free mode, precision, rank and dims.  The file format is one entry per line:
-//   <key> <nt> <ni> <mt> <split> <order> <xcd> <microseconds>
+//   <key> <nt> <ni> <mt> <xnt> <split> <order> <xcd> <microseconds>
 // with '#' starting a comment line.
 #include <algorithm>
 #include <cstdio>
@@ -35,8 +35,9 @@ deinsum_status load_file(const char *path, bool must_exist)
         std::istringstream is(line);
         std::string key;
         TuneChoice c;
-        if (!(is >> key >> c.nt >> c.ni >> c.mt >> c.split >> c.order >> c.xcd >> c.us) || c.nt < 1 || c.ni < 1 ||
-            c.mt < 1 || c.split < 0 || c.order < 0 || c.order > 1 || c.xcd < 0 || c.xcd > 1)
+        if (!(is >> key >> c.nt >> c.ni >> c.mt >> c.xnt >> c.split >> c.order >> c.xcd >> c.us) || c.nt < 1 ||
+            c.ni < 1 || c.mt < 1 || c.xnt < 0 || c.xnt > 1 || c.split < 0 || c.order < 0 || c.order > 1 || c.xcd < 0 ||
+            c.xcd > 1)
             return fail(DEINSUM_ERR_PARSE, std::string("tune_load: bad entry at line ") + std::to_string(lineno));
         g_cache[key] = c;
     }
@@ -47,11 +48,11 @@ deinsum_status save_file(const char *path)
 {
     std::ofstream f(path, std::ios::trunc);
     if (!f) return fail(DEINSUM_ERR_INVALID_ARG, std::string("tune_save: cannot write ") + path);
-    f << "# deinsum MTTKRP plan cache: key nt ni mt split order xcd microseconds\n";
+    f << "# deinsum MTTKRP plan cache: key nt ni mt xnt split order xcd microseconds\n";
     for (const auto &kv : g_cache) {
         const TuneChoice &c = kv.second;
-        f << kv.first << ' ' << c.nt << ' ' << c.ni << ' ' << c.mt << ' ' << c.split << ' ' << c.order << ' ' << c.xcd
-          << ' ' << c.us << '\n';
+        f << kv.first << ' ' << c.nt << ' ' << c.ni << ' ' << c.mt << ' ' << c.xnt << ' ' << c.split << ' ' << c.order
+          << ' ' << c.xcd << ' ' << c.us << '\n';
     }
     return f ? DEINSUM_OK : fail(DEINSUM_ERR_INVALID_ARG, std::string("tune_save: write failed for ") + path);
 }

@@ -11,7 +11,7 @@ enum TunePath { TUNE_STREAM = 0, TUNE_BATCH = 1 };
 
 // A tuned choice: the tile shape (kernel variant) and the outer-chunk count.
 struct TuneChoice {
-    int nt = 0, ni = 0, mt = 0;
+    int nt = 0, ni = 0, mt = 0, xnt = 0;
     int split = 0;
     int order = 0, xcd = 0;  // unit order and XCD remap of the per-call kernel
     double us = 0;           // measured median time of the winner

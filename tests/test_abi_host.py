@@ -153,14 +153,14 @@ def test_tune_cache_drives_the_planner(dn, tmp_path):
     forced = dn.workspace_size(spec, dims, [24], split_hint=1)  # hints bypass the cache
     assert forced < heuristic
     f = tmp_path / "cache.txt"
-    f.write_text(f"# comment\n{KEY_1024_M0} 2 16 1 1 0 0 123.5\n")
+    f.write_text(f"# comment\n{KEY_1024_M0} 2 16 1 0 1 0 0 123.5\n")
     dn.tune_load(f)
     assert dn.tune_entries() == 1
     assert dn.workspace_size(spec, dims, [24]) == forced
     assert dn.workspace_size(spec, dims, [24], split_hint=4) != forced
     out = tmp_path / "saved.txt"
     dn.tune_save(out)
-    assert f"{KEY_1024_M0} 2 16 1 1 0 0 123.5" in out.read_text()
+    assert f"{KEY_1024_M0} 2 16 1 0 1 0 0 123.5" in out.read_text()
     dn.tune_clear()
     assert dn.tune_entries() == 0
     assert dn.workspace_size(spec, dims, [24]) == heuristic
@@ -171,7 +171,7 @@ def test_tune_cache_stale_variant_falls_back(dn, tmp_path):
     dn.tune_clear()
     heuristic = dn.workspace_size(spec, dims, [24])
     f = tmp_path / "stale.txt"
-    f.write_text(f"{KEY_1024_M0} 2 99 1 1 0 0 1.0\n")
+    f.write_text(f"{KEY_1024_M0} 2 99 1 0 1 0 0 1.0\n")
     dn.tune_load(f)
     assert dn.workspace_size(spec, dims, [24]) == heuristic
     dn.tune_clear()
@@ -179,7 +179,7 @@ def test_tune_cache_stale_variant_falls_back(dn, tmp_path):
 
 def test_tune_rejects_bad_input(dn, tmp_path):
     f = tmp_path / "bad.txt"
-    f.write_text("s:N3:n0:p0:R24:8x8x8 two 16 1 1 0 0 1.0\n")
+    f.write_text("s:N3:n0:p0:R24:8x8x8 two 16 1 0 1 0 0 1.0\n")
     with pytest.raises(dn.DeinsumError) as e:
         dn.tune_load(f)
     assert e.value.status == -2

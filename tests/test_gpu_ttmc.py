@@ -94,3 +94,27 @@ def test_full_size_sampled_slabs(dn, synth, oracle_mod, dims, rank):
         assert nrel(Y[i].cpu().numpy(), ref) <= 1e-12, i
     del X
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dims,ranks", [((40, 70, 130), (8, 32, 24)), ((24, 60, 50, 70), (3, 40, 20, 64))])
+def test_ttmc_every_kernel_variant(dn, oracle_mod, dims, ranks):
+    """Every compiled fused-kernel variant for the ranks (plan_hint = 0, 1, ...) matches the oracle."""
+    rng = np.random.default_rng(sum(dims))
+    X = rng.uniform(-1, 1, dims)
+    Xd = to_dev(X)
+    n = 0
+    U = [None if m == n else rng.standard_normal((d, ranks[m])) for m, d in enumerate(dims)]
+    ref = oracle_mod.ttmc(X, U, n)
+    Ud = [to_dev(u) for u in U if u is not None]
+    seen = 0
+    for v in range(8):
+        try:
+            got = dn.ttmc(ttmc_spec(len(dims), n), Xd, Ud, variant=v)
+        except dn.DeinsumError as e:
+            assert e.status == -1  # no such variant
+            break
+        torch.cuda.synchronize()
+        flush(f"ttmc variant {v} dims={dims}: {nrel(got.cpu().numpy(), ref):.2e}")
+        assert nrel(got.cpu().numpy(), ref) <= 1e-12, v
+        seen += 1
+    assert seen >= 1
