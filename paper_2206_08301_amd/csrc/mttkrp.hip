@@ -67,7 +67,8 @@ __global__ void __launch_bounds__(256) outer_weights_kernel(const OuterDesc od, 
 template <typename OT>
 __global__ void __launch_bounds__(256)
 reduce_partials_kernel(const double *__restrict__ P, int64_t nparts, int64_t n_tiles, int tile_rows,
-                       int cols_pad, int64_t rows, int ncols, OT *__restrict__ out, int64_t ldo)
+                       int cols_pad, int64_t rows, int ncols, OT *__restrict__ out, int64_t ldo,
+                       const Fx24Header *__restrict__ hx, int64_t nx)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= rows * ncols) return;
@@ -88,6 +89,8 @@ reduce_partials_kernel(const double *__restrict__ P, int64_t nparts, int64_t n_t
         for (int u = 0; u < 8; ++u) s += v[u];
     }
     for (; q < nparts; ++q) s += p[q * part_stride];
+    if (hx) s = (hx->magic == kFx24Magic && hx->count == nx) ? ldexp(s, hx->exp2 - 8)  // kernels ran on m * 2^8
+                                                              : __builtin_nan("");
     out[i * ldo + col] = from_f64<OT>(s);
 }
 
@@ -117,6 +120,9 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16X3, L_KCONTIG, 1, 4, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 4, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_KCONTIG, 1, 3, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 3, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 3, 1, 2),
     SK(P_BF16X3, L_KCONTIG, 1, 1, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 1, 1, 3),
+    // FX24: runs of 16 elements per chunk (32 bytes of the 16-bit plane, 16 of the 8-bit plane)
+    SK(P_FX24, L_KCONTIG, 1, 32, 1, 3), SK(P_FX24, L_KCONTIG, 2, 32, 1, 3), SK(P_FX24, L_KCONTIG, 4, 16, 1, 2),
+    SK(P_FX24, L_KCONTIG, 1, 16, 1, 3), SK(P_FX24, L_KCONTIG, 2, 16, 1, 3),
     // M-contiguous: NI K-steps of 4*KE rows; MT output indices per lane
     // (FP64: non-temporal X loads first -- they keep the per-K-step factor rows cached, 1.50 -> 1.37 ms
     //  for the 1024^3 R=24 last mode; the K-contiguous kernels lose with them and keep plain loads.)
@@ -127,6 +133,8 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
     SKN(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SKN(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SKN(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
+    // FX24: four output indices per lane (8 bytes of the 16-bit plane, 4 of the 8-bit plane per row)
+    SK(P_FX24, L_MCONTIG, 1, 8, 4, 3), SK(P_FX24, L_MCONTIG, 2, 8, 4, 2),
 };
 #undef SK
 #undef SKN
@@ -154,16 +162,16 @@ deinsum_status launch_outer_weights(const OuterDesc &od, int64_t O, int64_t ldu,
 
 deinsum_status launch_reduce_partials(const double *P, int64_t nparts, int64_t n_tiles, int tile_rows,
                                       int cols_pad, int64_t rows, int ncols, void *out, int out_dtype,
-                                      int64_t ldo, hipStream_t s)
+                                      int64_t ldo, const Fx24Header *hx, int64_t nx, hipStream_t s)
 {
     const int64_t total = rows * ncols;
     const unsigned grid = static_cast<unsigned>((total + 255) / 256);
     if (out_dtype == DEINSUM_F64)
         reduce_partials_kernel<double><<<grid, 256, 0, s>>>(P, nparts, n_tiles, tile_rows, cols_pad, rows,
-                                                            ncols, static_cast<double *>(out), ldo);
+                                                            ncols, static_cast<double *>(out), ldo, hx, nx);
     else if (out_dtype == DEINSUM_F32)
         reduce_partials_kernel<float><<<grid, 256, 0, s>>>(P, nparts, n_tiles, tile_rows, cols_pad, rows,
-                                                           ncols, static_cast<float *>(out), ldo);
+                                                           ncols, static_cast<float *>(out), ldo, hx, nx);
     else
         return fail(DEINSUM_ERR_INVALID_ARG, "output dtype must be f64 or f32");
     return check_launch("reduce_partials");

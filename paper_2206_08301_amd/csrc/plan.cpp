@@ -122,6 +122,18 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
             best_padded = padded;
         }
     }
+    // Forms without a kernel of this column width take narrower tiles (more column blocks).
+    for (int w = nt / 2; !best && w >= 1; w /= 2)
+        for (int i = 0; i < count; ++i) {
+            const StreamKernelInfo &k = table[i];
+            if (k.prec != pb.prec || k.layout != layout || k.nt != w) continue;
+            const int64_t slice = 4LL * k.ni * ke_of(pb.prec);
+            const int64_t padded = cdiv(Ig, slice) * slice;
+            if (!best || padded < best_padded) {
+                best = &k;
+                best_padded = padded;
+            }
+        }
     if (!best) return fail(DEINSUM_ERR_UNSUPPORTED, "no compiled MTTKRP kernel for this precision and rank");
     return plan_geometry(pb, best, split_hint, out);
 }

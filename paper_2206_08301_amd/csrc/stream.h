@@ -20,6 +20,8 @@ template <> struct PrecTypes<P_FP64> { using XT = double; using DT = f64x4; stat
 template <> struct PrecTypes<P_FP32> { using XT = float;  using DT = f32x4; static constexpr int KE = 1; };
 template <> struct PrecTypes<P_BF16> { using XT = bf16_t; using DT = f32x4; static constexpr int KE = 8; };
 template <> struct PrecTypes<P_BF16X3> { using XT = float; using DT = f32x4; static constexpr int KE = 8; };
+// FX24: the ring holds raw words of the two planes; values are decoded per step.
+template <> struct PrecTypes<P_FX24> { using XT = uint32_t; using DT = f32x4; static constexpr int KE = 1; };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -110,9 +112,12 @@ struct Tile {
     using XT = typename PrecTypes<P>::XT;
     static constexpr int KE = PrecTypes<P>::KE;
     static constexpr int SLICE = 4 * NI * KE;
-    static constexpr int VE = (P == P_BF16X3) ? 8 : static_cast<int>(16 / sizeof(XT));
+    static constexpr int VE = (P == P_BF16X3) ? 8 : (P == P_FX24 ? 16 : static_cast<int>(16 / sizeof(XT)));
     static constexpr int XN = (L == L_KCONTIG) ? NI * KE : NI * KE * MT;  // X elements per lane per step
+    // ring words per step: FX24 keeps XN/2 words of the 16-bit plane, then XN/4 of the 8-bit plane
+    static constexpr int XW = (P == P_FX24) ? XN / 2 + XN / 4 : XN;
     static_assert(L == L_MCONTIG || (NI * KE) % VE == 0, "K-contiguous runs must be whole chunks");
+    static_assert(P != P_FX24 || L == L_KCONTIG || MT % 4 == 0, "FX24 M-contiguous tiles hold 4k indices");
 
     __device__ static int pos_k(int t, int g) { return (t / VE) * 4 * VE + g * VE + t % VE; }
     __device__ static int pos_m(int q, int g, int e) { return q * 4 * KE + g * KE + e; }
@@ -181,6 +186,83 @@ __device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
     }
 }
 
+// FX24 tile of a lane: element offset `off` of its first element in both
+// planes (same layout as load_tile).  Element t of the run lands in 16-bit
+// word t/2 (half t%2) and in 8-bit word XN/2 + t/4 (byte t%4).
+template <int L, int NI, int MT, bool FULL, bool NTL>
+__device__ __forceinline__ void load_tile_fx24(uint32_t *x, int64_t off, const StreamArgs &a, int64_t lim,
+                                               int ivalid, int g)
+{
+    using TL = Tile<P_FX24, L, NI, MT>;
+    constexpr int XN = TL::XN;
+    const uint16_t *__restrict__ H = static_cast<const uint16_t *>(a.X) + off;
+    const uint8_t *__restrict__ B = static_cast<const uint8_t *>(a.X2) + off;
+    uint32_t *xh = x, *xl = x + XN / 2;
+    if constexpr (L == L_KCONTIG) {
+        constexpr int NCH = NI / TL::VE;  // chunks of 16 elements, 4*16 apart in the slice
+#pragma unroll
+        for (int j = 0; j < NCH; ++j) {
+            const int64_t e0 = static_cast<int64_t>(j) * 4 * TL::VE;
+            if constexpr (FULL) {
+                const u32x4 h0 = ld_stream<NTL>(reinterpret_cast<const u32x4 *>(H + e0));
+                const u32x4 h1 = ld_stream<NTL>(reinterpret_cast<const u32x4 *>(H + e0) + 1);
+                const u32x4 l0 = ld_stream<NTL>(reinterpret_cast<const u32x4 *>(B + e0));
+                __builtin_memcpy(xh + j * 8, &h0, 16);
+                __builtin_memcpy(xh + j * 8 + 4, &h1, 16);
+                __builtin_memcpy(xl + j * 4, &l0, 16);
+            } else {
+                const int64_t valid = lim - e0;
+#pragma unroll
+                for (int w = 0; w < 8; ++w) xh[j * 8 + w] = 0;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) xl[j * 4 + w] = 0;
+#pragma unroll
+                for (int i = 0; i < TL::VE; ++i)
+                    if (i < valid) {
+                        xh[j * 8 + i / 2] |= static_cast<uint32_t>(H[e0 + i]) << (16 * (i % 2));
+                        xl[j * 4 + i / 4] |= static_cast<uint32_t>(B[e0 + i]) << (8 * (i % 4));
+                    }
+            }
+        }
+    } else {
+        static_assert(MT == 4, "FX24 M-contiguous tiles are 4 indices wide");
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+            const int r = TL::pos_m(q, g, 0);
+            const int64_t e0 = static_cast<int64_t>(r) * a.stride_g;
+            if constexpr (FULL) {
+                const uint64_t h = ld_stream<NTL>(reinterpret_cast<const uint64_t *>(H + e0));
+                const uint32_t l = ld_stream<NTL>(reinterpret_cast<const uint32_t *>(B + e0));
+                xh[2 * q] = static_cast<uint32_t>(h);
+                xh[2 * q + 1] = static_cast<uint32_t>(h >> 32);
+                xl[q] = l;
+            } else {
+                xh[2 * q] = xh[2 * q + 1] = xl[q] = 0;
+                if (r < lim) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (i < ivalid) {
+                            xh[2 * q + i / 2] |= static_cast<uint32_t>(H[e0 + i]) << (16 * (i % 2));
+                            xl[q] |= static_cast<uint32_t>(B[e0 + i]) << (8 * i);
+                        }
+                }
+            }
+        }
+    }
+}
+
+// Element t of an FX24 ring slot as FP32: v_perm assembles (m16 << 16) | (m8 << 8),
+// i.e. m * 2^8 as a 32-bit integer, exactly representable in FP32.
+template <int XN>
+__device__ __forceinline__ float fx24_value(const uint32_t *x, int t)
+{
+    const uint32_t h = x[t >> 1];
+    const uint32_t l = x[XN / 2 + (t >> 2)];
+    const uint32_t sel = 0x0Cu | (static_cast<uint32_t>(t & 3) << 8) | (static_cast<uint32_t>(4 + 2 * (t & 1)) << 16) |
+                         (static_cast<uint32_t>(5 + 2 * (t & 1)) << 24);
+    return static_cast<float>(static_cast<int32_t>(__builtin_amdgcn_perm(h, l, sel)));
+}
+
 template <int L, int NT, int MT>
 constexpr int unit_lds_elems() { return ((L == L_KCONTIG) ? 16 : 16 * MT) * 16 * NT; }
 
@@ -244,7 +326,7 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
 
     // Register-resident slice of U^g for every K slot of every instruction.
     double fr64[(P == P_FP64) ? NI * NT : 1];
-    float fr32[(P == P_FP32) ? NI * NT : 1];
+    float fr32[(P == P_FP32 || P == P_FX24) ? NI * NT : 1];
     u16x8 frh[(P >= P_BF16) ? NI * NT : 1];
     u16x8 frl[(P == P_BF16X3) ? NI * NT : 1];
 #pragma unroll
@@ -303,6 +385,10 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
                         if constexpr (P == P_FP64) d[mt][nt] = mfma_f64(xa, fr64[q * NT + nt], d[mt][nt]);
                         else d[mt][nt] = mfma_f32(xa, fr32[q * NT + nt], d[mt][nt]);
                     }
+                } else if constexpr (P == P_FX24) {
+                    const float xa = fx24_value<TL::XN>(x, (L == L_KCONTIG) ? q : q * MT + mt);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) d[mt][nt] = mfma_f32(xa, fr32[q * NT + nt], d[mt][nt]);
                 } else if constexpr (P == P_BF16) {
                     u16x8 xa;
 #pragma unroll
@@ -347,7 +433,7 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     // Hadamard weights of step t+NBUF-1 are loaded while step t computes.
     auto walk = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        XT xb[NBUF][XN];
+        XT xb[NBUF][TL::XW];
         double wb[NBUF][NT];
         Odometer od;
         od.init(a.od, o0);
@@ -355,7 +441,10 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
         auto issue = [&](int slot) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) wb[slot][nt] = a.W[lo * a.ldw + nt * 16 + c];
-            load_tile<P, L, NI, MT, FULL, XNT>(xb[slot], X + od.off + xlane, a, g, lim, ivalid);
+            if constexpr (P == P_FX24)
+                load_tile_fx24<L, NI, MT, FULL, XNT>(xb[slot], od.off + xlane, a, lim, ivalid, g);
+            else
+                load_tile<P, L, NI, MT, FULL, XNT>(xb[slot], X + od.off + xlane, a, g, lim, ivalid);
             od.next(a.od);
             ++lo;
         };

@@ -1,0 +1,130 @@
+"""GPU tests of the FX24 form: the encoder against a plain numpy encoding of the
+format, and MTTKRP on FX24 storage against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import flush, mttkrp_spec, nrel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dn():
+    import paper_2206_08301_amd as m
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    m._lib.load()
+    return m
+
+
+def encode_np(x):
+    """The FX24 format written out in numpy: e, m (int24), planes."""
+    x = np.asarray(x, dtype=np.float64).ravel()
+    mx = float(np.max(np.abs(x))) if x.size else 0.0
+    e = (np.frexp(mx)[1] - 23) if mx > 0 else 0
+    m = np.clip(np.rint(np.ldexp(x, -e)), -(2 ** 23), 2 ** 23 - 1).astype(np.int64)
+    hi = ((m >> 8) & 0xFFFF).astype(np.uint16)
+    lo = (m & 255).astype(np.uint8)
+    return e, mx, m, hi, lo
+
+
+def planes(dn, f):
+    n = f.numel()
+    raw = f.buf.cpu().numpy()
+    hi = raw[256:256 + 2 * n].view(np.uint16)
+    lo_off = 256 + (2 * n + 255) // 256 * 256
+    lo = raw[lo_off:lo_off + n]
+    return hi, lo
+
+
+@pytest.mark.parametrize("shape,scale", [((7, 5, 9), 1.0), ((64, 33, 17), 1e-3), ((1,), 3.0), ((300,), 1e6)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_encoder_matches_format(dn, shape, scale, dtype):
+    rng = np.random.default_rng(len(shape) + int(scale))
+    x = rng.uniform(-scale, scale, shape)
+    if dtype == torch.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    f = dn.to_fx24(to_dev(x, dtype))
+    torch.cuda.synchronize()
+    e, mx, m, hi, lo = encode_np(x)
+    h = f.header()
+    assert h["magic"] == 0x34325846 and h["exp2"] == e and h["count"] == x.size and h["max_abs"] == mx
+    ghi, glo = planes(dn, f)
+    assert np.array_equal(ghi, hi) and np.array_equal(glo, lo)
+    # decoding the numpy planes gives back m, and |x - m 2^e| <= 2^(e-1)
+    dec = (ghi.astype(np.int16).astype(np.int64) << 8) | glo.astype(np.int64)
+    assert np.array_equal(dec, m)
+    assert np.max(np.abs(x.ravel() - np.ldexp(dec.astype(np.float64), e))) <= 2.0 ** (e - 1)
+
+
+def test_encoder_zero_tensor(dn):
+    f = dn.to_fx24(torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    h = f.header()
+    assert h["exp2"] == 0 and h["max_abs"] == 0.0
+    ghi, glo = planes(dn, f)
+    assert not ghi.any() and not glo.any()
+
+
+SHAPES = [((64, 64, 64), 24), ((37, 45, 96), 20), ((16, 21, 130), 40), ((6, 5, 7, 48), 16), ((40, 33, 80), 64)]
+
+
+@pytest.mark.parametrize("dims,R", SHAPES)
+def test_fx24_integer_exact(dn, oracle_mod, synth, dims, R):
+    """Integer X in [-2, 2] and integer factors: encoding and arithmetic are exact."""
+    rng = np.random.default_rng(sum(dims))
+    X = rng.integers(-2, 3, dims).astype(np.float64)
+    U = [rng.integers(-2, 3, (d, R)).astype(np.float64) for d in dims]
+    f = dn.to_fx24(to_dev(X))
+    for n in range(len(dims)):
+        flush(f"fx24 exact dims={dims} R={R} n={n}")
+        ops = [to_dev(U[m], torch.float32) for m in range(len(dims)) if m != n]
+        M = dn.mttkrp(mttkrp_spec(len(dims), n), f, ops, precision="fx24", out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        ref = oracle_mod.mttkrp(X, [None if m == n else U[m] for m in range(len(dims))], n)
+        assert np.array_equal(M.cpu().numpy(), ref), (dims, n)
+
+
+@pytest.mark.parametrize("dims,R", SHAPES)
+def test_fx24_uniform_error(dn, oracle_mod, dims, R):
+    rng = np.random.default_rng(7 + sum(dims))
+    X = rng.uniform(-1, 1, dims)
+    U = [rng.standard_normal((d, R)).astype(np.float32).astype(np.float64) for d in dims]
+    f = dn.to_fx24(to_dev(X))
+    for n in range(len(dims)):
+        ops = [to_dev(U[m], torch.float32) for m in range(len(dims)) if m != n]
+        M = dn.mttkrp(mttkrp_spec(len(dims), n), f, ops, precision="fx24", out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        ref = oracle_mod.mttkrp(X, [None if m == n else U[m] for m in range(len(dims))], n)
+        err = nrel(M.cpu().numpy(), ref)
+        flush(f"fx24 uniform dims={dims} R={R} n={n}: {err:.2e}")
+        assert err <= 1e-6
+
+
+def test_fx24_header_mismatch_gives_nan(dn):
+    """A buffer encoded for more elements than the call's dims is rejected in the output."""
+    X = torch.rand((8, 8, 9), dtype=torch.float64, device="cuda")
+    f = dn.to_fx24(X)
+    small = dn.FX24(f.buf, (8, 8, 8))  # fewer elements than encoded: reads stay inside the buffer
+    U = [torch.rand((8, 4), dtype=torch.float32, device="cuda") for _ in range(2)]
+    M = dn.mttkrp(mttkrp_spec(3, 0), small, U, precision="fx24", out_dtype=torch.float64)
+    torch.cuda.synchronize()
+    assert torch.isnan(M).all()
+
+
+def test_fx24_tuned_plan(dn, oracle_mod):
+    rng = np.random.default_rng(99)
+    dims, R = (96, 80, 128), 24
+    X = rng.uniform(-1, 1, dims)
+    U = [rng.standard_normal((d, R)).astype(np.float32).astype(np.float64) for d in dims]
+    f = dn.to_fx24(to_dev(X))
+    for n in (0, 2):
+        ops = [to_dev(U[m], torch.float32) for m in range(3) if m != n]
+        dn.tune_clear()
+        rep = dn.tune_mttkrp(mttkrp_spec(3, n), f, ops, precision="fx24", out_dtype=torch.float64, reps=2)
+        assert rep.tuned_us > 0
+        M = dn.mttkrp(mttkrp_spec(3, n), f, ops, precision="fx24", out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        ref = oracle_mod.mttkrp(X, [None if m == n else U[m] for m in range(3)], n)
+        assert nrel(M.cpu().numpy(), ref) <= 1e-6
+    dn.tune_clear()
