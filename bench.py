@@ -42,7 +42,7 @@ def parse_args():
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic plans instead of autotuning first")
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: run one plain 1 GiB device copy first (calibrates HBM byte counters)")
-    ap.add_argument("--only", default="", help="profiling: run just one form (fp64|fx24|fp32|bf16|bf16x3|ttmc|serving)")
+    ap.add_argument("--only", default="", help="profiling: run just one form (fp64|fx20|fp32|bf16|bf16x3|ttmc|serving)")
     return ap.parse_args()
 
 
@@ -211,15 +211,15 @@ def main():
         dn.convert(X, X32)
         Xb = None
         Xf = None
-        forms_all = ("fx24", "fp32", "bf16x3", "bf16")
+        forms_all = ("fx20", "fp32", "bf16x3", "bf16")
         todo = list(forms_all) if not args.only else ([args.only] if args.only in forms_all else [])
         for prec in todo:
             if prec == "bf16" and Xb is None:
                 Xb = torch.empty(DIMS, dtype=torch.bfloat16, device=dev)
                 dn.convert(X, Xb)
-            if prec == "fx24" and Xf is None:
-                Xf = dn.to_fx24(X)
-            Xp = Xb if prec == "bf16" else (Xf if prec == "fx24" else X32)
+            if prec == "fx20" and Xf is None:
+                Xf = dn.to_fx20(X)
+            Xp = Xb if prec == "bf16" else (Xf if prec == "fx20" else X32)
             modes = [0, 1, 2]
             o32 = {n: torch.empty((DIMS[n], R), dtype=torch.float32, device=dev) for n in modes}
             if tune:
@@ -241,7 +241,7 @@ def main():
                     evs[k + 1].record(stream)
                 torch.cuda.synchronize()
                 t = statistics.median(evs[k].elapsed_time(evs[k + 1]) for k in range(10))
-                xb = {"bf16": 2, "fx24": 3}.get(prec, 4)
+                xb = {"bf16": 2, "fx20": 3}.get(prec, 4)
                 b, f = alg_counts(DIMS, R, n, xb)
                 res[str(n)] = {"ms": round(t, 4), "GB/s": round(b / (t / 1e3) / 1e9, 1),
                                "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -249,7 +249,7 @@ def main():
                 if steps:
                     res[str(n)]["speedup_vs_fp64"] = round(med[n] / t, 3)
             err = sampled_error(o32)
-            forms[prec] = {"x_storage": {"bf16": "bf16", "fx24": "fx24 (24-bit fixed point, 3 bytes)"}.get(prec, "f32"),
+            forms[prec] = {"x_storage": {"bf16": "bf16", "fx20": "fx20 (20-bit fixed point: FP16 + int8 planes, 3 bytes)"}.get(prec, "f32"),
                            "modes": res,
                            "max_rel_err_sampled_vs_fp64_oracle": err}
             print(f"[bench] {prec}: {res} err {err:.2e}", file=sys.stderr, flush=True)

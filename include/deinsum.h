@@ -77,17 +77,21 @@ typedef enum deinsum_dtype { DEINSUM_F64 = 0, DEINSUM_F32 = 1, DEINSUM_BF16 = 2 
  *   BF16X3 : X and factors FP32, each split on the device into hi + lo
  *            BF16 parts; products hi*hi + hi*lo + lo*hi on the matrix cores
  *            with FP32 accumulation, FP64 beyond one slice.
- *   FX24   : X in the 3-byte FX24 storage below (deinsum_fx24_encode),
- *            factors FP32; X values decoded exactly to FP32, FP32
- *            matrix-core products, FP64 beyond one slice; output FP32 or
- *            FP64.  Reads 3 bytes per element of X instead of 8.
+ *   FX20   : X in the 3-byte FX20 storage below (deinsum_fx20_encode),
+ *            factors FP32.  Last-mode-contiguous free modes: each factor
+ *            slice is scaled per column by a power of two and split into
+ *            FP16 hi + lo parts; X's FP16 part h and int8 part l feed FP16
+ *            matrix-core products h*hi + h*lo + l*hi with FP32 accumulation,
+ *            FP64 beyond one slice.  Free mode = last mode: X decoded to FP32,
+ *            FP32 matrix-core products.  Output FP32 or FP64.  Reads 3 bytes
+ *            per element of X instead of 8.
  */
 typedef enum deinsum_precision {
     DEINSUM_PREC_FP64 = 0,
     DEINSUM_PREC_FP32 = 1,
     DEINSUM_PREC_BF16 = 2,
     DEINSUM_PREC_BF16X3 = 3,
-    DEINSUM_PREC_FX24 = 4
+    DEINSUM_PREC_FX20 = 4
 } deinsum_precision;
 
 /* Parsed einsum (deinsum_parse).  Letters are ASCII a-z / A-Z. */
@@ -203,28 +207,29 @@ deinsum_status deinsum_synth_fill(void *X, int32_t dtype, int64_t count, uint64_
                                   int64_t offset, int32_t dist, void *stream);
 
 /*
- * FX24 storage of a tensor X of `count` elements: 24-bit fixed point with one
- * power-of-two scale, X[i] ~ m[i] * 2^e, m[i] a signed 24-bit integer,
- * e = (exponent of max|X|) - 23, m[i] = X[i] * 2^-e rounded to nearest even and
- * clamped to [-2^23, 2^23 - 1].  The absolute error of every element is at most
- * 2^(e-1) <= 2^-24 * 2 max|X|; the normwise relative error of X is at most
- * 2^-23 * max|X| / rms(X) (about 2e-7 for uniform data).  Layout of the
- * buffer (256-byte aligned, deinsum_fx24_size bytes):
- *   bytes [0, 256)                 header: uint32 magic 0x34325846 ("FX24"),
+ * FX20 storage of a tensor X of `count` elements: 20-bit fixed point with one
+ * power-of-two scale, X[i] ~ m[i] * 2^e, e = (exponent of max|X|) - 19 (so
+ * max|X| < 2^(e+19)), m[i] = X[i] * 2^-e rounded to nearest even, |m[i]| <= 2^19.
+ * m is kept as m = 256 h + l with h = floor((m + 128) / 256) in [-2048, 2048]
+ * and l = m - 256 h in [-128, 127].  The absolute error of every element is at
+ * most 2^(e-1) <= 2^-20 max|X|; the normwise relative error of X is at most
+ * 2^-19 * max|X| / rms(X) (3.3e-6 for uniform data, about 1e-6 in practice).
+ * Layout of the buffer (256-byte aligned, deinsum_fx20_size bytes):
+ *   bytes [0, 256)                 header: uint32 magic 0x30325846 ("FX20"),
  *                                  int32 e, int64 count, double max|X|, zeros;
- *   bytes [256, 256 + A(2 count))  uint16 plane: m[i] >> 8 (two's complement);
- *   then A(count) bytes            uint8 plane: m[i] & 255,
+ *   bytes [256, 256 + A(2 count))  FP16 plane: h[i] as IEEE binary16 (exact);
+ *   then A(count) bytes            int8 plane: l[i] (two's complement),
  * with A(b) = b rounded up to a multiple of 256.  X keeps its row-major index
- * order in both planes.  MTTKRP with DEINSUM_PREC_FX24 takes the buffer's
+ * order in both planes.  MTTKRP with DEINSUM_PREC_FX20 takes the buffer's
  * base address as X; a buffer whose header does not match the call's element
  * count yields NaN outputs.
  */
-deinsum_status deinsum_fx24_size(int64_t count, size_t *bytes);
+deinsum_status deinsum_fx20_size(int64_t count, size_t *bytes);
 
 /* Encode `count` elements of src (DEINSUM_F64 or DEINSUM_F32, device) into the
- * FX24 buffer dst of dst_bytes >= deinsum_fx24_size(count) bytes (device,
+ * FX20 buffer dst of dst_bytes >= deinsum_fx20_size(count) bytes (device,
  * 256-byte aligned).  Asynchronous on `stream`; deterministic. */
-deinsum_status deinsum_fx24_encode(const void *src, int32_t src_dtype, int64_t count, void *dst, size_t dst_bytes,
+deinsum_status deinsum_fx20_encode(const void *src, int32_t src_dtype, int64_t count, void *dst, size_t dst_bytes,
                                    void *stream);
 
 /* Elementwise conversion f64 -> f32 / bf16 or f32 -> bf16, round to nearest even. */

@@ -23,11 +23,11 @@ from ._lib import DeinsumError, Report, Spec  # noqa: F401
 MTTKRP = 1
 TTMC = 2
 F64, F32, BF16 = 0, 1, 2
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fx24": 4}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fx20": 4}
 _X_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16, "bf16x3": torch.float32,
-            "fx24": None}
+            "fx20": None}
 _U_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32, "bf16x3": torch.float32,
-            "fx24": torch.float32}
+            "fx20": torch.float32}
 _DT_CODE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
 DIST = {"uniform": 0, "int5": 1, "int3": 2}
 
@@ -72,9 +72,10 @@ def _opts(precision, out_dtype, workspace, plan_hint, split_hint, report):
     return o
 
 
-class FX24:
-    """X in FX24 storage (24-bit fixed point, one power-of-two scale; layout in
-    include/deinsum.h): ``buf`` is the uint8 device buffer, ``shape`` the tensor's shape."""
+class FX20:
+    """X in FX20 storage (20-bit fixed point in an FP16 and an int8 plane, one power-of-two
+    scale; layout in include/deinsum.h): ``buf`` is the uint8 device buffer, ``shape`` the
+    tensor's shape."""
 
     def __init__(self, buf: torch.Tensor, shape):
         self.buf = buf
@@ -101,24 +102,24 @@ class FX24:
         return {"magic": magic, "exp2": e, "count": count, "max_abs": mx}
 
 
-def fx24_size(count: int) -> int:
+def fx20_size(count: int) -> int:
     n = ctypes.c_size_t(0)
-    _lib.check(_lib.load().deinsum_fx24_size(int(count), ctypes.byref(n)))
+    _lib.check(_lib.load().deinsum_fx20_size(int(count), ctypes.byref(n)))
     return n.value
 
 
-def to_fx24(X: torch.Tensor, stream=None) -> FX24:
-    """Encode an FP64 or FP32 device tensor into FX24 storage (on the device)."""
+def to_fx20(X: torch.Tensor, stream=None) -> FX20:
+    """Encode an FP64 or FP32 device tensor into FX20 storage (on the device)."""
     if X.device.type != "cuda" or not X.is_contiguous() or X.dtype not in (torch.float64, torch.float32):
-        raise TypeError("to_fx24 needs a contiguous FP64 or FP32 device tensor")
-    nbytes = fx24_size(X.numel())
+        raise TypeError("to_fx20 needs a contiguous FP64 or FP32 device tensor")
+    nbytes = fx20_size(X.numel())
     buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=X.device)
     off = (-buf.data_ptr()) % 256  # the caching allocator aligns to 512; kept general
     buf = buf[off:off + nbytes]
     with torch.cuda.device(X.device):
-        _lib.check(_lib.load().deinsum_fx24_encode(ctypes.c_void_p(X.data_ptr()), _DT_CODE[X.dtype], X.numel(),
+        _lib.check(_lib.load().deinsum_fx20_encode(ctypes.c_void_p(X.data_ptr()), _DT_CODE[X.dtype], X.numel(),
                                                    ctypes.c_void_p(buf.data_ptr()), nbytes, _stream(stream)))
-    return FX24(buf, X.shape)
+    return FX20(buf, X.shape)
 
 
 def _check_tensor(t, dtype, name):
@@ -150,9 +151,9 @@ def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=Non
     sp = _spec(spec)
     if sp.kind != MTTKRP:
         raise ValueError("spec is not an MTTKRP")
-    if precision == "fx24":
-        if not isinstance(X, FX24):
-            raise TypeError("the fx24 form takes X from to_fx24()")
+    if precision == "fx20":
+        if not isinstance(X, FX20):
+            raise TypeError("the fx20 form takes X from to_fx20()")
     else:
         _check_tensor(X, _X_DTYPE[precision], "X")
     if X.dim() != sp.order:
@@ -178,7 +179,7 @@ def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=Non
             raise ValueError("out has the wrong shape")
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
     o = _opts(precision, out_dtype, workspace, plan_hint, split_hint, report)
-    xptr = X.buf.data_ptr() if isinstance(X, FX24) else X.data_ptr()
+    xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
     with torch.cuda.device(X.device):
         _lib.check(_lib.load().deinsum_mttkrp(ctypes.byref(sp), _i64(X.shape), R, ctypes.c_void_p(xptr),
                                               ptrs, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o),
@@ -192,9 +193,9 @@ def tune_mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, reps=5, 
     sp = _spec(spec)
     if sp.kind != MTTKRP:
         raise ValueError("spec is not an MTTKRP")
-    if precision == "fx24":
-        if not isinstance(X, FX24):
-            raise TypeError("the fx24 form takes X from to_fx24()")
+    if precision == "fx20":
+        if not isinstance(X, FX20):
+            raise TypeError("the fx20 form takes X from to_fx20()")
     else:
         _check_tensor(X, _X_DTYPE[precision], "X")
     R = U[0].shape[1]
@@ -207,7 +208,7 @@ def tune_mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, reps=5, 
     o = _opts(precision, out_dtype, None, 0, 0, None)
     rep = Report()
     fn = _lib.load().deinsum_tune_batch_mttkrp if batched else _lib.load().deinsum_tune_mttkrp
-    xptr = X.buf.data_ptr() if isinstance(X, FX24) else X.data_ptr()
+    xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
     with torch.cuda.device(X.device):
         _lib.check(fn(ctypes.byref(sp), _i64(X.shape), R, ctypes.c_void_p(xptr), ptrs,
                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), int(reps), ctypes.byref(rep),

@@ -74,7 +74,7 @@ size_t x_elem_bytes(int prec)
     switch (prec) {
     case DEINSUM_PREC_FP64: return 8;
     case DEINSUM_PREC_BF16: return 2;
-    case DEINSUM_PREC_FX24: return 3;  // algorithmic bytes; the buffer adds a header and plane padding
+    case DEINSUM_PREC_FX20: return 3;  // algorithmic bytes; the buffer adds a header and plane padding
     default: return 4;
     }
 }
@@ -91,7 +91,7 @@ deinsum_status resolve_opts(const deinsum_opts *in, deinsum_opts *o)
 {
     deinsum_opts_init(o);
     if (in) *o = *in;
-    if (o->precision < DEINSUM_PREC_FP64 || o->precision > DEINSUM_PREC_FX24)
+    if (o->precision < DEINSUM_PREC_FP64 || o->precision > DEINSUM_PREC_FX20)
         return fail(DEINSUM_ERR_INVALID_ARG, "opts.precision is not a deinsum_precision");
     if (o->out_dtype != DEINSUM_F64 && o->out_dtype != DEINSUM_F32)
         return fail(DEINSUM_ERR_INVALID_ARG, "opts.out_dtype must be DEINSUM_F64 or DEINSUM_F32");
@@ -176,10 +176,10 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
         }
     }
     const int cols_pad = 16 * p.nt;
-    const bool fx24 = pb.prec == P_FX24;
+    const bool fx20 = pb.prec == P_FX20;
     int64_t nx = 1;
     for (int m = 0; m < N; ++m) nx *= pb.dims[m];
-    const Fx24Header *hx = fx24 ? static_cast<const Fx24Header *>(c.X) : nullptr;
+    const Fx20Header *hx = fx20 ? static_cast<const Fx20Header *>(c.X) : nullptr;
     for (int64_t cb = 0; cb < p.col_blocks; ++cb) {
         const int64_t col0 = cb * cols_pad;
         const int ncols = static_cast<int>(std::min<int64_t>(cols_pad, pb.R - col0));
@@ -187,8 +187,8 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
             return static_cast<const void *>(static_cast<const char *>(c.U[m]) + col0 * ub);
         };
         StreamArgs a{};
-        a.X = fx24 ? static_cast<const void *>(static_cast<const char *>(c.X) + kFx24Header) : c.X;
-        a.X2 = fx24 ? static_cast<const void *>(static_cast<const char *>(c.X) + fx24_lo_offset(nx)) : nullptr;
+        a.X = fx20 ? static_cast<const void *>(static_cast<const char *>(c.X) + kFx20Header) : c.X;
+        a.X2 = fx20 ? static_cast<const void *>(static_cast<const char *>(c.X) + fx20_lo_offset(nx)) : nullptr;
         a.Ug = ucol(gmode);
         a.ldu = pb.R;
         int k = 0;
@@ -216,7 +216,7 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
         a.n_chunks = p.n_chunks;
         a.n_groups = p.groups;
         const int64_t contig = kcontig ? a.Ig : a.In;  // extent of the contiguous mode
-        if (fx24)  // planes are 256-byte aligned; runs of 16 (K-contiguous) or 4 (M-contiguous) elements
+        if (fx20)  // planes are 256-byte aligned; runs of 16 (K-contiguous) or 4 (M-contiguous) elements
             a.vec_ok = kcontig ? (contig % 16 == 0) : (contig % 4 == 0);
         else
             a.vec_ok = ((contig * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
@@ -345,12 +345,12 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
             return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps factor operand " + std::to_string(k));
         c.U[m] = U[k];
     }
-    const bool fx24 = o.precision == DEINSUM_PREC_FX24;
-    const size_t xbytes = fx24 ? static_cast<size_t>(fx24_bytes(nx)) : static_cast<size_t>(nx) * xb;
+    const bool fx20 = o.precision == DEINSUM_PREC_FX20;
+    const size_t xbytes = fx20 ? static_cast<size_t>(fx20_bytes(nx)) : static_cast<size_t>(nx) * xb;
     if (overlaps(M, mbytes, X, xbytes)) return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps X");
     if (reinterpret_cast<uintptr_t>(M) % dtype_bytes(o.out_dtype) != 0 ||
-        reinterpret_cast<uintptr_t>(X) % (fx24 ? 256 : xb) != 0)
-        return fail(DEINSUM_ERR_INVALID_ARG, fx24 ? "an FX24 X buffer must be 256-byte aligned"
+        reinterpret_cast<uintptr_t>(X) % (fx20 ? 256 : xb) != 0)
+        return fail(DEINSUM_ERR_INVALID_ARG, fx20 ? "an FX20 X buffer must be 256-byte aligned"
                                                   : "X and M must be aligned to their element size");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (dims[n] == 0) { clear_error(); return DEINSUM_OK; }

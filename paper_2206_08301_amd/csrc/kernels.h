@@ -39,22 +39,22 @@ __device__ __forceinline__ V ld_stream(const V *p)
     else return *p;
 }
 
-enum PrecisionId { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_FX24 = 4 };
+enum PrecisionId { P_FP64 = 0, P_FP32 = 1, P_BF16 = 2, P_BF16X3 = 3, P_FX20 = 4 };
 
-// FX24 storage of X: signed 24-bit integers m with X = m * 2^e (one exponent e
-// per tensor), kept as a 16-bit plane (m >> 8) and an 8-bit plane (m & 255)
-// behind a header; see include/deinsum.h.
-constexpr int kFx24Header = 256;
-__host__ __device__ inline int64_t fx24_align(int64_t b) { return (b + 255) / 256 * 256; }
-__host__ __device__ inline int64_t fx24_lo_offset(int64_t count) { return kFx24Header + fx24_align(2 * count); }
-__host__ __device__ inline int64_t fx24_bytes(int64_t count) { return fx24_lo_offset(count) + fx24_align(count); }
-struct Fx24Header {
-    uint32_t magic;   // kFx24Magic
-    int32_t exp2;     // X = m * 2^exp2
+// FX20 storage of X: X ~ (256 h + l) * 2^e with one exponent e per tensor,
+// h in [-2048, 2048] kept as FP16 bit patterns (exact) and l in [-128, 127] as
+// int8, in two planes behind a header; see include/deinsum.h.
+constexpr int kFx20Header = 256;
+__host__ __device__ inline int64_t fx20_align(int64_t b) { return (b + 255) / 256 * 256; }
+__host__ __device__ inline int64_t fx20_lo_offset(int64_t count) { return kFx20Header + fx20_align(2 * count); }
+__host__ __device__ inline int64_t fx20_bytes(int64_t count) { return fx20_lo_offset(count) + fx20_align(count); }
+struct Fx20Header {
+    uint32_t magic;   // kFx20Magic
+    int32_t exp2;     // X ~ (256 h + l) * 2^exp2
     int64_t count;
     double max_abs;   // max |X| before encoding
 };
-constexpr uint32_t kFx24Magic = 0x34325846u;  // "FX24"
+constexpr uint32_t kFx20Magic = 0x30325846u;  // "FX20"
 
 // Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)
@@ -93,6 +93,12 @@ __device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f32x4 mfma_f16(u16x8 a, u16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0,
+                                                  0);
+}
 __device__ __forceinline__ f32x4 mfma_bf16(u16x8 a, u16x8 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
@@ -105,7 +111,7 @@ template <> __device__ __forceinline__ int tile_row<P_FP64>(int lane, int v) { r
 template <> __device__ __forceinline__ int tile_row<P_FP32>(int lane, int v) { return 4 * (lane >> 4) + v; }
 template <> __device__ __forceinline__ int tile_row<P_BF16>(int lane, int v) { return 4 * (lane >> 4) + v; }
 template <> __device__ __forceinline__ int tile_row<P_BF16X3>(int lane, int v) { return 4 * (lane >> 4) + v; }
-template <> __device__ __forceinline__ int tile_row<P_FX24>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ __forceinline__ int tile_row<P_FX20>(int lane, int v) { return 4 * (lane >> 4) + v; }
 
 // ----------------------------------------------------------------- launch interface
 // Modes other than the free mode and the matrix-core mode ("outer" modes), in

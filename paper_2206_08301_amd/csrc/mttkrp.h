@@ -24,8 +24,8 @@ enum StreamLayout {
 //     chunk = rest, or (order 1) chunk = (u / n_kgroups) % n_chunks, tile = rest;
 //   wave w: slice kgroup*wk + w % wk of mode g, outer sub-range w / wk of the chunk.
 struct StreamArgs {
-    const void *X;       // FX24: the 16-bit plane
-    const void *X2;      // FX24: the 8-bit plane (unused otherwise)
+    const void *X;       // FX20: the 16-bit plane
+    const void *X2;      // FX20: the 8-bit plane (unused otherwise)
     const void *Ug;      // factor of mode g, column block applied; row stride ldu
     int64_t ldu;
     OuterDesc od;        // modes other than n and g
@@ -59,10 +59,10 @@ deinsum_status launch_mttkrp_stream(const StreamKernelInfo &k, const StreamArgs 
                                     hipStream_t s);
 deinsum_status launch_outer_weights(const OuterDesc &od, int64_t O, int64_t ldu, int ncols, int ldw, int prec,
                                     double *W, hipStream_t s);
-// hx (FX24 only, else null): the header of X; the sums are scaled by 2^(exp2 - 8), and
-// a header that is not an FX24 header of nx elements turns the output into NaN.
+// hx (FX20 only, else null): the header of X; the sums are scaled by 2^exp2, and
+// a header that is not an FX20 header of nx elements turns the output into NaN.
 deinsum_status launch_reduce_partials(const double *P, int64_t nparts, int64_t n_tiles, int tile_rows,
                                       int cols_pad, int64_t rows, int ncols, void *out, int out_dtype,
-                                      int64_t ldo, const Fx24Header *hx, int64_t nx, hipStream_t s);
+                                      int64_t ldo, const Fx20Header *hx, int64_t nx, hipStream_t s);
 
 }  // namespace deinsum

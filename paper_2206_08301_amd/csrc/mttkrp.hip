@@ -68,7 +68,7 @@ template <typename OT>
 __global__ void __launch_bounds__(256)
 reduce_partials_kernel(const double *__restrict__ P, int64_t nparts, int64_t n_tiles, int tile_rows,
                        int cols_pad, int64_t rows, int ncols, OT *__restrict__ out, int64_t ldo,
-                       const Fx24Header *__restrict__ hx, int64_t nx)
+                       const Fx20Header *__restrict__ hx, int64_t nx)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= rows * ncols) return;
@@ -89,8 +89,7 @@ reduce_partials_kernel(const double *__restrict__ P, int64_t nparts, int64_t n_t
         for (int u = 0; u < 8; ++u) s += v[u];
     }
     for (; q < nparts; ++q) s += p[q * part_stride];
-    if (hx) s = (hx->magic == kFx24Magic && hx->count == nx) ? ldexp(s, hx->exp2 - 8)  // kernels ran on m * 2^8
-                                                              : __builtin_nan("");
+    if (hx) s = (hx->magic == kFx20Magic && hx->count == nx) ? ldexp(s, hx->exp2) : __builtin_nan("");
     out[i * ldo + col] = from_f64<OT>(s);
 }
 
@@ -120,9 +119,9 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16X3, L_KCONTIG, 1, 4, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 4, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_KCONTIG, 1, 3, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 3, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 3, 1, 2),
     SK(P_BF16X3, L_KCONTIG, 1, 1, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 1, 1, 3),
-    // FX24: runs of 16 elements per chunk (32 bytes of the 16-bit plane, 16 of the 8-bit plane)
-    SK(P_FX24, L_KCONTIG, 1, 32, 1, 3), SK(P_FX24, L_KCONTIG, 2, 32, 1, 3), SK(P_FX24, L_KCONTIG, 4, 16, 1, 2),
-    SK(P_FX24, L_KCONTIG, 1, 16, 1, 3), SK(P_FX24, L_KCONTIG, 2, 16, 1, 3),
+    // FX20: FP16 matrix cores; runs of 16 elements per chunk (32 bytes of the FP16 plane, 16 of the int8 plane)
+    SK(P_FX20, L_KCONTIG, 1, 4, 1, 3), SK(P_FX20, L_KCONTIG, 2, 4, 1, 3), SK(P_FX20, L_KCONTIG, 4, 2, 1, 2),
+    SK(P_FX20, L_KCONTIG, 1, 2, 1, 3), SK(P_FX20, L_KCONTIG, 2, 2, 1, 3),
     // M-contiguous: NI K-steps of 4*KE rows; MT output indices per lane
     // (FP64: non-temporal X loads first -- they keep the per-K-step factor rows cached, 1.50 -> 1.37 ms
     //  for the 1024^3 R=24 last mode; the K-contiguous kernels lose with them and keep plain loads.)
@@ -133,8 +132,9 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
     SKN(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SKN(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SKN(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
-    // FX24: four output indices per lane (8 bytes of the 16-bit plane, 4 of the 8-bit plane per row)
-    SK(P_FX24, L_MCONTIG, 1, 8, 4, 3), SK(P_FX24, L_MCONTIG, 2, 8, 4, 2),
+    // FX20: FP32 matrix cores on decoded values, four output indices per lane (8 bytes of the FP16 plane,
+    // 4 of the int8 plane per row)
+    SK(P_FX20, L_MCONTIG, 1, 8, 4, 3), SK(P_FX20, L_MCONTIG, 2, 8, 4, 2),
 };
 #undef SK
 #undef SKN
@@ -162,7 +162,7 @@ deinsum_status launch_outer_weights(const OuterDesc &od, int64_t O, int64_t ldu,
 
 deinsum_status launch_reduce_partials(const double *P, int64_t nparts, int64_t n_tiles, int tile_rows,
                                       int cols_pad, int64_t rows, int ncols, void *out, int out_dtype,
-                                      int64_t ldo, const Fx24Header *hx, int64_t nx, hipStream_t s)
+                                      int64_t ldo, const Fx20Header *hx, int64_t nx, hipStream_t s)
 {
     const int64_t total = rows * ncols;
     const unsigned grid = static_cast<unsigned>((total + 255) / 256);

@@ -24,7 +24,13 @@ constexpr int64_t kMinSteps = 8;         // outer steps per wave
 constexpr int kWaves = 4;
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-int ke_of(int prec) { return (prec == P_BF16 || prec == P_BF16X3) ? 8 : 1; }
+// K values per lane per matrix-core instruction.
+int ke_of(int prec, int layout)
+{
+    if (prec == P_BF16 || prec == P_BF16X3) return 8;
+    if (prec == P_FX20) return layout == L_KCONTIG ? 8 : 1;
+    return 1;
+}
 
 }  // namespace
 
@@ -47,7 +53,7 @@ deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *ke
         if (m != n && m != g) O *= pb.dims[m];
     p.ni = kernel->ni;
     p.mt = kernel->mt;
-    p.slice = 4 * p.ni * ke_of(pb.prec);
+    p.slice = 4 * p.ni * ke_of(pb.prec, layout);
     p.tile_rows = (layout == L_KCONTIG) ? 16 : 16 * p.mt;
     const int64_t nks = cdiv(Ig, p.slice);
     p.waves = kWaves;
@@ -115,7 +121,7 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
     for (int i = 0; i < count; ++i) {
         const StreamKernelInfo &k = table[i];
         if (k.prec != pb.prec || k.layout != layout || k.nt != nt) continue;
-        const int64_t slice = 4LL * k.ni * ke_of(pb.prec);
+        const int64_t slice = 4LL * k.ni * ke_of(pb.prec, layout);
         const int64_t padded = cdiv(Ig, slice) * slice;
         if (!best || padded < best_padded) {
             best = &k;
@@ -127,7 +133,7 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
         for (int i = 0; i < count; ++i) {
             const StreamKernelInfo &k = table[i];
             if (k.prec != pb.prec || k.layout != layout || k.nt != w) continue;
-            const int64_t slice = 4LL * k.ni * ke_of(pb.prec);
+            const int64_t slice = 4LL * k.ni * ke_of(pb.prec, layout);
             const int64_t padded = cdiv(Ig, slice) * slice;
             if (!best || padded < best_padded) {
                 best = &k;

@@ -20,8 +20,8 @@ template <> struct PrecTypes<P_FP64> { using XT = double; using DT = f64x4; stat
 template <> struct PrecTypes<P_FP32> { using XT = float;  using DT = f32x4; static constexpr int KE = 1; };
 template <> struct PrecTypes<P_BF16> { using XT = bf16_t; using DT = f32x4; static constexpr int KE = 8; };
 template <> struct PrecTypes<P_BF16X3> { using XT = float; using DT = f32x4; static constexpr int KE = 8; };
-// FX24: the ring holds raw words of the two planes; values are decoded per step.
-template <> struct PrecTypes<P_FX24> { using XT = uint32_t; using DT = f32x4; static constexpr int KE = 1; };
+// FX20: the ring holds raw words of the two planes; values are decoded per step.
+template <> struct PrecTypes<P_FX20> { using XT = uint32_t; using DT = f32x4; static constexpr int KE = 8; };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -110,14 +110,16 @@ struct Odometer {
 template <int P, int L, int NI, int MT>
 struct Tile {
     using XT = typename PrecTypes<P>::XT;
-    static constexpr int KE = PrecTypes<P>::KE;
+    // FX20: FP16 matrix cores (8 K slots per lane) when K is the contiguous mode,
+    // FP32 matrix cores (1 K slot) when the free mode is.
+    static constexpr int KE = (P == P_FX20 && L == L_MCONTIG) ? 1 : PrecTypes<P>::KE;
     static constexpr int SLICE = 4 * NI * KE;
-    static constexpr int VE = (P == P_BF16X3) ? 8 : (P == P_FX24 ? 16 : static_cast<int>(16 / sizeof(XT)));
+    static constexpr int VE = (P == P_BF16X3) ? 8 : (P == P_FX20 ? 16 : static_cast<int>(16 / sizeof(XT)));
     static constexpr int XN = (L == L_KCONTIG) ? NI * KE : NI * KE * MT;  // X elements per lane per step
-    // ring words per step: FX24 keeps XN/2 words of the 16-bit plane, then XN/4 of the 8-bit plane
-    static constexpr int XW = (P == P_FX24) ? XN / 2 + XN / 4 : XN;
+    // ring words per step: FX20 keeps XN/2 words of the 16-bit plane, then XN/4 of the 8-bit plane
+    static constexpr int XW = (P == P_FX20) ? XN / 2 + XN / 4 : XN;
     static_assert(L == L_MCONTIG || (NI * KE) % VE == 0, "K-contiguous runs must be whole chunks");
-    static_assert(P != P_FX24 || L == L_KCONTIG || MT % 4 == 0, "FX24 M-contiguous tiles hold 4k indices");
+    static_assert(P != P_FX20 || L == L_KCONTIG || MT % 4 == 0, "FX20 M-contiguous tiles hold 4k indices");
 
     __device__ static int pos_k(int t, int g) { return (t / VE) * 4 * VE + g * VE + t % VE; }
     __device__ static int pos_m(int q, int g, int e) { return q * 4 * KE + g * KE + e; }
@@ -186,20 +188,20 @@ __device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
     }
 }
 
-// FX24 tile of a lane: element offset `off` of its first element in both
+// FX20 tile of a lane: element offset `off` of its first element in both
 // planes (same layout as load_tile).  Element t of the run lands in 16-bit
 // word t/2 (half t%2) and in 8-bit word XN/2 + t/4 (byte t%4).
 template <int L, int NI, int MT, bool FULL, bool NTL>
-__device__ __forceinline__ void load_tile_fx24(uint32_t *x, int64_t off, const StreamArgs &a, int64_t lim,
+__device__ __forceinline__ void load_tile_fx20(uint32_t *x, int64_t off, const StreamArgs &a, int64_t lim,
                                                int ivalid, int g)
 {
-    using TL = Tile<P_FX24, L, NI, MT>;
+    using TL = Tile<P_FX20, L, NI, MT>;
     constexpr int XN = TL::XN;
     const uint16_t *__restrict__ H = static_cast<const uint16_t *>(a.X) + off;
     const uint8_t *__restrict__ B = static_cast<const uint8_t *>(a.X2) + off;
     uint32_t *xh = x, *xl = x + XN / 2;
     if constexpr (L == L_KCONTIG) {
-        constexpr int NCH = NI / TL::VE;  // chunks of 16 elements, 4*16 apart in the slice
+        constexpr int NCH = (NI * TL::KE) / TL::VE;  // chunks of 16 elements, 4*16 apart in the slice
 #pragma unroll
         for (int j = 0; j < NCH; ++j) {
             const int64_t e0 = static_cast<int64_t>(j) * 4 * TL::VE;
@@ -225,7 +227,7 @@ __device__ __forceinline__ void load_tile_fx24(uint32_t *x, int64_t off, const S
             }
         }
     } else {
-        static_assert(MT == 4, "FX24 M-contiguous tiles are 4 indices wide");
+        static_assert(MT == 4, "FX20 M-contiguous tiles are 4 indices wide");
 #pragma unroll
         for (int q = 0; q < NI; ++q) {
             const int r = TL::pos_m(q, g, 0);
@@ -251,16 +253,31 @@ __device__ __forceinline__ void load_tile_fx24(uint32_t *x, int64_t off, const S
     }
 }
 
-// Element t of an FX24 ring slot as FP32: v_perm assembles (m16 << 16) | (m8 << 8),
-// i.e. m * 2^8 as a 32-bit integer, exactly representable in FP32.
+// Element t of an FX20 ring slot as FP32: 256 h + l, exact (|.| <= 2^19).
 template <int XN>
-__device__ __forceinline__ float fx24_value(const uint32_t *x, int t)
+__device__ __forceinline__ float fx20_value(const uint32_t *x, int t)
 {
-    const uint32_t h = x[t >> 1];
-    const uint32_t l = x[XN / 2 + (t >> 2)];
-    const uint32_t sel = 0x0Cu | (static_cast<uint32_t>(t & 3) << 8) | (static_cast<uint32_t>(4 + 2 * (t & 1)) << 16) |
-                         (static_cast<uint32_t>(5 + 2 * (t & 1)) << 24);
-    return static_cast<float>(static_cast<int32_t>(__builtin_amdgcn_perm(h, l, sel)));
+    const uint16_t hb = static_cast<uint16_t>(x[t >> 1] >> (16 * (t & 1)));
+    const int8_t lb = static_cast<int8_t>(x[XN / 2 + (t >> 2)] >> (8 * (t & 3)));
+    return 256.0f * static_cast<float>(__builtin_bit_cast(_Float16, hb)) + static_cast<float>(lb);
+}
+
+// FP16 operands of an FX20 K-contiguous instruction q (elements 8q .. 8q+7 of the
+// run): h is the FP16 plane itself; l enters as the FP16 value 1152 + l, built
+// from the int8 byte b as the bit pattern 0x6400 | (b ^ 0x80) (1024 + (l + 128);
+// the 1152 offset is removed with the factor column sum).
+template <int XN>
+__device__ __forceinline__ void fx20_operands(const uint32_t *x, int q, u16x8 &ah, u16x8 &al)
+{
+    __builtin_memcpy(&ah, x + 4 * q, 16);
+    uint32_t o[4];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+        const uint32_t b = x[XN / 2 + 2 * q + w] ^ 0x80808080u;
+        o[2 * w] = __builtin_amdgcn_perm(0u, b, 0x0C010C00u) | 0x64006400u;
+        o[2 * w + 1] = __builtin_amdgcn_perm(0u, b, 0x0C030C02u) | 0x64006400u;
+    }
+    __builtin_memcpy(&al, o, 16);
 }
 
 template <int L, int NT, int MT>
@@ -325,16 +342,65 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     }
 
     // Register-resident slice of U^g for every K slot of every instruction.
+    constexpr bool FX16 = (P == P_FX20 && L == L_KCONTIG);  // FX20 on FP16 matrix cores
     double fr64[(P == P_FP64) ? NI * NT : 1];
-    float fr32[(P == P_FP32 || P == P_FX24) ? NI * NT : 1];
-    u16x8 frh[(P >= P_BF16) ? NI * NT : 1];
-    u16x8 frl[(P == P_BF16X3) ? NI * NT : 1];
+    float fr32[(P == P_FP32 || (P == P_FX20 && !FX16)) ? NI * NT : 1];
+    u16x8 frh[(P == P_BF16 || P == P_BF16X3 || FX16) ? NI * NT : 1];
+    u16x8 frl[(P == P_BF16X3 || FX16) ? NI * NT : 1];
+    // FX16: each factor column of the slice is scaled by 2^-k (|u| < 1) before
+    // the FP16 split; cs = 2^k, and sh = the column sum of the FP16 hi parts
+    // (removes the 1152 offset of the int8 operand).
+    double cs[FX16 ? NT : 1], sh[FX16 ? NT : 1];
+    if constexpr (FX16) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int col = nt * 16 + c;
+            float mx = 0.0f;
+#pragma unroll
+            for (int q = 0; q < NI; ++q)
+#pragma unroll
+                for (int e = 0; e < KE; ++e) {
+                    const int pos = TL::slot_pos(q, g, e);
+                    if (pos < slice_avail && col < a.ncols)
+                        mx = fmaxf(mx, fabsf(static_cast<const float *>(a.Ug)[(s0 + pos) * a.ldu + col]));
+                }
+            mx = fmaxf(mx, __shfl_xor(mx, 16));
+            mx = fmaxf(mx, __shfl_xor(mx, 32));
+            int k = 0;
+            if (mx > 0.0f) (void)frexpf(mx, &k);  // mx < 2^k
+            double psum = 0.0;
+#pragma unroll
+            for (int q = 0; q < NI; ++q) {
+                u16x8 hi, lo;
+#pragma unroll
+                for (int e = 0; e < KE; ++e) {
+                    const int pos = TL::slot_pos(q, g, e);
+                    const float v = (pos < slice_avail && col < a.ncols)
+                                        ? ldexpf(static_cast<const float *>(a.Ug)[(s0 + pos) * a.ldu + col], -k)
+                                        : 0.0f;
+                    const _Float16 h = static_cast<_Float16>(v);
+                    const _Float16 l = static_cast<_Float16>(v - static_cast<float>(h));
+                    hi[e] = __builtin_bit_cast(uint16_t, h);
+                    lo[e] = __builtin_bit_cast(uint16_t, l);
+                    psum += static_cast<double>(static_cast<float>(h));
+                }
+                frh[q * NT + nt] = hi;
+                frl[q * NT + nt] = lo;
+            }
+            psum += __shfl_xor(psum, 16);
+            psum += __shfl_xor(psum, 32);
+            cs[nt] = ldexp(1.0, k);
+            sh[nt] = psum;
+        }
+    }
 #pragma unroll
     for (int q = 0; q < NI; ++q)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int col = nt * 16 + c;
-            if constexpr (KE == 1) {
+            if constexpr (FX16) {
+                // built above
+            } else if constexpr (KE == 1) {
                 const int pos = TL::slot_pos(q, g, 0);
                 const double v = (pos < slice_avail && col < a.ncols) ? ld_u(a.Ug, (s0 + pos) * a.ldu + col, P) : 0.0;
                 if constexpr (P == P_FP64) fr64[q * NT + nt] = v;
@@ -365,6 +431,31 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
 
     // One step: stage 1 on the matrix cores, then the Hadamard fold (stage 2).
     auto step = [&](const XT *x, const double *wv) {
+        if constexpr (FX16) {
+            // sum_k (256 h + l) u' = 256 (h.uh + h.ul) + ((1152 + l).uh - 1152 sum uh)
+            DT dh[NT], dl[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) dh[nt] = dl[nt] = DT{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < NI; ++q) {
+                u16x8 ah, al;
+                fx20_operands<XN>(x, q, ah, al);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    dh[nt] = mfma_f16(ah, frh[q * NT + nt], dh[nt]);
+                    dh[nt] = mfma_f16(ah, frl[q * NT + nt], dh[nt]);
+                    dl[nt] = mfma_f16(al, frh[q * NT + nt], dl[nt]);
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const double wc = wv[nt] * cs[nt];
+                const double off = 1152.0 * sh[nt];
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[0][nt][v] += (256.0 * static_cast<double>(dh[nt][v]) + (static_cast<double>(dl[nt][v]) - off)) * wc;
+            }
+        } else {
         DT d[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -385,8 +476,8 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
                         if constexpr (P == P_FP64) d[mt][nt] = mfma_f64(xa, fr64[q * NT + nt], d[mt][nt]);
                         else d[mt][nt] = mfma_f32(xa, fr32[q * NT + nt], d[mt][nt]);
                     }
-                } else if constexpr (P == P_FX24) {
-                    const float xa = fx24_value<TL::XN>(x, (L == L_KCONTIG) ? q : q * MT + mt);
+                } else if constexpr (P == P_FX20) {
+                    const float xa = fx20_value<TL::XN>(x, q * MT + mt);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) d[mt][nt] = mfma_f32(xa, fr32[q * NT + nt], d[mt][nt]);
                 } else if constexpr (P == P_BF16) {
@@ -418,6 +509,7 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[mt][nt][v] += static_cast<double>(d[mt][nt][v]) * wv[nt];
+        }
     };
 
     // Outer range of this wave.
@@ -441,8 +533,8 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
         auto issue = [&](int slot) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) wb[slot][nt] = a.W[lo * a.ldw + nt * 16 + c];
-            if constexpr (P == P_FX24)
-                load_tile_fx24<L, NI, MT, FULL, XNT>(xb[slot], od.off + xlane, a, lim, ivalid, g);
+            if constexpr (P == P_FX20)
+                load_tile_fx20<L, NI, MT, FULL, XNT>(xb[slot], od.off + xlane, a, lim, ivalid, g);
             else
                 load_tile<P, L, NI, MT, FULL, XNT>(xb[slot], X + od.off + xlane, a, g, lim, ivalid);
             od.next(a.od);

@@ -1,5 +1,5 @@
-"""GPU tests of the FX24 form: the encoder against a plain numpy encoding of the
-format, and MTTKRP on FX24 storage against the FP64 oracle."""
+"""GPU tests of the FX20 form (20-bit fixed point in an FP16 and an int8 plane): the encoder against a plain numpy encoding of the
+format, and MTTKRP on FX20 storage against the FP64 oracle."""
 import numpy as np
 import pytest
 import torch
@@ -18,13 +18,16 @@ def dn():
 
 
 def encode_np(x):
-    """The FX24 format written out in numpy: e, m (int24), planes."""
+    """The FX20 format written out in numpy: e, m, h (FP16 plane), l (int8 plane)."""
     x = np.asarray(x, dtype=np.float64).ravel()
     mx = float(np.max(np.abs(x))) if x.size else 0.0
-    e = (np.frexp(mx)[1] - 23) if mx > 0 else 0
-    m = np.clip(np.rint(np.ldexp(x, -e)), -(2 ** 23), 2 ** 23 - 1).astype(np.int64)
-    hi = ((m >> 8) & 0xFFFF).astype(np.uint16)
-    lo = (m & 255).astype(np.uint8)
+    e = (np.frexp(mx)[1] - 19) if mx > 0 else 0
+    m = np.clip(np.rint(np.ldexp(x, -e)), -(2 ** 19), 2 ** 19).astype(np.int64)
+    h = np.floor_divide(m + 128, 256)
+    l = m - 256 * h
+    assert np.all(np.abs(h) <= 2048) and np.all((l >= -128) & (l <= 127))
+    hi = h.astype(np.float16).view(np.uint16)
+    lo = l.astype(np.int8).view(np.uint8)
     return e, mx, m, hi, lo
 
 
@@ -44,21 +47,21 @@ def test_encoder_matches_format(dn, shape, scale, dtype):
     x = rng.uniform(-scale, scale, shape)
     if dtype == torch.float32:
         x = x.astype(np.float32).astype(np.float64)
-    f = dn.to_fx24(to_dev(x, dtype))
+    f = dn.to_fx20(to_dev(x, dtype))
     torch.cuda.synchronize()
     e, mx, m, hi, lo = encode_np(x)
     h = f.header()
-    assert h["magic"] == 0x34325846 and h["exp2"] == e and h["count"] == x.size and h["max_abs"] == mx
+    assert h["magic"] == 0x30325846 and h["exp2"] == e and h["count"] == x.size and h["max_abs"] == mx
     ghi, glo = planes(dn, f)
     assert np.array_equal(ghi, hi) and np.array_equal(glo, lo)
-    # decoding the numpy planes gives back m, and |x - m 2^e| <= 2^(e-1)
-    dec = (ghi.astype(np.int16).astype(np.int64) << 8) | glo.astype(np.int64)
+    # decoding the planes gives back m = 256 h + l, and |x - m 2^e| <= 2^(e-1)
+    dec = 256 * ghi.view(np.float16).astype(np.int64) + glo.view(np.int8).astype(np.int64)
     assert np.array_equal(dec, m)
     assert np.max(np.abs(x.ravel() - np.ldexp(dec.astype(np.float64), e))) <= 2.0 ** (e - 1)
 
 
 def test_encoder_zero_tensor(dn):
-    f = dn.to_fx24(torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda"))
+    f = dn.to_fx20(torch.zeros((4, 4, 4), dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     h = f.header()
     assert h["exp2"] == 0 and h["max_abs"] == 0.0
@@ -70,61 +73,61 @@ SHAPES = [((64, 64, 64), 24), ((37, 45, 96), 20), ((16, 21, 130), 40), ((6, 5, 7
 
 
 @pytest.mark.parametrize("dims,R", SHAPES)
-def test_fx24_integer_exact(dn, oracle_mod, synth, dims, R):
+def test_fx20_integer_exact(dn, oracle_mod, synth, dims, R):
     """Integer X in [-2, 2] and integer factors: encoding and arithmetic are exact."""
     rng = np.random.default_rng(sum(dims))
     X = rng.integers(-2, 3, dims).astype(np.float64)
     U = [rng.integers(-2, 3, (d, R)).astype(np.float64) for d in dims]
-    f = dn.to_fx24(to_dev(X))
+    f = dn.to_fx20(to_dev(X))
     for n in range(len(dims)):
-        flush(f"fx24 exact dims={dims} R={R} n={n}")
+        flush(f"fx20 exact dims={dims} R={R} n={n}")
         ops = [to_dev(U[m], torch.float32) for m in range(len(dims)) if m != n]
-        M = dn.mttkrp(mttkrp_spec(len(dims), n), f, ops, precision="fx24", out_dtype=torch.float64)
+        M = dn.mttkrp(mttkrp_spec(len(dims), n), f, ops, precision="fx20", out_dtype=torch.float64)
         torch.cuda.synchronize()
         ref = oracle_mod.mttkrp(X, [None if m == n else U[m] for m in range(len(dims))], n)
         assert np.array_equal(M.cpu().numpy(), ref), (dims, n)
 
 
 @pytest.mark.parametrize("dims,R", SHAPES)
-def test_fx24_uniform_error(dn, oracle_mod, dims, R):
+def test_fx20_uniform_error(dn, oracle_mod, dims, R):
     rng = np.random.default_rng(7 + sum(dims))
     X = rng.uniform(-1, 1, dims)
     U = [rng.standard_normal((d, R)).astype(np.float32).astype(np.float64) for d in dims]
-    f = dn.to_fx24(to_dev(X))
+    f = dn.to_fx20(to_dev(X))
     for n in range(len(dims)):
         ops = [to_dev(U[m], torch.float32) for m in range(len(dims)) if m != n]
-        M = dn.mttkrp(mttkrp_spec(len(dims), n), f, ops, precision="fx24", out_dtype=torch.float64)
+        M = dn.mttkrp(mttkrp_spec(len(dims), n), f, ops, precision="fx20", out_dtype=torch.float64)
         torch.cuda.synchronize()
         ref = oracle_mod.mttkrp(X, [None if m == n else U[m] for m in range(len(dims))], n)
         err = nrel(M.cpu().numpy(), ref)
-        flush(f"fx24 uniform dims={dims} R={R} n={n}: {err:.2e}")
-        assert err <= 1e-6
+        flush(f"fx20 uniform dims={dims} R={R} n={n}: {err:.2e}")
+        assert err <= 4e-6  # X carries 20 bits: about 1e-6 for uniform data
 
 
-def test_fx24_header_mismatch_gives_nan(dn):
+def test_fx20_header_mismatch_gives_nan(dn):
     """A buffer encoded for more elements than the call's dims is rejected in the output."""
     X = torch.rand((8, 8, 9), dtype=torch.float64, device="cuda")
-    f = dn.to_fx24(X)
-    small = dn.FX24(f.buf, (8, 8, 8))  # fewer elements than encoded: reads stay inside the buffer
+    f = dn.to_fx20(X)
+    small = dn.FX20(f.buf, (8, 8, 8))  # fewer elements than encoded: reads stay inside the buffer
     U = [torch.rand((8, 4), dtype=torch.float32, device="cuda") for _ in range(2)]
-    M = dn.mttkrp(mttkrp_spec(3, 0), small, U, precision="fx24", out_dtype=torch.float64)
+    M = dn.mttkrp(mttkrp_spec(3, 0), small, U, precision="fx20", out_dtype=torch.float64)
     torch.cuda.synchronize()
     assert torch.isnan(M).all()
 
 
-def test_fx24_tuned_plan(dn, oracle_mod):
+def test_fx20_tuned_plan(dn, oracle_mod):
     rng = np.random.default_rng(99)
     dims, R = (96, 80, 128), 24
     X = rng.uniform(-1, 1, dims)
     U = [rng.standard_normal((d, R)).astype(np.float32).astype(np.float64) for d in dims]
-    f = dn.to_fx24(to_dev(X))
+    f = dn.to_fx20(to_dev(X))
     for n in (0, 2):
         ops = [to_dev(U[m], torch.float32) for m in range(3) if m != n]
         dn.tune_clear()
-        rep = dn.tune_mttkrp(mttkrp_spec(3, n), f, ops, precision="fx24", out_dtype=torch.float64, reps=2)
+        rep = dn.tune_mttkrp(mttkrp_spec(3, n), f, ops, precision="fx20", out_dtype=torch.float64, reps=2)
         assert rep.tuned_us > 0
-        M = dn.mttkrp(mttkrp_spec(3, n), f, ops, precision="fx24", out_dtype=torch.float64)
+        M = dn.mttkrp(mttkrp_spec(3, n), f, ops, precision="fx20", out_dtype=torch.float64)
         torch.cuda.synchronize()
         ref = oracle_mod.mttkrp(X, [None if m == n else U[m] for m in range(3)], n)
-        assert nrel(M.cpu().numpy(), ref) <= 1e-6
+        assert nrel(M.cpu().numpy(), ref) <= 4e-6
     dn.tune_clear()
