@@ -216,8 +216,8 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
         a.n_chunks = p.n_chunks;
         a.n_groups = p.groups;
         const int64_t contig = kcontig ? a.Ig : a.In;  // extent of the contiguous mode
-        if (fx20)  // planes are 256-byte aligned; runs of 16 (K-contiguous) or 4 (M-contiguous) elements
-            a.vec_ok = kcontig ? (contig % 16 == 0) : (contig % 4 == 0);
+        if (fx20)  // planes are 256-byte aligned; runs of 16 (K-contiguous) or MT (M-contiguous) elements
+            a.vec_ok = kcontig ? (contig % 16 == 0) : (contig % p.mt == 0);
         else
             a.vec_ok = ((contig * xb) % 16 == 0) && (reinterpret_cast<uintptr_t>(c.X) % 16 == 0);
         a.P = static_cast<double *>(ws);

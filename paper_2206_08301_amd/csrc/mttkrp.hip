@@ -132,9 +132,11 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
     SKN(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SKN(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SKN(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
-    // FX20: FP32 matrix cores on decoded values, four output indices per lane (8 bytes of the FP16 plane,
-    // 4 of the int8 plane per row)
-    SK(P_FX20, L_MCONTIG, 1, 8, 4, 3), SK(P_FX20, L_MCONTIG, 2, 8, 4, 2),
+    // FX20: 8 slice rows per instruction, MT output indices per lane (2*MT bytes of the FP16 plane and
+    // MT of the int8 plane per row)
+    SK(P_FX20, L_MCONTIG, 2, 1, 4, 2), SKN(P_FX20, L_MCONTIG, 2, 1, 4, 2), SK(P_FX20, L_MCONTIG, 2, 1, 2, 3),
+    SKN(P_FX20, L_MCONTIG, 2, 1, 2, 3), SK(P_FX20, L_MCONTIG, 2, 2, 2, 2), SK(P_FX20, L_MCONTIG, 1, 1, 4, 3),
+    SK(P_FX20, L_MCONTIG, 1, 2, 2, 3), SKN(P_FX20, L_MCONTIG, 1, 2, 2, 3), SK(P_FX20, L_MCONTIG, 4, 1, 1, 2),
 };
 #undef SK
 #undef SKN

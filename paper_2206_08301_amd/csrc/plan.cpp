@@ -27,9 +27,8 @@ int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // K values per lane per matrix-core instruction.
 int ke_of(int prec, int layout)
 {
-    if (prec == P_BF16 || prec == P_BF16X3) return 8;
-    if (prec == P_FX20) return layout == L_KCONTIG ? 8 : 1;
-    return 1;
+    (void)layout;
+    return (prec == P_BF16 || prec == P_BF16X3 || prec == P_FX20) ? 8 : 1;
 }
 
 }  // namespace

@@ -110,16 +110,18 @@ struct Odometer {
 template <int P, int L, int NI, int MT>
 struct Tile {
     using XT = typename PrecTypes<P>::XT;
-    // FX20: FP16 matrix cores (8 K slots per lane) when K is the contiguous mode,
-    // FP32 matrix cores (1 K slot) when the free mode is.
-    static constexpr int KE = (P == P_FX20 && L == L_MCONTIG) ? 1 : PrecTypes<P>::KE;
+    static constexpr int KE = PrecTypes<P>::KE;
     static constexpr int SLICE = 4 * NI * KE;
     static constexpr int VE = (P == P_BF16X3) ? 8 : (P == P_FX20 ? 16 : static_cast<int>(16 / sizeof(XT)));
     static constexpr int XN = (L == L_KCONTIG) ? NI * KE : NI * KE * MT;  // X elements per lane per step
-    // ring words per step: FX20 keeps XN/2 words of the 16-bit plane, then XN/4 of the 8-bit plane
-    static constexpr int XW = (P == P_FX20) ? XN / 2 + XN / 4 : XN;
+    // FX20 ring words per step.  K-contiguous: XN/2 words of the FP16 plane, then XN/4
+    // of the int8 plane.  M-contiguous: per slice row (q, g, e), FHW words holding its
+    // MT FP16 values, then one word per row holding its MT int8 values.
+    static constexpr int FHW = (MT + 1) / 2;
+    static constexpr int FROWS = NI * KE;  // slice rows of one lane per step (M-contiguous)
+    static constexpr int XW = (P != P_FX20) ? XN : (L == L_KCONTIG ? XN / 2 + XN / 4 : FROWS * (FHW + 1));
     static_assert(L == L_MCONTIG || (NI * KE) % VE == 0, "K-contiguous runs must be whole chunks");
-    static_assert(P != P_FX20 || L == L_KCONTIG || MT % 4 == 0, "FX20 M-contiguous tiles hold 4k indices");
+    static_assert(P != P_FX20 || L == L_KCONTIG || MT <= 4, "FX20 M-contiguous tiles hold at most 4 indices");
 
     __device__ static int pos_k(int t, int g) { return (t / VE) * 4 * VE + g * VE + t % VE; }
     __device__ static int pos_m(int q, int g, int e) { return q * 4 * KE + g * KE + e; }
@@ -227,45 +229,52 @@ __device__ __forceinline__ void load_tile_fx20(uint32_t *x, int64_t off, const S
             }
         }
     } else {
-        static_assert(MT == 4, "FX20 M-contiguous tiles are 4 indices wide");
+        // Row (q, g, e) of the slice: MT FP16 values and MT int8 values of the lane's indices.
+        constexpr int FHW = TL::FHW, HW = TL::FROWS * FHW;
 #pragma unroll
-        for (int q = 0; q < NI; ++q) {
-            const int r = TL::pos_m(q, g, 0);
-            const int64_t e0 = static_cast<int64_t>(r) * a.stride_g;
-            if constexpr (FULL) {
-                const uint64_t h = ld_stream<NTL>(reinterpret_cast<const uint64_t *>(H + e0));
-                const uint32_t l = ld_stream<NTL>(reinterpret_cast<const uint32_t *>(B + e0));
-                xh[2 * q] = static_cast<uint32_t>(h);
-                xh[2 * q + 1] = static_cast<uint32_t>(h >> 32);
-                xl[q] = l;
-            } else {
-                xh[2 * q] = xh[2 * q + 1] = xl[q] = 0;
-                if (r < lim) {
+        for (int q = 0; q < NI; ++q)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        if (i < ivalid) {
-                            xh[2 * q + i / 2] |= static_cast<uint32_t>(H[e0 + i]) << (16 * (i % 2));
-                            xl[q] |= static_cast<uint32_t>(B[e0 + i]) << (8 * i);
-                        }
+            for (int e = 0; e < TL::KE; ++e) {
+                const int rr = q * TL::KE + e;  // ring row
+                const int r = TL::pos_m(q, g, e);
+                const int64_t e0 = static_cast<int64_t>(r) * a.stride_g;
+                uint32_t *wh = xh + rr * FHW;
+                uint32_t &wl = x[HW + rr];
+                if constexpr (FULL) {
+                    if constexpr (MT == 4) {
+                        const uint64_t h = ld_stream<NTL>(reinterpret_cast<const uint64_t *>(H + e0));
+                        wh[0] = static_cast<uint32_t>(h);
+                        wh[1] = static_cast<uint32_t>(h >> 32);
+                        wl = ld_stream<NTL>(reinterpret_cast<const uint32_t *>(B + e0));
+                    } else if constexpr (MT == 2) {
+                        wh[0] = ld_stream<NTL>(reinterpret_cast<const uint32_t *>(H + e0));
+                        wl = ld_stream<NTL>(reinterpret_cast<const uint16_t *>(B + e0));
+                    } else {
+                        wh[0] = H[e0];
+                        wl = B[e0];
+                    }
+                } else {
+#pragma unroll
+                    for (int w = 0; w < FHW; ++w) wh[w] = 0;
+                    wl = 0;
+                    if (r < lim) {
+#pragma unroll
+                        for (int i = 0; i < MT; ++i)
+                            if (i < ivalid) {
+                                wh[i / 2] |= static_cast<uint32_t>(H[e0 + i]) << (16 * (i % 2));
+                                wl |= static_cast<uint32_t>(B[e0 + i]) << (8 * i);
+                            }
+                    }
                 }
             }
-        }
     }
 }
 
-// Element t of an FX20 ring slot as FP32: 256 h + l, exact (|.| <= 2^19).
-template <int XN>
-__device__ __forceinline__ float fx20_value(const uint32_t *x, int t)
-{
-    const uint16_t hb = static_cast<uint16_t>(x[t >> 1] >> (16 * (t & 1)));
-    const int8_t lb = static_cast<int8_t>(x[XN / 2 + (t >> 2)] >> (8 * (t & 3)));
-    return 256.0f * static_cast<float>(__builtin_bit_cast(_Float16, hb)) + static_cast<float>(lb);
-}
-
 // FP16 operands of an FX20 K-contiguous instruction q (elements 8q .. 8q+7 of the
-// run): h is the FP16 plane itself; l enters as the FP16 value 1152 + l, built
-// from the int8 byte b as the bit pattern 0x6400 | (b ^ 0x80) (1024 + (l + 128);
-// the 1152 offset is removed with the factor column sum).
+// run): h is the FP16 plane itself; l enters as the FP16 value (1152 + l) / 256,
+// exact, built from the int8 byte b as the bit pattern 0x4400 | (b ^ 0x80)
+// (4 + (l + 128) / 256), so h*u and the l part accumulate in one register set;
+// the 1152/256 offset is removed with the factor column sum.
 template <int XN>
 __device__ __forceinline__ void fx20_operands(const uint32_t *x, int q, u16x8 &ah, u16x8 &al)
 {
@@ -274,10 +283,31 @@ __device__ __forceinline__ void fx20_operands(const uint32_t *x, int q, u16x8 &a
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
         const uint32_t b = x[XN / 2 + 2 * q + w] ^ 0x80808080u;
-        o[2 * w] = __builtin_amdgcn_perm(0u, b, 0x0C010C00u) | 0x64006400u;
-        o[2 * w + 1] = __builtin_amdgcn_perm(0u, b, 0x0C030C02u) | 0x64006400u;
+        o[2 * w] = __builtin_amdgcn_perm(0u, b, 0x0C010C00u) | 0x44004400u;
+        o[2 * w + 1] = __builtin_amdgcn_perm(0u, b, 0x0C030C02u) | 0x44004400u;
     }
     __builtin_memcpy(&al, o, 16);
+}
+
+// FP16 operands of an FX20 M-contiguous instruction q for output index mt of the
+// lane: K slot e is slice row (q, g, e); the same int8 offset encoding as above.
+template <int NI, int MT>
+__device__ __forceinline__ void fx20_operands_m(const uint32_t *x, int q, int mt, u16x8 &ah, u16x8 &al)
+{
+    constexpr int KE = 8, FHW = (MT + 1) / 2, HW = NI * KE * FHW;
+    const int hs = 2 * (mt & 1);
+    const uint32_t selh = static_cast<uint32_t>(hs) | (static_cast<uint32_t>(hs + 1) << 8) |
+                          (static_cast<uint32_t>(hs + 4) << 16) | (static_cast<uint32_t>(hs + 5) << 24);
+    const uint32_t sell = static_cast<uint32_t>(mt) | (0x0Cu << 8) | (static_cast<uint32_t>(mt + 4) << 16) | (0x0Cu << 24);
+    uint32_t oh[4], ol[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int r0 = q * KE + 2 * j, r1 = r0 + 1;
+        oh[j] = __builtin_amdgcn_perm(x[r1 * FHW + mt / 2], x[r0 * FHW + mt / 2], selh);
+        ol[j] = __builtin_amdgcn_perm(x[HW + r1] ^ 0x80808080u, x[HW + r0] ^ 0x80808080u, sell) | 0x44004400u;
+    }
+    __builtin_memcpy(&ah, oh, 16);
+    __builtin_memcpy(&al, ol, 16);
 }
 
 template <int L, int NT, int MT>
@@ -342,9 +372,9 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     }
 
     // Register-resident slice of U^g for every K slot of every instruction.
-    constexpr bool FX16 = (P == P_FX20 && L == L_KCONTIG);  // FX20 on FP16 matrix cores
+    constexpr bool FX16 = (P == P_FX20);  // FX20 runs on FP16 matrix cores
     double fr64[(P == P_FP64) ? NI * NT : 1];
-    float fr32[(P == P_FP32 || (P == P_FX20 && !FX16)) ? NI * NT : 1];
+    float fr32[(P == P_FP32) ? NI * NT : 1];
     u16x8 frh[(P == P_BF16 || P == P_BF16X3 || FX16) ? NI * NT : 1];
     u16x8 frl[(P == P_BF16X3 || FX16) ? NI * NT : 1];
     // FX16: each factor column of the slice is scaled by 2^-k (|u| < 1) before
@@ -432,28 +462,35 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     // One step: stage 1 on the matrix cores, then the Hadamard fold (stage 2).
     auto step = [&](const XT *x, const double *wv) {
         if constexpr (FX16) {
-            // sum_k (256 h + l) u' = 256 (h.uh + h.ul) + ((1152 + l).uh - 1152 sum uh)
-            DT dh[NT], dl[NT];
+            // sum_k (256 h + l) u' = 256 (h.uh + h.ul + ((1152 + l)/256).uh) - 1152 sum uh
+            DT dh[MT][NT];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) dh[nt] = dl[nt] = DT{0, 0, 0, 0};
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int q = 0; q < NI; ++q) {
-                u16x8 ah, al;
-                fx20_operands<XN>(x, q, ah, al);
+                for (int nt = 0; nt < NT; ++nt) dh[mt][nt] = DT{0, 0, 0, 0};
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    dh[nt] = mfma_f16(ah, frh[q * NT + nt], dh[nt]);
-                    dh[nt] = mfma_f16(ah, frl[q * NT + nt], dh[nt]);
-                    dl[nt] = mfma_f16(al, frh[q * NT + nt], dl[nt]);
+            for (int q = 0; q < NI; ++q)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    u16x8 ah, al;
+                    if constexpr (L == L_KCONTIG) fx20_operands<XN>(x, q, ah, al);
+                    else fx20_operands_m<NI, MT>(x, q, mt, ah, al);
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        dh[mt][nt] = mfma_f16(ah, frh[q * NT + nt], dh[mt][nt]);
+                        dh[mt][nt] = mfma_f16(ah, frl[q * NT + nt], dh[mt][nt]);
+                        dh[mt][nt] = mfma_f16(al, frh[q * NT + nt], dh[mt][nt]);
+                    }
                 }
-            }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const double wc = wv[nt] * cs[nt];
                 const double off = 1152.0 * sh[nt];
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[0][nt][v] += (256.0 * static_cast<double>(dh[nt][v]) + (static_cast<double>(dl[nt][v]) - off)) * wc;
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[mt][nt][v] += (256.0 * static_cast<double>(dh[mt][nt][v]) - off) * wc;
             }
         } else {
         DT d[MT][NT];
@@ -476,10 +513,6 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
                         if constexpr (P == P_FP64) d[mt][nt] = mfma_f64(xa, fr64[q * NT + nt], d[mt][nt]);
                         else d[mt][nt] = mfma_f32(xa, fr32[q * NT + nt], d[mt][nt]);
                     }
-                } else if constexpr (P == P_FX20) {
-                    const float xa = fx20_value<TL::XN>(x, q * MT + mt);
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) d[mt][nt] = mfma_f32(xa, fr32[q * NT + nt], d[mt][nt]);
                 } else if constexpr (P == P_BF16) {
                     u16x8 xa;
 #pragma unroll
