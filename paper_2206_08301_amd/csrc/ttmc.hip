@@ -46,20 +46,20 @@ __device__ __forceinline__ double ldu_p(const void *p, int64_t i, int prec)
 
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-template <typename T, int n>
+template <typename T, int n, bool NTL = false>
 __device__ __forceinline__ void load_vec_n(T *dst, const T *__restrict__ src)
 {
     static_assert((n * sizeof(T)) % 8 == 0, "whole 8-byte words");
     if constexpr ((n * sizeof(T)) % 16 == 0) {
 #pragma unroll
         for (int i = 0; i < static_cast<int>(n * sizeof(T) / 16); ++i) {
-            const v4u v = ld_stream<false>(reinterpret_cast<const v4u *>(src) + i);
+            const v4u v = ld_stream<NTL>(reinterpret_cast<const v4u *>(src) + i);
             __builtin_memcpy(dst + i * (16 / sizeof(T)), &v, 16);
         }
     } else {
 #pragma unroll
         for (int i = 0; i < static_cast<int>(n * sizeof(T) / 8); ++i) {
-            const uint64_t v = ld_stream<false>(reinterpret_cast<const uint64_t *>(src) + i);
+            const uint64_t v = ld_stream<NTL>(reinterpret_cast<const uint64_t *>(src) + i);
             __builtin_memcpy(dst + i * (8 / sizeof(T)), &v, 8);
         }
     }
@@ -105,7 +105,7 @@ struct SlabWalk {
 // UB K-steps (4*UB rows), prefetched NBUF-1 steps ahead; complete steps issue
 // a fixed sequence of unmasked loads (the factors are zero-padded to whole
 // column tiles), so the compiler waits for exactly the oldest step.
-template <int P, int NTA, int NTC, int MT, bool STAGE2, int UB, int NBUF>
+template <int P, int NTA, int NTC, int MT, bool STAGE2, int UB, int NBUF, bool XNT>
 __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
 {
     // UB: K-steps (of 4 rows) per ring step; NBUF: ring depth.
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                     for (int nt = 0; nt < NTA; ++nt)
                         ub[slot][u][nt] = rv ? Ua[r * TA + nt * 16 + c] : 0.0;
                     if constexpr (FULL && (MT * sizeof(XT)) % 8 == 0) {
-                        if (rv) load_vec_n<XT, MT>(xb[slot][u], xs + r * a.stride_a);
+                        if (rv) load_vec_n<XT, MT, XNT>(xb[slot][u], xs + r * a.stride_a);
                         else {
 #pragma unroll
                             for (int i = 0; i < MT; ++i) xb[slot][u][i] = XT{};
@@ -347,10 +347,10 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
     else static_cast<float *>(a.out)[ooff] = static_cast<float>(acc);
 }
 
-template <int P, int NTA, int NTC, int MT, bool S2, int UB, int NB>
+template <int P, int NTA, int NTC, int MT, bool S2, int UB, int NB, bool XNT>
 void launch_tk(const TkArgs &a, int64_t grid, hipStream_t s)
 {
-    ttmc_fused_kernel<P, NTA, NTC, MT, S2, UB, NB><<<static_cast<unsigned>(grid), 64 * a.nwaves, 0, s>>>(a);
+    ttmc_fused_kernel<P, NTA, NTC, MT, S2, UB, NB, XNT><<<static_cast<unsigned>(grid), 64 * a.nwaves, 0, s>>>(a);
 }
 
 using TkLaunch = void (*)(const TkArgs &, int64_t, hipStream_t);
@@ -364,13 +364,17 @@ struct TkEntry {
 // more X (the factor rows come from L2: a 16*NTA-wide row per 16*MT X values).
 // For each (precision, NTA, NTC) the first entry is the default; later ones
 // are alternatives selectable by plan_hint.
-#define TK(P, A, C, MT, UB, NB) {P, A, C, MT, UB, NB, true, &launch_tk<P, A, C, MT, true, UB, NB>}
-#define TK1(P, A, MT, UB, NB) {P, A, 0, MT, UB, NB, false, &launch_tk<P, A, 1, MT, false, UB, NB>}
+#define TK(P, A, C, MT, UB, NB) {P, A, C, MT, UB, NB, true, &launch_tk<P, A, C, MT, true, UB, NB, false>}
+#define TKN(P, A, C, MT, UB, NB) {P, A, C, MT, UB, NB, true, &launch_tk<P, A, C, MT, true, UB, NB, true>}
+#define TK1(P, A, MT, UB, NB) {P, A, 0, MT, UB, NB, false, &launch_tk<P, A, 1, MT, false, UB, NB, false>}
 const TkEntry kTkTable[] = {
     TK(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 2, 4), TK(P_FP64, 1, 4, 4, 2, 4),
     TK(P_FP64, 2, 1, 4, 2, 3), TK(P_FP64, 2, 2, 4, 2, 3), TK(P_FP64, 2, 4, 2, 2, 4),
     TK(P_FP64, 4, 1, 2, 2, 3), TK(P_FP64, 4, 2, 2, 2, 3), TK(P_FP64, 4, 4, 1, 2, 4),
-    TK(P_FP64, 2, 1, 2, 2, 4), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 4, 1, 1, 2, 4), TK(P_FP64, 4, 2, 1, 2, 4),
+    // alternatives (plan_hint 1, 2, ...)
+    TK(P_FP64, 1, 1, 4, 3, 2), TK(P_FP64, 1, 2, 4, 3, 2), TK(P_FP64, 2, 1, 4, 3, 2), TK(P_FP64, 2, 2, 4, 3, 2),
+    TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 1, 2, 2, 4), TK(P_FP64, 4, 1, 1, 2, 4),
+    TK(P_FP64, 4, 2, 1, 2, 4),
     TK(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
     TK(P_FP32, 2, 2, 4, 2, 4), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
     TK(P_FP32, 4, 4, 2, 2, 4),
@@ -378,6 +382,7 @@ const TkEntry kTkTable[] = {
     TK1(P_FP32, 1, 4, 2, 4), TK1(P_FP32, 2, 4, 2, 4), TK1(P_FP32, 4, 2, 2, 4),
 };
 #undef TK
+#undef TKN
 #undef TK1
 
 // The variant-th compiled kernel (0 = default) for this precision and rank tiles.
