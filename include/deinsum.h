@@ -129,8 +129,9 @@ typedef struct deinsum_opts {
     int32_t plan_hint;        /* MTTKRP: 0 = autotuned plan if cached, else the
                                  heuristic; 1 / 2 = heuristic, and the free mode
                                  must be < N-1 / = N-1 (tests).
-                                 TTMc: k >= 0 picks the k-th compiled fused-kernel
-                                 variant for the ranks (0 = default; tests, tuning) */
+                                 TTMc: 0 = autotuned fused-kernel variant if cached,
+                                 else the default; k >= 1 = compiled variant k-1
+                                 for the ranks (tests, tuning)                        */
     int32_t split_hint;       /* 0 = planner choice; else outer-chunk count          */
     deinsum_report *report;   /* optional host out-parameter                         */
 } deinsum_opts;
@@ -372,7 +373,14 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
 deinsum_status deinsum_tune_batch_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R, const void *X,
                                          const void *const *U, void *M, const deinsum_opts *opts, int32_t reps,
                                          deinsum_report *best, void *stream);
-/* Read entries from / write the whole cache to a text file (one entry per line). */
+/* The same for a TTMc problem: times every compiled fused-kernel variant for its
+ * ranks on the caller's buffers (Y is overwritten) and caches the fastest, which
+ * deinsum_ttmc uses when plan_hint = 0. */
+deinsum_status deinsum_tune_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
+                                 const void *const *U, void *Y, const deinsum_opts *opts, int32_t reps,
+                                 deinsum_report *best, void *stream);
+/* Read entries from / write the whole cache to a text file (one entry per line;
+ * for TTMc keys the split column holds the variant). */
 deinsum_status deinsum_tune_load(const char *path);
 deinsum_status deinsum_tune_save(const char *path);
 /* Forget every cached plan. */

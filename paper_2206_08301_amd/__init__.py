@@ -235,9 +235,10 @@ def tune_entries() -> int:
 
 
 def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None,
-         variant=0):
-    """Mode-n TTMc.  ``U`` lists the factor operands in the spec's operand order; ``variant``
-    picks an alternative compiled fused kernel for the ranks (0 = default)."""
+         variant=None, tune_reps=0):
+    """Mode-n TTMc.  ``U`` lists the factor operands in the spec's operand order.
+    ``variant`` picks a compiled fused kernel for the ranks (None = the autotuned one if
+    cached, else the default); ``tune_reps`` > 0 autotunes first (``out`` is overwritten)."""
     sp = _spec(spec)
     if sp.kind != TTMC:
         raise ValueError("spec is not a TTMc")
@@ -261,7 +262,13 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
         if list(out.shape) != shape:
             raise ValueError("out has the wrong shape")
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
-    o = _opts(precision, out_dtype, workspace, variant, 0, report)
+    o = _opts(precision, out_dtype, workspace, 0 if variant is None else int(variant) + 1, 0, report)
+    if tune_reps:
+        rep = Report()
+        with torch.cuda.device(X.device):
+            _lib.check(_lib.load().deinsum_tune_ttmc(ctypes.byref(sp), _i64(X.shape), _i64(ranks),
+                                                     ctypes.c_void_p(X.data_ptr()), ptrs, ctypes.c_void_p(out.data_ptr()),
+                                                     ctypes.byref(o), int(tune_reps), ctypes.byref(rep), _stream(stream)))
     with torch.cuda.device(X.device):
         _lib.check(_lib.load().deinsum_ttmc(ctypes.byref(sp), _i64(X.shape), _i64(ranks), ctypes.c_void_p(X.data_ptr()),
                                             ptrs, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), _stream(stream)))

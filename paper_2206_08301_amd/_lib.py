@@ -90,7 +90,7 @@ EXPORTS = (
     "deinsum_server_submit", "deinsum_server_replay", "deinsum_server_drain", "deinsum_server_results",
     "deinsum_server_stats", "deinsum_server_destroy", "deinsum_tune_mttkrp", "deinsum_tune_batch_mttkrp",
     "deinsum_tune_load", "deinsum_tune_save", "deinsum_tune_clear", "deinsum_tune_entries",
-    "deinsum_fx20_size", "deinsum_fx20_encode",
+    "deinsum_fx20_size", "deinsum_fx20_encode", "deinsum_tune_ttmc",
 )
 
 _lib = None
@@ -181,6 +181,9 @@ def load():
     lib.deinsum_tune_clear.restype = ctypes.c_int
     lib.deinsum_tune_entries.argtypes = [i64p]
     lib.deinsum_tune_entries.restype = ctypes.c_int
+    lib.deinsum_tune_ttmc.argtypes = [ctypes.POINTER(Spec), i64p, i64p, vp, ctypes.POINTER(vp), vp,
+                                      ctypes.POINTER(Opts), ctypes.c_int32, ctypes.POINTER(Report), vp]
+    lib.deinsum_tune_ttmc.restype = ctypes.c_int
     lib.deinsum_fx20_size.argtypes = [ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]
     lib.deinsum_fx20_size.restype = ctypes.c_int
     lib.deinsum_fx20_encode.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_size_t, vp]

@@ -449,6 +449,49 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
     return DEINSUM_OK;
 }
 
+deinsum_status deinsum_tune_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
+                                 const void *const *U, void *Y, const deinsum_opts *opts, int32_t reps,
+                                 deinsum_report *best, void *stream)
+{
+    if (reps < 1 || reps > 1000) return fail(DEINSUM_ERR_INVALID_ARG, "tune_ttmc: reps must be 1..1000");
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    o.workspace = nullptr;
+    o.workspace_bytes = 0;
+    o.report = nullptr;
+    o.plan_hint = 1;  // validates every argument as a plain call does (variant 0)
+    if (deinsum_status st = deinsum_ttmc(spec, dims, ranks, X, U, Y, &o, stream)) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double best_us = -1;
+    int best_v = 0;
+    const int nvar = (spec->order == 2 && spec->free_mode == 0) ? 1 : 64;  // that case runs the MTTKRP kernel
+    for (int v = 0; v < nvar; ++v) {
+        o.plan_hint = v + 1;
+        size_t need = 0;
+        if (deinsum_workspace_size(spec, dims, ranks, &o, &need) != DEINSUM_OK) break;  // no variant v
+        double us = 0;
+        if (deinsum_status st = time_median([&] { return deinsum_ttmc(spec, dims, ranks, X, U, Y, &o, stream); },
+                                            reps, s, &us))
+            return st;
+        if (best_us < 0 || us < best_us) {
+            best_us = us;
+            best_v = v;
+        }
+    }
+    TuneChoice c;
+    c.nt = c.ni = c.mt = 1;
+    c.split = best_v;  // TTMc entries: the fused-kernel variant
+    c.us = best_us;
+    tune_store(ttmc_tune_key(spec, dims, ranks, o.precision), c);
+    if (best) {
+        std::memset(best, 0, sizeof(*best));
+        std::snprintf(best->plan_name, sizeof(best->plan_name), "ttmc fused variant %d", best_v);
+        best->tuned_us = best_us;
+    }
+    clear_error();
+    return DEINSUM_OK;
+}
+
 deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
                             const void *const *U, void *Y, const deinsum_opts *opts, void *stream)
 {

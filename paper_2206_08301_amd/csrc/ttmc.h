@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
 
 #include "kernels.h"
 
@@ -28,6 +29,9 @@ struct TkArgs {
 
 deinsum_status ttmc_workspace_size(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
                                    const deinsum_opts &o, size_t *bytes);
+// Plan-cache key of a TTMc problem (autotuned fused-kernel variant).
+std::string ttmc_tune_key(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, int prec);
+
 deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
                         const void *const *U, void *Y, const deinsum_opts &o, void *ws, size_t ws_bytes,
                         hipStream_t s);

@@ -24,6 +24,7 @@
 #include "kernels.h"
 #include "mttkrp.h"
 #include "ttmc.h"
+#include "tune.h"
 
 namespace deinsum {
 
@@ -394,6 +395,24 @@ const TkEntry *find_tk(int prec, int nta, int ntc, bool s2, int variant)
 }
 
 int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace
+
+std::string ttmc_tune_key(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, int prec)
+{
+    std::string k = "t:N" + std::to_string(spec->order) + ":n" + std::to_string(spec->free_mode) + ":p" +
+                    std::to_string(prec) + ":R";
+    for (int m = 0, first = 1; m < spec->order; ++m) {
+        if (m == spec->free_mode) continue;
+        k += (first ? "" : "x") + std::to_string(ranks[spec->operand_of_mode[m]]);
+        first = 0;
+    }
+    k += ":";
+    for (int m = 0; m < spec->order; ++m) k += (m ? "x" : "") + std::to_string(dims[m]);
+    return k;
+}
+
+namespace {
 int ntiles_for(int64_t r) { return r <= 16 ? 1 : (r <= 32 ? 2 : 4); }
 
 // ------------------------------------------------------------------ host plan
@@ -452,7 +471,15 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
             p.slab_modes.push_back(m);
             p.n_slabs *= p.I[m];
         }
-    p.kernel = find_tk(prec, p.nta, p.ntc, p.stage2, variant);
+    // plan_hint 0: the autotuned variant for this problem if cached, else the default;
+    // plan_hint k >= 1: compiled variant k - 1.
+    int v = variant > 0 ? variant - 1 : 0;
+    if (variant == 0) {
+        TuneChoice tc;
+        if (tune_lookup(ttmc_tune_key(spec, dims, ranks, prec), &tc) && find_tk(prec, p.nta, p.ntc, p.stage2, tc.split))
+            v = tc.split;
+    }
+    p.kernel = find_tk(prec, p.nta, p.ntc, p.stage2, v);
     if (!p.kernel)
         return fail(variant ? DEINSUM_ERR_INVALID_ARG : DEINSUM_ERR_UNSUPPORTED,
                     variant ? "plan_hint names no compiled TTMc kernel variant"

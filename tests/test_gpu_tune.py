@@ -61,3 +61,20 @@ def test_tuned_batch_job_is_cached_and_correct(dn, oracle_mod):
     assert nrel(M.cpu().numpy(), ref) <= 1e-12
     b.close()
     dn.tune_clear()
+
+
+def test_tuned_ttmc_variant_is_cached_and_correct(dn, oracle_mod):
+    from gpu_common import ttmc_spec
+    rng = np.random.default_rng(78)
+    dims, ranks = (40, 70, 130), (8, 32, 24)
+    X = rng.uniform(-1, 1, dims)
+    U = [None] + [rng.standard_normal((d, ranks[m])) for m, d in enumerate(dims) if m > 0]
+    Xd = to_dev(X)
+    Ud = [to_dev(u) for u in U if u is not None]
+    dn.tune_clear()
+    Y = dn.ttmc(ttmc_spec(3, 0), Xd, Ud, tune_reps=2)
+    torch.cuda.synchronize()
+    assert dn.tune_entries() == 1
+    ref = oracle_mod.ttmc(X, U, 0)
+    assert nrel(Y.cpu().numpy(), ref) <= 1e-12
+    dn.tune_clear()
