@@ -40,9 +40,10 @@ def parse_args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-serving", action="store_true", help="skip the CP-ALS serving measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic plans instead of autotuning first")
+    ap.add_argument("--no-more", action="store_true", help="skip the order-5 MTTKRP and order-4 TTMc workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: run one plain 1 GiB device copy first (calibrates HBM byte counters)")
-    ap.add_argument("--only", default="", help="profiling: run just one form (fp64|fx20|fp32|bf16|bf16x3|ttmc|serving)")
+    ap.add_argument("--only", default="", help="profiling: run just one part (fp64|fx20|fp32|bf16|bf16x3|ttmc|more|serving)")
     return ap.parse_args()
 
 
@@ -68,6 +69,94 @@ def measured_traffic():
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return int(mb.group(1)) if h.hexdigest() == mh.group(1) else None
+
+
+def event_median(torch, stream, fn, reps=10):
+    """Median duration (ms) of `reps` back-to-back calls, HIP events on the launch stream."""
+    fn()
+    torch.cuda.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+    evs[0].record(stream)
+    for k in range(reps):
+        fn()
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    return statistics.median(evs[k].elapsed_time(evs[k + 1]) for k in range(reps))
+
+
+def more_workloads(dn, synth, torch, stream, tune):
+    """Order-5 MTTKRP (80^5, R=24, modes 0 and 2: FP64, FP32, FX20) and order-4 TTMc
+    (192^4, ranks 16, mode 0: FP64, FP32).  Reduced forms report their error against
+    the FP64 result of the same call (which the GPU tests pin to the oracle)."""
+    dev = torch.device("cuda:0")
+    out = {}
+    D5, R5 = (80,) * 5, 24
+    X = torch.empty(D5, dtype=torch.float64, device=dev)
+    dn.synth_fill(X, synth.config_seed(3, 0))
+    U = [torch.from_numpy(synth.normal_factor(synth.config_seed(3, 1 + m), 80, R5)).to(dev) for m in range(5)]
+    X32 = torch.empty(D5, dtype=torch.float32, device=dev)
+    dn.convert(X, X32)
+    Xf = dn.to_fx20(X)
+    nx = 80 ** 5
+    res = {}
+    for n in (0, 2):
+        spec = "abcde," + ",".join(f"{l}z" for i, l in enumerate("abcde") if i != n) + "->" + "abcde"[n] + "z"
+        ops = [U[m] for m in range(5) if m != n]
+        ops32 = [u.float() for u in ops]
+        M64 = torch.empty((80, R5), dtype=torch.float64, device=dev)
+        M32 = torch.empty((80, R5), dtype=torch.float64, device=dev)
+        row = {}
+        for form, Xp, opsp in (("fp64", X, ops), ("fp32", X32, ops32), ("fx20", Xf, ops32)):
+            M = M64 if form == "fp64" else M32
+            if tune:
+                dn.tune_mttkrp(spec, Xp, opsp, precision=form, out=M, reps=2)
+            t = event_median(torch, stream, lambda: dn.mttkrp(spec, Xp, opsp, precision=form, out=M))
+            xb = {"fp64": 8, "fp32": 4, "fx20": 3}[form]
+            byts = nx * xb + 4 * 80 * R5 * (8 if form == "fp64" else 4) + 80 * R5 * 8
+            flops = 2 * nx * R5 + 2 * (nx // 80) * R5 * 3
+            e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
+                 "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "GFLOP/s": round(flops / (t / 1e3) / 1e9, 1)}
+            if form != "fp64":
+                torch.cuda.synchronize()
+                e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
+                e["rel_err_vs_fp64"] = float((M - M64).norm() / M64.norm())
+            row[form] = e
+        res[str(n)] = row
+        print(f"[bench] order-5 mode {n}: {row}", file=sys.stderr, flush=True)
+    out["mttkrp_order5"] = {"workload": "MTTKRP order 5, X 80^5 FP64 (26.2 GB), R=24, modes 0 and 2", "modes": res}
+    del X, X32, Xf, U
+    torch.cuda.empty_cache()
+
+    D4, R4 = (192,) * 4, 16
+    X = torch.empty(D4, dtype=torch.float64, device=dev)
+    dn.synth_fill(X, synth.config_seed(4, 0))
+    B = [torch.from_numpy(synth.orthonormal_factor(synth.config_seed(4, 1 + m), 192, R4)).to(dev) for m in (1, 2, 3)]
+    X32 = torch.empty(D4, dtype=torch.float32, device=dev)
+    dn.convert(X, X32)
+    Y64 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
+    Y32 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
+    row = {}
+    nx = 192 ** 4
+    for form, Xp, Bp, Y in (("fp64", X, B, Y64), ("fp32", X32, [b.float() for b in B], Y32)):
+        if tune:
+            dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y, tune_reps=2)
+        t = event_median(torch, stream, lambda: dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y))
+        xb = 8 if form == "fp64" else 4
+        byts = nx * xb + 3 * 192 * R4 * xb + 192 * R4 ** 3 * 8
+        e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
+             "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if form != "fp64":
+            torch.cuda.synchronize()
+            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
+            e["rel_err_vs_fp64"] = float((Y - Y64).norm() / Y64.norm())
+        row[form] = e
+    print(f"[bench] ttmc order-4: {row}", file=sys.stderr, flush=True)
+    out["ttmc_order4"] = {"workload": "TTMc order 4 mode 0, X 192^4 FP64 (10.9 GB), ranks 16, orthonormal factors",
+                          "forms": row}
+    del X, X32, Y64, Y32
+    torch.cuda.empty_cache()
+    return out
 
 
 def alg_counts(dims, R, n, xbytes):
@@ -287,10 +376,16 @@ def main():
                               "GFLOP/s": round(f / (t / 1e3) / 1e9, 1), "max_rel_err_sampled": max(errs)}
     result["checks"] = checks
 
+    # ---- the other single-GPU workloads: order-5 MTTKRP and order-4 TTMc (extras)
+    if not args.no_extras and not args.no_more and (not args.only or args.only == "more"):
+        X = None  # the 1024^3 tensor is no longer needed
+        torch.cuda.empty_cache()
+        result["more_workloads"] = more_workloads(dn, synth, torch, stream, tune)
+
     # ---- CP-ALS serving: continuous batching vs one launch per request (extras)
     if not args.no_extras and not args.no_serving and (not args.only or args.only == "serving"):
         from paper_2206_08301_amd import serve_workload
-        del X
+        X = None
         torch.cuda.empty_cache()
         result["serving"] = serve_workload.measure(
             dn, repeats=int(os.environ.get("BENCH_SERVE_REPEATS", "3")),

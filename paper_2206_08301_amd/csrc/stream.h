@@ -167,7 +167,8 @@ __device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
 #pragma unroll
         for (int j = 0; j < NCH; ++j) {
             if constexpr (FULL) load_vec<XT, TL::VE, NTL>(x + j * TL::VE, base + j * 4 * TL::VE);
-            else load_contig<XT, TL::VE>(x + j * TL::VE, base + j * 4 * TL::VE, false, lim - j * 4 * TL::VE);
+            else  // whole chunks in range still take vector loads
+                load_contig<XT, TL::VE>(x + j * TL::VE, base + j * 4 * TL::VE, a.vec_ok != 0, lim - j * 4 * TL::VE);
         }
     } else {
         // base = slice row 0 + first output index of the lane; lim = slice rows available
@@ -216,16 +217,25 @@ __device__ __forceinline__ void load_tile_fx20(uint32_t *x, int64_t off, const S
                 __builtin_memcpy(xl + j * 4, &l0, 16);
             } else {
                 const int64_t valid = lim - e0;
+                if (a.vec_ok && valid >= TL::VE) {  // a whole chunk in range: vector loads
+                    const u32x4 h0 = reinterpret_cast<const u32x4 *>(H + e0)[0];
+                    const u32x4 h1 = reinterpret_cast<const u32x4 *>(H + e0)[1];
+                    const u32x4 l0 = reinterpret_cast<const u32x4 *>(B + e0)[0];
+                    __builtin_memcpy(xh + j * 8, &h0, 16);
+                    __builtin_memcpy(xh + j * 8 + 4, &h1, 16);
+                    __builtin_memcpy(xl + j * 4, &l0, 16);
+                } else {
 #pragma unroll
-                for (int w = 0; w < 8; ++w) xh[j * 8 + w] = 0;
+                    for (int w = 0; w < 8; ++w) xh[j * 8 + w] = 0;
 #pragma unroll
-                for (int w = 0; w < 4; ++w) xl[j * 4 + w] = 0;
+                    for (int w = 0; w < 4; ++w) xl[j * 4 + w] = 0;
 #pragma unroll
-                for (int i = 0; i < TL::VE; ++i)
-                    if (i < valid) {
-                        xh[j * 8 + i / 2] |= static_cast<uint32_t>(H[e0 + i]) << (16 * (i % 2));
-                        xl[j * 4 + i / 4] |= static_cast<uint32_t>(B[e0 + i]) << (8 * (i % 4));
-                    }
+                    for (int i = 0; i < TL::VE; ++i)
+                        if (i < valid) {
+                            xh[j * 8 + i / 2] |= static_cast<uint32_t>(H[e0 + i]) << (16 * (i % 2));
+                            xl[j * 4 + i / 4] |= static_cast<uint32_t>(B[e0 + i]) << (8 * (i % 4));
+                        }
+                }
             }
         }
     } else {
