@@ -21,6 +21,7 @@
 #include <chrono>
 #include <cstring>
 #include <deque>
+#include <condition_variable>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -108,7 +109,8 @@ struct deinsum_server {
     deinsum_server_config cfg{};
     std::vector<STensor> tensors;
     std::vector<SRequest> reqs;
-    std::mutex mu;                    // guards reqs growth and `submitted`
+    std::mutex mu;                    // guards reqs growth, `submitted` and `error`
+    std::condition_variable cv;       // signalled on submission and on stop
     std::deque<int64_t> submitted;
     std::thread sched;
     std::atomic<bool> stop{false};
@@ -131,6 +133,8 @@ struct deinsum_server {
     // per request
     std::deque<std::pair<int64_t, hipEvent_t>> inflight;
     std::vector<hipEvent_t> event_pool;
+    void *ws = nullptr;  // per request: the server's own MTTKRP workspace (stream-ordered reuse)
+    size_t ws_bytes = 0;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -139,6 +143,7 @@ namespace {
 
 void set_failed(deinsum_server *s, const std::string &msg)
 {
+    std::lock_guard<std::mutex> lk(s->mu);
     s->error = msg;
     s->failed = true;
 }
@@ -237,7 +242,15 @@ bool launch_one(deinsum_server *s, int64_t r)
     deinsum_opts_init(&o);
     o.precision = t.prec;
     o.out_dtype = DEINSUM_F64;
-    if (deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]) != DEINSUM_OK) {
+    o.workspace = s->ws;
+    o.workspace_bytes = s->ws_bytes;
+    deinsum_status st = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]);
+    if (st == DEINSUM_ERR_NO_MEMORY && s->ws) {  // a plan tuned after start needs more: the library pool
+        o.workspace = nullptr;
+        o.workspace_bytes = 0;
+        st = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]);
+    }
+    if (st != DEINSUM_OK) {
         set_failed(s, std::string("serve: mttkrp: ") + deinsum_last_error());
         return false;
     }
@@ -311,7 +324,17 @@ void scheduler(deinsum_server *s)
             std::lock_guard<std::mutex> lk(s->mu);
             if (idle && s->submitted.empty()) return;
         }
-        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(5));
+        if (!progress) {
+            // Work on the device: poll its events without sleeping (a sleep costs tens of
+            // microseconds of latency).  Nothing to do: wait for a submission.
+            const bool busy = !pending.empty() || !s->inflight.empty() || s->epoch[0].active || s->epoch[1].active;
+            if (busy) {
+                std::this_thread::yield();
+            } else {
+                std::unique_lock<std::mutex> lk(s->mu);
+                s->cv.wait_for(lk, std::chrono::milliseconds(1), [&] { return !s->submitted.empty() || s->stop.load(); });
+            }
+        }
     }
 }
 
@@ -435,6 +458,17 @@ deinsum_status deinsum_server_start(deinsum_server *s)
     if (!s) return fail(DEINSUM_ERR_INVALID_ARG, "server_start: null server");
     if (s->started) return fail(DEINSUM_ERR_BUSY, "server_start: already started");
     s->reqs.reserve(static_cast<size_t>(s->cfg.max_requests));
+    if (!s->cfg.batched) {
+        size_t mx = 0;
+        for (auto &t : s->tensors)
+            for (int m = 0; m < t.order; ++m) mx = std::max(mx, t.ws[m]);
+        if (mx && hipMalloc(&s->ws, mx) != hipSuccess) {
+            (void)hipGetLastError();
+            s->ws = nullptr;
+            return fail(DEINSUM_ERR_NO_MEMORY, "server_start: workspace allocation failed");
+        }
+        s->ws_bytes = s->ws ? mx : 0;
+    }
     s->t0 = Clock::now();
     s->started = true;
     s->sched = std::thread(scheduler, s);
@@ -449,8 +483,8 @@ deinsum_status deinsum_server_submit(deinsum_server *s, int32_t tensor_id, int32
     if (tensor_id < 0 || tensor_id >= static_cast<int32_t>(s->tensors.size()))
         return fail(DEINSUM_ERR_INVALID_ARG, "server_submit: unknown tensor");
     if (mode < 0 || mode >= s->tensors[tensor_id].order) return fail(DEINSUM_ERR_INVALID_ARG, "server_submit: bad mode");
-    if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server_submit: server failed: " + s->error);
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server_submit: server failed: " + s->error);
     if (s->reqs.size() == s->reqs.capacity())
         return fail(DEINSUM_ERR_BUSY, "server_submit: request table full");  // reqs must not reallocate while served
     SRequest rq;
@@ -460,6 +494,7 @@ deinsum_status deinsum_server_submit(deinsum_server *s, int32_t tensor_id, int32
     s->reqs.push_back(rq);
     const int64_t id = static_cast<int64_t>(s->reqs.size()) - 1;
     s->submitted.push_back(id);
+    s->cv.notify_one();
     ++s->nsubmitted;
     if (request_id) *request_id = id;
     return DEINSUM_OK;
@@ -487,10 +522,10 @@ deinsum_status deinsum_server_drain(deinsum_server *s)
 {
     if (!s || !s->started) return fail(DEINSUM_ERR_INVALID_ARG, "server_drain: server not started");
     for (;;) {
-        if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server failed: " + s->error);
         int64_t nsub;
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server failed: " + s->error);
             nsub = s->nsubmitted;
         }
         if (s->completed >= nsub) break;
@@ -526,6 +561,7 @@ deinsum_status deinsum_server_destroy(deinsum_server *s)
 {
     if (!s) return DEINSUM_OK;
     s->stop = true;
+    s->cv.notify_all();
     if (s->sched.joinable()) s->sched.join();
     for (int e = 0; e < 2; ++e) {
         if (s->stream[e]) (void)hipStreamSynchronize(s->stream[e]);
@@ -539,6 +575,7 @@ deinsum_status deinsum_server_destroy(deinsum_server *s)
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
     for (auto &t : s->tensors)
         if (t.M) (void)hipFree(t.M);
+    if (s->ws) (void)hipFree(s->ws);
     delete s;
     return DEINSUM_OK;
 }
