@@ -30,6 +30,7 @@
 #include "als.h"
 #include "internal.h"
 #include "kernels.h"
+#include "serve_sched.h"
 
 using namespace deinsum;
 
@@ -154,20 +155,16 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
     ep.reqs.clear();
     ep.footprint = 0;
     const size_t cap = static_cast<size_t>(std::max(1, s->cfg.max_jobs_per_epoch));
-    for (auto it = pending.begin(); it != pending.end() && ep.reqs.size() < cap;) {
-        const int64_t r = *it;
-        STensor &t = s->tensors[s->reqs[r].tensor];
-        const size_t ws = t.ws[s->reqs[r].mode];
-        const bool head = !t.fifo.empty() && t.fifo.front() == r;
-        if (!t.busy && head && (s->footprint_used + ep.footprint + ws <= s->cfg.hbm_budget_bytes || ep.reqs.empty())) {
-            t.busy = true;
-            ep.reqs.push_back(r);
-            ep.footprint += ws;
-            it = pending.erase(it);
-        } else {
-            ++it;
-        }
-    }
+    admit_epoch(
+        pending, cap, s->footprint_used, s->cfg.hbm_budget_bytes, ep.reqs, ep.footprint,
+        [&](int64_t r) { return s->reqs[r].tensor; },
+        [&](int64_t r) {
+            const STensor &t = s->tensors[s->reqs[r].tensor];
+            return !t.fifo.empty() && t.fifo.front() == r;
+        },
+        [&](int32_t t) { return s->tensors[t].busy; },
+        [&](int64_t r) { return s->tensors[s->reqs[r].tensor].ws[s->reqs[r].mode]; },
+        [&](int32_t t) { s->tensors[t].busy = true; });
     if (ep.reqs.empty()) return false;
     deinsum_batch_reset(s->batch[e]);
     int64_t als_total = 0;
