@@ -16,14 +16,16 @@ namespace deinsum {
 // where c = N-1 is the contiguous mode and `slab` enumerates the other modes.
 struct TkArgs {
     const void *X;
-    const double *Ua;        // U^a zero-padded to 16*NTA columns (FP64 copy)
-    const double *Uc;        // U^c zero-padded to 16*NTC columns (FP64 copy), stage 2 only
+    const void *Ua;          // U^a zero-padded to 16*NTA columns (FP64 or FP32, as X)
+    const void *Uc;          // U^c zero-padded to 16*NTC columns, stage 2 only
     int64_t Ia, Ic, stride_a;
     OuterDesc od;            // slab modes (X strides only)
     int64_t n_slabs, slabs_per_group;
     int n_ctiles, nwaves, n_cgroups;
     int ra, rc;
     int vec_ok;
+    int xcd_remap;           // 1: the workgroups of one XCD take one contiguous range of units
+    int64_t n_groups;        // grid size
     double *P;               // stage2: [cgroup][slab][16*NTA][16*NTC]; else [slab][n_ctiles*16*MT][16*NTA]
 };
 

@@ -35,9 +35,10 @@ constexpr int kMaxTtmcRank = 64;
 template <int P> struct TkTypes;
 template <> struct TkTypes<P_FP64> { using XT = double; using DT = f64x4; };
 template <> struct TkTypes<P_FP32> { using XT = float;  using DT = f32x4; };
+// The factor copies the fused kernel reads are zero-padded to whole column tiles
+// and stored in the form's element type (FP64 or FP32).
 
 __device__ __forceinline__ int64_t tmin(int64_t a, int64_t b) { return a < b ? a : b; }
-__device__ __forceinline__ int64_t tmax(int64_t a, int64_t b) { return a > b ? a : b; }
 
 __device__ __forceinline__ double ldu_p(const void *p, int64_t i, int prec)
 {
@@ -111,6 +112,7 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
 {
     // UB: K-steps (of 4 rows) per ring step; NBUF: ring depth.
     using XT = typename TkTypes<P>::XT;
+    using UT = XT;
     using DT = typename TkTypes<P>::DT;
     constexpr int TA = 16 * NTA, TC = 16 * NTC;
     __shared__ double lds[STAGE2 ? TA * TC : 1];
@@ -118,165 +120,192 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, c = lane & 15;
-    const int64_t b = blockIdx.x;
+    int64_t b = blockIdx.x;
+    if (a.xcd_remap) {  // workgroups are dispatched round-robin over the 8 XCDs
+        const int64_t q = a.n_groups >> 3, r = a.n_groups & 7, x = b & 7;
+        b = x * q + (x < r ? x : r) + (b >> 3);
+    }
     const int cgroup = static_cast<int>(b % a.n_cgroups);
     const int64_t sg = b / a.n_cgroups;
     const int ctile = cgroup * a.nwaves + w;
+    // A lane's MT indices of the contiguous mode come in chunks of V (at most 16
+    // bytes); chunk j of lane c starts at j*16*V + c*V of the wave's tile, so one
+    // load instruction reads 16*V contiguous elements of a row.
+    constexpr int V = (MT * static_cast<int>(sizeof(XT)) <= 16) ? MT : 16 / static_cast<int>(sizeof(XT));
+    constexpr int NCH = MT / V;
+    static_assert(NCH * V == MT, "MT must be whole chunks");
     const int64_t cbase = static_cast<int64_t>(ctile) * 16 * MT;
-    const int64_t ibase = cbase + MT * c;
-    const int ivalid = (ctile < a.n_ctiles) ? static_cast<int>(tmin(MT, tmax(0, a.Ic - ibase))) : 0;
-    const bool full = a.vec_ok && ctile < a.n_ctiles && cbase + 16 * MT <= a.Ic && (MT * sizeof(XT)) % 8 == 0;
+    const int64_t ibase = cbase + V * c;
+    const bool full = a.vec_ok && ctile < a.n_ctiles && cbase + 16 * MT <= a.Ic && (V * sizeof(XT)) % 8 == 0;
     const int64_t s0 = sg * a.slabs_per_group;
     const int64_t s1 = tmin(a.n_slabs, s0 + a.slabs_per_group);
     const XT *__restrict__ X = static_cast<const XT *>(a.X);
-    const double *__restrict__ Ua = a.Ua;  // zero-padded FP64 copy, row stride TA
+    const UT *__restrict__ Ua = static_cast<const UT *>(a.Ua);  // zero-padded copy, row stride TA
+    const UT *__restrict__ Uc = static_cast<const UT *>(a.Uc);  // zero-padded copy, row stride TC
     const int64_t nsteps = (a.Ia + 4 * UB - 1) / (4 * UB);
-    const int64_t nfull = a.Ia / (4 * UB);  // ring steps whose rows are all in range
+    const int64_t nfull = a.Ia / (4 * UB);            // ring steps whose rows are all in range
+    const int64_t nsp = (nsteps + NBUF - 1) / NBUF * NBUF;  // whole ring turns per slab
 
-    SlabWalk walk;
-    walk.init(a.od, s0);
-    for (int64_t slab = s0; slab < s1; ++slab) {
-        DT d[MT][NTA];
+    auto run = [&](auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        XT xb[NBUF][UB][MT];
+        UT ub[NBUF][UB][NTA];
+        // Ring step st of the slab at xsrc into ring slot `slot`.  FULL and unguarded:
+        // a fixed sequence of unmasked vector loads, so the compiler waits for exactly
+        // the oldest step; otherwise rows past I_a (and dead steps) read as zero.
+        auto issue = [&](int slot, const XT *xsrc, int64_t st, bool guard, bool live) {
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+            for (int u = 0; u < UB; ++u) {
+                const int64_t r = (st * UB + u) * 4 + g;
+                const bool rv = live && (!guard || r < a.Ia);
 #pragma unroll
-            for (int nt = 0; nt < NTA; ++nt) d[mt][nt] = DT{0, 0, 0, 0};
-        const XT *xs = X + walk.off + ibase;
-
-        auto run = [&](auto full_tag) {
-            constexpr bool FULL = decltype(full_tag)::value;
-            XT xb[NBUF][UB][MT];
-            double ub[NBUF][UB][NTA];
-            // Complete ring step: unmasked loads (FULL) or column-masked loads.
-            auto issue = [&](int slot, int64_t st, bool guard) {
+                for (int nt = 0; nt < NTA; ++nt) ub[slot][u][nt] = rv ? Ua[r * TA + nt * 16 + c] : UT{};
+                if constexpr (FULL && (V * sizeof(XT)) % 8 == 0) {
+                    if (rv) {
 #pragma unroll
-                for (int u = 0; u < UB; ++u) {
-                    const int64_t r = (st * UB + u) * 4 + g;
-                    const bool rv = !guard || r < a.Ia;
-#pragma unroll
-                    for (int nt = 0; nt < NTA; ++nt)
-                        ub[slot][u][nt] = rv ? Ua[r * TA + nt * 16 + c] : 0.0;
-                    if constexpr (FULL && (MT * sizeof(XT)) % 8 == 0) {
-                        if (rv) load_vec_n<XT, MT, XNT>(xb[slot][u], xs + r * a.stride_a);
-                        else {
-#pragma unroll
-                            for (int i = 0; i < MT; ++i) xb[slot][u][i] = XT{};
-                        }
+                        for (int j = 0; j < NCH; ++j)
+                            load_vec_n<XT, V, XNT>(xb[slot][u] + j * V, xsrc + r * a.stride_a + j * 16 * V);
                     } else {
 #pragma unroll
-                        for (int i = 0; i < MT; ++i) xb[slot][u][i] = (rv && i < ivalid) ? xs[r * a.stride_a + i] : XT{};
+                        for (int i = 0; i < MT; ++i) xb[slot][u][i] = XT{};
                     }
-                }
-            };
-            auto mac = [&](int slot) {
+                } else {
 #pragma unroll
-                for (int u = 0; u < UB; ++u)
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                        for (int nt = 0; nt < NTA; ++nt) {
-                            if constexpr (P == P_FP64)
-                                d[mt][nt] = mfma_f64(xb[slot][u][mt], ub[slot][u][nt], d[mt][nt]);
-                            else
-                                d[mt][nt] = mfma_f32(xb[slot][u][mt], static_cast<float>(ub[slot][u][nt]), d[mt][nt]);
-                        }
-            };
-#pragma unroll
-            for (int u = 0; u < NBUF - 1; ++u)
-                if (u < nsteps) issue(u, u, u >= nfull);
-            int64_t t = 0;
-            for (; t + 2 * NBUF - 2 < nfull; t += NBUF) {
-#pragma unroll
-                for (int u = 0; u < NBUF; ++u) {
-                    issue((u + NBUF - 1) % NBUF, t + u + NBUF - 1, false);
-                    mac(u);
-                }
-            }
-            for (; t < nsteps; t += NBUF) {
-#pragma unroll
-                for (int u = 0; u < NBUF; ++u) {
-                    if (t + u < nsteps) {
-                        if (t + u + NBUF - 1 < nsteps) issue((u + NBUF - 1) % NBUF, t + u + NBUF - 1, true);
-                        mac(u);
+                    for (int i = 0; i < MT; ++i) {
+                        const int64_t e = (i / V) * 16 * V + i % V;
+                        xb[slot][u][i] = (rv && ibase + e < a.Ic) ? xsrc[r * a.stride_a + e] : XT{};
                     }
                 }
             }
         };
-        if (full) run(std::true_type{});
-        else run(std::false_type{});
-
-        if constexpr (STAGE2) {
-            // Z[r_c, r_a] = sum_{i_c} U^c[i_c, r_c] D[i_c, r_a]: K-step v pairs slot g
-            // with the D row that lanes of group g hold in register v.
-            DT z[NTC][NTA];
+        DT d[MT][NTA];
+        auto mac = [&](int slot) {
 #pragma unroll
-            for (int tc = 0; tc < NTC; ++tc)
-#pragma unroll
-                for (int ta = 0; ta < NTA; ++ta) z[tc][ta] = DT{0, 0, 0, 0};
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int64_t rowc = cbase + MT * tile_row<P>(lane, v) + mt;
-                    const bool rv = ctile < a.n_ctiles && rowc < a.Ic;
-#pragma unroll
-                    for (int tc = 0; tc < NTC; ++tc) {
-                        const double u = rv ? a.Uc[rowc * TC + tc * 16 + c] : 0.0;
-#pragma unroll
-                        for (int ta = 0; ta < NTA; ++ta) {
-                            if constexpr (P == P_FP64)
-                                z[tc][ta] = mfma_f64(u, d[mt][ta][v], z[tc][ta]);
-                            else
-                                z[tc][ta] = mfma_f32(static_cast<float>(u), d[mt][ta][v], z[tc][ta]);
-                        }
-                    }
-                }
-            // Fixed-order reduction over the workgroup's c-tiles (wave order).
-            for (int ww = 0; ww < a.nwaves; ++ww) {
-                if (w == ww) {
-#pragma unroll
-                    for (int tc = 0; tc < NTC; ++tc)
-#pragma unroll
-                        for (int ta = 0; ta < NTA; ++ta)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int i = (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v);
-                                const double zv = static_cast<double>(z[tc][ta][v]);
-                                lds[i] = (ww == 0) ? zv : lds[i] + zv;
-                            }
-                }
-                __syncthreads();
-            }
-            double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * (TA * TC);
-            for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) out[i] = lds[i];
-            __syncthreads();
-        } else {
-            const int64_t rows = static_cast<int64_t>(a.n_ctiles) * 16 * MT;
-            double *out = a.P + slab * rows * TA;
-            if (ctile < a.n_ctiles) {
+            for (int u = 0; u < UB; ++u)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int ta = 0; ta < NTA; ++ta)
+                    for (int nt = 0; nt < NTA; ++nt) {
+                        if constexpr (P == P_FP64)
+                            d[mt][nt] = mfma_f64(xb[slot][u][mt], ub[slot][u][nt], d[mt][nt]);
+                        else
+                            d[mt][nt] = mfma_f32(xb[slot][u][mt], ub[slot][u][nt], d[mt][nt]);
+                    }
+        };
+
+        SlabWalk walk;
+        walk.init(a.od, s0);
+        const XT *xs = X + walk.off + ibase;
+        // The ring runs on across slab boundaries: the first NBUF-1 steps of a slab are
+        // issued during the last ring turn of the previous one, so the loads stay in
+        // flight through stage 2 and the workgroup reduction.
 #pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            out[(cbase + MT * tile_row<P>(lane, v) + mt) * TA + ta * 16 + c] =
-                                static_cast<double>(d[mt][ta][v]);
+        for (int u = 0; u < NBUF - 1; ++u) issue(u, xs, u, u >= nfull, s0 < s1);
+        for (int64_t slab = s0; slab < s1; ++slab) {
+            const bool has_next = slab + 1 < s1;
+            SlabWalk wn = walk;
+            if (has_next) wn.next(a.od);
+            const XT *xn = X + wn.off + ibase;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NTA; ++nt) d[mt][nt] = DT{0, 0, 0, 0};
+            int64_t t = 0;
+            for (; t + 2 * NBUF - 2 < nfull; t += NBUF) {
+#pragma unroll
+                for (int u = 0; u < NBUF; ++u) {
+                    issue((u + NBUF - 1) % NBUF, xs, t + u + NBUF - 1, false, true);
+                    mac(u);
+                }
             }
+            for (; t < nsp; t += NBUF) {
+#pragma unroll
+                for (int u = 0; u < NBUF; ++u) {
+                    const int64_t tn = t + u + NBUF - 1;
+                    const bool cur = tn < nsp;
+                    issue((u + NBUF - 1) % NBUF, cur ? xs : xn, cur ? tn : tn - nsp, true, cur || has_next);
+                    if (t + u < nsteps) mac(u);
+                }
+            }
+
+            if constexpr (STAGE2) {
+                // Z[r_c, r_a] = sum_{i_c} U^c[i_c, r_c] D[i_c, r_a]: K-step v pairs slot g
+                // with the D row that lanes of group g hold in register v.
+                DT z[NTC][NTA];
+#pragma unroll
+                for (int tc = 0; tc < NTC; ++tc)
+#pragma unroll
+                    for (int ta = 0; ta < NTA; ++ta) z[tc][ta] = DT{0, 0, 0, 0};
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int tr = tile_row<P>(lane, v);
+                        const int64_t rowc = cbase + (mt / V) * 16 * V + tr * V + mt % V;
+                        const bool rv = ctile < a.n_ctiles && rowc < a.Ic;
+#pragma unroll
+                        for (int tc = 0; tc < NTC; ++tc) {
+                            const UT u = rv ? Uc[rowc * TC + tc * 16 + c] : UT{};
+#pragma unroll
+                            for (int ta = 0; ta < NTA; ++ta) {
+                                if constexpr (P == P_FP64)
+                                    z[tc][ta] = mfma_f64(u, d[mt][ta][v], z[tc][ta]);
+                                else
+                                    z[tc][ta] = mfma_f32(u, d[mt][ta][v], z[tc][ta]);
+                            }
+                        }
+                    }
+                // Fixed-order reduction over the workgroup's c-tiles (wave order).
+                for (int ww = 0; ww < a.nwaves; ++ww) {
+                    if (w == ww) {
+#pragma unroll
+                        for (int tc = 0; tc < NTC; ++tc)
+#pragma unroll
+                            for (int ta = 0; ta < NTA; ++ta)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int i = (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v);
+                                    const double zv = static_cast<double>(z[tc][ta][v]);
+                                    lds[i] = (ww == 0) ? zv : lds[i] + zv;
+                                }
+                    }
+                    __syncthreads();
+                }
+                double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * (TA * TC);
+                for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) out[i] = lds[i];
+                __syncthreads();
+            } else {
+                const int64_t rows = static_cast<int64_t>(a.n_ctiles) * 16 * MT;
+                double *out = a.P + slab * rows * TA;
+                if (ctile < a.n_ctiles) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int ta = 0; ta < NTA; ++ta)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                out[(cbase + (mt / V) * 16 * V + tile_row<P>(lane, v) * V + mt % V) * TA + ta * 16 + c] =
+                                    static_cast<double>(d[mt][ta][v]);
+                }
+            }
+            walk = wn;
+            xs = xn;
         }
-        walk.next(a.od);
-    }
+    };
+    if (full) run(std::true_type{});
+    else run(std::false_type{});
 }
 
-// Zero-padded FP64 copy of a factor: dst[i][j] = src[i][j] for j < r, 0 up to ldd.
-__global__ void __launch_bounds__(256) pad_factor_kernel(const void *src, int prec, int64_t rows, int r, int ldd,
-                                                         double *dst)
+// Zero-padded copy of a factor in the fused kernel's element type T (the form's
+// own: FP64 or FP32, so the copy is exact): dst[i][j] = src[i][j] for j < r, 0 up to ldd.
+template <typename T>
+__global__ void __launch_bounds__(256) pad_factor_kernel(const T *src, int64_t rows, int r, int ldd, T *dst)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= rows * ldd) return;
     const int64_t i = e / ldd;
     const int j = static_cast<int>(e % ldd);
-    dst[e] = (j < r) ? ldu_p(src, i * r + j, prec) : 0.0;
+    dst[e] = (j < r) ? src[i * r + j] : T{};
 }
 
 // Sum `parts` padded partial tensors and scatter into a strided destination.
@@ -370,15 +399,18 @@ struct TkEntry {
 #define TK1(P, A, MT, UB, NB) {P, A, 0, MT, UB, NB, false, &launch_tk<P, A, 1, MT, false, UB, NB, false>}
 const TkEntry kTkTable[] = {
     TK(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 2, 4), TK(P_FP64, 1, 4, 4, 2, 4),
-    TK(P_FP64, 2, 1, 4, 2, 3), TK(P_FP64, 2, 2, 4, 2, 3), TK(P_FP64, 2, 4, 2, 2, 4),
-    TK(P_FP64, 4, 1, 2, 2, 3), TK(P_FP64, 4, 2, 2, 2, 3), TK(P_FP64, 4, 4, 1, 2, 4),
+    TK(P_FP64, 2, 1, 4, 2, 3), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 4, 2, 2, 4),
+    TK(P_FP64, 4, 1, 2, 2, 3), TK(P_FP64, 4, 2, 2, 2, 3), TK(P_FP64, 4, 4, 1, 2, 3),
     // alternatives (plan_hint 1, 2, ...)
-    TK(P_FP64, 1, 1, 4, 3, 2), TK(P_FP64, 1, 2, 4, 3, 2), TK(P_FP64, 2, 1, 4, 3, 2), TK(P_FP64, 2, 2, 4, 3, 2),
-    TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 1, 2, 2, 4), TK(P_FP64, 4, 1, 1, 2, 4),
-    TK(P_FP64, 4, 2, 1, 2, 4),
+    TK(P_FP64, 1, 1, 4, 3, 2), TKN(P_FP64, 1, 1, 4, 3, 2), TKN(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 3, 2),
+    TKN(P_FP64, 1, 2, 4, 3, 2), TK(P_FP64, 2, 1, 4, 3, 2), TKN(P_FP64, 2, 1, 4, 3, 2), TK(P_FP64, 2, 2, 4, 2, 3),
+    TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 2, 3), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 1, 2, 2, 4),
+    TK(P_FP64, 4, 1, 1, 2, 4), TK(P_FP64, 4, 2, 1, 2, 4),
     TK(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
     TK(P_FP32, 2, 2, 4, 2, 4), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
-    TK(P_FP32, 4, 4, 2, 2, 4),
+    TK(P_FP32, 4, 4, 2, 2, 3),
+    TKN(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 1, 4, 4, 2), TKN(P_FP32, 2, 2, 4, 2, 4), TK(P_FP32, 2, 2, 4, 4, 2),
+    TKN(P_FP32, 2, 2, 4, 4, 2), TK(P_FP32, 2, 2, 4, 6, 2), TKN(P_FP32, 2, 2, 4, 6, 2),
     TK1(P_FP64, 1, 4, 2, 4), TK1(P_FP64, 2, 2, 2, 4), TK1(P_FP64, 4, 1, 2, 4),
     TK1(P_FP32, 1, 4, 2, 4), TK1(P_FP32, 2, 4, 2, 4), TK1(P_FP32, 4, 2, 2, 4),
 };
@@ -600,20 +632,21 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     double *Z = reinterpret_cast<double *>(base + align(p.p_bytes));
     double *T0 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes));
     double *T1 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes) + align(p.t_bytes));
-    double *Ua_pad = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes));
-    double *Uc_pad = reinterpret_cast<double *>(reinterpret_cast<char *>(Ua_pad) +
-                                                align(static_cast<size_t>(p.I[p.a]) * 16 * p.nta * 8));
+    char *Ua_pad = base + align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes);
+    char *Uc_pad = Ua_pad + align(static_cast<size_t>(p.I[p.a]) * 16 * p.nta * 8);
     {
-        const int lda = 16 * p.nta;
-        const int64_t na = p.I[p.a] * lda;
-        pad_factor_kernel<<<static_cast<unsigned>(cdivl(na, 256)), 256, 0, s>>>(Um[p.a], o.precision, p.I[p.a],
-                                                                              static_cast<int>(p.Rm[p.a]), lda, Ua_pad);
-        if (p.stage2) {
-            const int ldc = 16 * p.ntc;
-            const int64_t nc = p.I[p.c] * ldc;
-            pad_factor_kernel<<<static_cast<unsigned>(cdivl(nc, 256)), 256, 0, s>>>(
-                Um[p.c], o.precision, p.I[p.c], static_cast<int>(p.Rm[p.c]), ldc, Uc_pad);
-        }
+        auto pad = [&](int m, int ld, char *dst) {
+            const int64_t n = p.I[m] * ld;
+            const unsigned grid = static_cast<unsigned>(cdivl(n, 256));
+            if (o.precision == P_FP64)
+                pad_factor_kernel<double><<<grid, 256, 0, s>>>(static_cast<const double *>(Um[m]), p.I[m],
+                                                               static_cast<int>(p.Rm[m]), ld, reinterpret_cast<double *>(dst));
+            else
+                pad_factor_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float *>(Um[m]), p.I[m],
+                                                              static_cast<int>(p.Rm[m]), ld, reinterpret_cast<float *>(dst));
+        };
+        pad(p.a, 16 * p.nta, Ua_pad);
+        if (p.stage2) pad(p.c, 16 * p.ntc, Uc_pad);
         if (deinsum_status st = check_launch("ttmc_pad_factor")) return st;
     }
 
@@ -639,6 +672,8 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     a.ra = static_cast<int>(p.Rm[p.a]);
     a.rc = p.stage2 ? static_cast<int>(p.Rm[p.c]) : 0;
     a.vec_ok = ((p.I[p.c] * xb) % 8 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    a.xcd_remap = 1;
+    a.n_groups = p.groups;
     a.P = P;
     p.kernel->fn(a, p.groups, s);
     if (deinsum_status st = check_launch("ttmc_fused")) return st;
