@@ -115,7 +115,14 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
     using UT = XT;
     using DT = typename TkTypes<P>::DT;
     constexpr int TA = 16 * NTA, TC = 16 * NTC;
-    __shared__ double lds[STAGE2 ? TA * TC : 1];
+    // Stage-2 factor rows of the workgroup held in LDS when they fit in 32 KB (they
+    // are the same for every slab); per-wave Z tiles summed after one barrier when
+    // four of them fit in 32 KB, else accumulated wave by wave in one tile.
+    constexpr int CROWS = 4 * 16 * MT;
+    constexpr bool UC_LDS = STAGE2 && CROWS * TC * sizeof(UT) <= 32768;
+    constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) <= 32768;
+    __shared__ UT lds_uc[UC_LDS ? CROWS * TC : 1];
+    __shared__ double lds[STAGE2 ? (Z_PAR ? 4 * TA * TC : TA * TC) : 1];
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -145,6 +152,16 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
     const int64_t nsteps = (a.Ia + 4 * UB - 1) / (4 * UB);
     const int64_t nfull = a.Ia / (4 * UB);            // ring steps whose rows are all in range
     const int64_t nsp = (nsteps + NBUF - 1) / NBUF * NBUF;  // whole ring turns per slab
+
+    const int64_t crow0 = static_cast<int64_t>(cgroup) * a.nwaves * 16 * MT;
+    if constexpr (UC_LDS) {
+        const int n = a.nwaves * 16 * MT * TC;
+        for (int i = threadIdx.x; i < n; i += 64 * a.nwaves) {
+            const int64_t row = crow0 + i / TC;
+            lds_uc[i] = row < a.Ic ? Uc[row * TC + i % TC] : UT{};
+        }
+        __syncthreads();
+    }
 
     auto run = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
@@ -245,7 +262,9 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                         const bool rv = ctile < a.n_ctiles && rowc < a.Ic;
 #pragma unroll
                         for (int tc = 0; tc < NTC; ++tc) {
-                            const UT u = rv ? Uc[rowc * TC + tc * 16 + c] : UT{};
+                            UT u;
+                            if constexpr (UC_LDS) u = lds_uc[(rowc - crow0) * TC + tc * 16 + c];  // zero past I_c
+                            else u = rv ? Uc[rowc * TC + tc * 16 + c] : UT{};
 #pragma unroll
                             for (int ta = 0; ta < NTA; ++ta) {
                                 if constexpr (P == P_FP64)
@@ -256,23 +275,40 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                         }
                     }
                 // Fixed-order reduction over the workgroup's c-tiles (wave order).
-                for (int ww = 0; ww < a.nwaves; ++ww) {
-                    if (w == ww) {
-#pragma unroll
-                        for (int tc = 0; tc < NTC; ++tc)
-#pragma unroll
-                            for (int ta = 0; ta < NTA; ++ta)
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    const int i = (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v);
-                                    const double zv = static_cast<double>(z[tc][ta][v]);
-                                    lds[i] = (ww == 0) ? zv : lds[i] + zv;
-                                }
-                    }
-                    __syncthreads();
-                }
                 double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * (TA * TC);
-                for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) out[i] = lds[i];
+                if constexpr (Z_PAR) {
+#pragma unroll
+                    for (int tc = 0; tc < NTC; ++tc)
+#pragma unroll
+                        for (int ta = 0; ta < NTA; ++ta)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                lds[w * TA * TC + (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v)] =
+                                    static_cast<double>(z[tc][ta][v]);
+                    __syncthreads();
+                    for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) {
+                        double acc = lds[i];
+                        for (int ww = 1; ww < a.nwaves; ++ww) acc += lds[ww * TA * TC + i];
+                        out[i] = acc;
+                    }
+                } else {
+                    for (int ww = 0; ww < a.nwaves; ++ww) {
+                        if (w == ww) {
+#pragma unroll
+                            for (int tc = 0; tc < NTC; ++tc)
+#pragma unroll
+                                for (int ta = 0; ta < NTA; ++ta)
+#pragma unroll
+                                    for (int v = 0; v < 4; ++v) {
+                                        const int i = (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v);
+                                        const double zv = static_cast<double>(z[tc][ta][v]);
+                                        lds[i] = (ww == 0) ? zv : lds[i] + zv;
+                                    }
+                        }
+                        __syncthreads();
+                    }
+                    for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) out[i] = lds[i];
+                }
                 __syncthreads();
             } else {
                 const int64_t rows = static_cast<int64_t>(a.n_ctiles) * 16 * MT;
@@ -342,7 +378,9 @@ __global__ void __launch_bounds__(256) reduce_strided_kernel(const ReduceArgs a)
     else static_cast<float *>(a.out)[off] = static_cast<float>(acc);
 }
 
-// One mode product on an FP64 intermediate with a strided destination.
+// One mode product on an FP64 intermediate with a strided destination.  A thread
+// computes kTtmRB consecutive ranks of one output fibre, reading each input value once.
+constexpr int kTtmRB = 8;
 struct SmallTtmArgs {
     const double *T;
     int nd;
@@ -354,27 +392,97 @@ struct SmallTtmArgs {
     const void *U;
     int64_t ldu;
     int uprec;
-    int64_t total;
+    int64_t total;                    // threads: product of odim with dim m counted in blocks of kTtmRB
     void *out;
     int out_dtype;
+    int lds;                          // 1: U staged in LDS (dynamic shared memory)
 };
+
+// Largest factor (rows x ranks rounded up to kTtmRB, FP64) staged in LDS per workgroup.
+constexpr size_t kTtmLdsBytes = 48 * 1024;
 
 __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
 {
+    extern __shared__ double su[];  // U as FP64, row stride ldl = ranks rounded up to kTtmRB (0 = not staged)
+    const int64_t ldl = (a.odim[a.m] + kTtmRB - 1) / kTtmRB * kTtmRB;
+    if (a.lds) {
+        for (int64_t i = threadIdx.x; i < a.Im * ldl; i += blockDim.x) {
+            const int64_t row = i / ldl, r = i % ldl;
+            su[i] = r < a.odim[a.m] ? ldu_p(a.U, row * a.ldu + r, a.uprec) : 0.0;
+        }
+        __syncthreads();
+    }
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= a.total) return;
-    int64_t rem = e, ioff = 0, ooff = 0, r = 0;
+    int64_t rem = e, ioff = 0, ooff = 0, r0 = 0;
     for (int d = a.nd - 1; d >= 0; --d) {
-        const int64_t i = rem % a.odim[d];
-        rem /= a.odim[d];
-        ooff += i * a.ostr[d];
-        if (d == a.m) r = i;
-        else ioff += i * a.tstr[d];
+        const int64_t ext = (d == a.m) ? (a.odim[d] + kTtmRB - 1) / kTtmRB : a.odim[d];
+        const int64_t i = rem % ext;
+        rem /= ext;
+        if (d == a.m) {
+            r0 = i * kTtmRB;
+        } else {
+            ooff += i * a.ostr[d];
+            ioff += i * a.tstr[d];
+        }
     }
-    double acc = 0.0;
-    for (int64_t i = 0; i < a.Im; ++i) acc += a.T[ioff + i * a.tstr[a.m]] * ldu_p(a.U, i * a.ldu + r, a.uprec);
-    if (a.out_dtype == DEINSUM_F64) static_cast<double *>(a.out)[ooff] = acc;
-    else static_cast<float *>(a.out)[ooff] = static_cast<float>(acc);
+    const int nr = static_cast<int>(tmin(kTtmRB, a.odim[a.m] - r0));
+    double acc[kTtmRB];
+#pragma unroll
+    for (int q = 0; q < kTtmRB; ++q) acc[q] = 0.0;
+    // Unconditional loads (ranks past the last are clamped and their sums dropped), so
+    // the loads of an unrolled step are all in flight together.
+    int64_t col[kTtmRB];
+#pragma unroll
+    for (int q = 0; q < kTtmRB; ++q) col[q] = r0 + (q < nr ? q : 0);
+    auto body = [&](const auto *U) {
+        const int64_t sm = a.tstr[a.m];
+        int64_t i = 0;
+        for (; i + 8 <= a.Im; i += 8) {
+            double t[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] = a.T[ioff + (i + k) * sm];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int q = 0; q < kTtmRB; ++q) acc[q] += t[k] * static_cast<double>(U[(i + k) * a.ldu + col[q]]);
+        }
+        for (; i < a.Im; ++i) {
+            const double t = a.T[ioff + i * sm];
+#pragma unroll
+            for (int q = 0; q < kTtmRB; ++q) acc[q] += t * static_cast<double>(U[i * a.ldu + col[q]]);
+        }
+    };
+    if (a.lds) {
+        // every rank of the block is staged (zero past the last): no clamping needed
+        const int64_t sm = a.tstr[a.m];
+        int64_t i = 0;
+        for (; i + 8 <= a.Im; i += 8) {
+            double t[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] = a.T[ioff + (i + k) * sm];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int q = 0; q < kTtmRB; ++q) acc[q] += t[k] * su[(i + k) * ldl + r0 + q];
+        }
+        for (; i < a.Im; ++i) {
+            const double t = a.T[ioff + i * sm];
+#pragma unroll
+            for (int q = 0; q < kTtmRB; ++q) acc[q] += t * su[i * ldl + r0 + q];
+        }
+    } else if (a.uprec == P_FP64) {
+        body(static_cast<const double *>(a.U));
+    } else {
+        body(static_cast<const float *>(a.U));
+    }
+#pragma unroll
+    for (int q = 0; q < kTtmRB; ++q) {
+        if (q >= nr) break;
+        const int64_t o = ooff + (r0 + q) * a.ostr[a.m];
+        if (a.out_dtype == DEINSUM_F64) static_cast<double *>(a.out)[o] = acc[q];
+        else static_cast<float *>(a.out)[o] = static_cast<float>(acc[q]);
+    }
 }
 
 template <int P, int NTA, int NTC, int MT, bool S2, int UB, int NB, bool XNT>
@@ -398,13 +506,13 @@ struct TkEntry {
 #define TKN(P, A, C, MT, UB, NB) {P, A, C, MT, UB, NB, true, &launch_tk<P, A, C, MT, true, UB, NB, true>}
 #define TK1(P, A, MT, UB, NB) {P, A, 0, MT, UB, NB, false, &launch_tk<P, A, 1, MT, false, UB, NB, false>}
 const TkEntry kTkTable[] = {
-    TK(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 2, 4), TK(P_FP64, 1, 4, 4, 2, 4),
-    TK(P_FP64, 2, 1, 4, 2, 3), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 4, 2, 2, 4),
+    TKN(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 2, 4), TK(P_FP64, 1, 4, 4, 2, 4),
+    TK(P_FP64, 2, 1, 4, 2, 3), TKN(P_FP64, 2, 2, 4, 2, 3), TK(P_FP64, 2, 4, 2, 2, 4),
     TK(P_FP64, 4, 1, 2, 2, 3), TK(P_FP64, 4, 2, 2, 2, 3), TK(P_FP64, 4, 4, 1, 2, 3),
     // alternatives (plan_hint 1, 2, ...)
-    TK(P_FP64, 1, 1, 4, 3, 2), TKN(P_FP64, 1, 1, 4, 3, 2), TKN(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 3, 2),
+    TK(P_FP64, 1, 1, 4, 3, 2), TKN(P_FP64, 1, 1, 4, 3, 2), TK(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 3, 2),
     TKN(P_FP64, 1, 2, 4, 3, 2), TK(P_FP64, 2, 1, 4, 3, 2), TKN(P_FP64, 2, 1, 4, 3, 2), TK(P_FP64, 2, 2, 4, 2, 3),
-    TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 2, 3), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 1, 2, 2, 4),
+    TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 1, 2, 2, 4),
     TK(P_FP64, 4, 1, 1, 2, 4), TK(P_FP64, 4, 2, 1, 2, 4),
     TK(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
     TK(P_FP32, 2, 2, 4, 2, 4), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
@@ -725,15 +833,23 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         r.out = Z;
         r.out_dtype = DEINSUM_F64;
     }
-    reduce_strided_kernel<<<static_cast<unsigned>(cdivl(r.total, 256)), 256, 0, s>>>(r);
-    if (deinsum_status st = check_launch("ttmc_reduce")) return st;
-    if (remaining.empty()) return DEINSUM_OK;
-
-    // ---- remaining mode products on the intermediate
+    // ---- remaining mode products on the intermediate; with a single partial the first
+    // product reads the fused pass's padded tiles directly
     std::vector<DimInfo> cur = zd;
     cur.push_back({xmode, r.X1});
     cur.push_back({ymode, r.Y1});
+    std::vector<int64_t> sext;  // extents of the source layout (padded for the tiles)
+    for (const auto &d : cur) sext.push_back(d.extent);
     const double *src = Z;
+    if (remaining.empty() || r.parts > 1) {
+        reduce_strided_kernel<<<static_cast<unsigned>(cdivl(r.total, 256)), 256, 0, s>>>(r);
+        if (deinsum_status st = check_launch("ttmc_reduce")) return st;
+        if (remaining.empty()) return DEINSUM_OK;
+    } else {
+        src = P;
+        sext[sext.size() - 2] = r.PX;
+        sext[sext.size() - 1] = r.PY;
+    }
     for (size_t k = 0; k < remaining.size(); ++k) {
         const int m = remaining[remaining.size() - 1 - k];  // last mode first
         const bool last = (k + 1 == remaining.size());
@@ -748,15 +864,18 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         int64_t st = 1;
         for (int d = t.nd - 1; d >= 0; --d) {
             t.tstr[d] = st;
-            st *= cur[d].extent;
+            st *= sext[d];
         }
         cur[pos].extent = p.Rm[m];
+        int64_t nout = 1;
         t.total = 1;
         for (int d = 0; d < t.nd; ++d) {
             t.odim[d] = cur[d].extent;
-            t.total *= cur[d].extent;
+            nout *= cur[d].extent;
+            t.total *= (d == pos) ? cdivl(cur[d].extent, kTtmRB) : cur[d].extent;
+            sext[d] = cur[d].extent;
         }
-        if (!last && static_cast<size_t>(t.total) * 8 > p.t_bytes)
+        if (!last && static_cast<size_t>(nout) * 8 > p.t_bytes)
             return fail(DEINSUM_ERR_NO_MEMORY, "ttmc: intermediate larger than its workspace slot");
         void *dst = last ? Y : static_cast<void *>((k % 2 == 0) ? T0 : T1);
         if (last) {
@@ -773,7 +892,9 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         t.uprec = o.precision;
         t.out = dst;
         t.out_dtype = last ? o.out_dtype : DEINSUM_F64;
-        small_ttm_kernel<<<static_cast<unsigned>(cdivl(t.total, 256)), 256, 0, s>>>(t);
+        const size_t ubytes = static_cast<size_t>(t.Im * cdivl(p.Rm[m], kTtmRB) * kTtmRB) * 8;
+        t.lds = ubytes <= kTtmLdsBytes;
+        small_ttm_kernel<<<static_cast<unsigned>(cdivl(t.total, 256)), 256, t.lds ? ubytes : 0, s>>>(t);
         if (deinsum_status st2 = check_launch("ttmc_small_ttm")) return st2;
         src = static_cast<const double *>(dst);
     }

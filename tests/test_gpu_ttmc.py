@@ -22,6 +22,10 @@ CASES = [
     ((9, 11, 13, 17), (3, 4, 5, 6)),
     ((6, 7, 5, 8, 9), (2, 3, 4, 3, 2)),
     ((33, 47), (5, 6)),
+    # remaining product over a 900-long mode: its factor is read from global memory, not LDS
+    ((3, 900, 20, 24), (2, 8, 8, 8)),
+    # several c-groups per slab (partials reduced) before the remaining products; ragged last tile
+    ((5, 6, 7, 300), (3, 4, 5, 6)),
 ]
 
 
