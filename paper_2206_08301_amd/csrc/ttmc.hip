@@ -117,10 +117,12 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
     constexpr int TA = 16 * NTA, TC = 16 * NTC;
     // Stage-2 factor rows of the workgroup held in LDS when they fit in 32 KB (they
     // are the same for every slab); per-wave Z tiles summed after one barrier when
-    // four of them fit in 32 KB, else accumulated wave by wave in one tile.
+    // the workgroup's LDS stays within 40 KB (four workgroups per CU), else
+    // accumulated wave by wave in one tile.
     constexpr int CROWS = 4 * 16 * MT;
-    constexpr bool UC_LDS = STAGE2 && CROWS * TC * sizeof(UT) <= 32768;
-    constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) <= 32768;
+    constexpr size_t UC_BYTES = static_cast<size_t>(CROWS) * TC * sizeof(UT);
+    constexpr bool UC_LDS = STAGE2 && UC_BYTES <= 32768;
+    constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) + (UC_LDS ? UC_BYTES : 0) <= 40960;
     __shared__ UT lds_uc[UC_LDS ? CROWS * TC : 1];
     __shared__ double lds[STAGE2 ? (Z_PAR ? 4 * TA * TC : TA * TC) : 1];
 
@@ -514,11 +516,12 @@ const TkEntry kTkTable[] = {
     TKN(P_FP64, 1, 2, 4, 3, 2), TK(P_FP64, 2, 1, 4, 3, 2), TKN(P_FP64, 2, 1, 4, 3, 2), TK(P_FP64, 2, 2, 4, 2, 3),
     TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 1, 2, 2, 4),
     TK(P_FP64, 4, 1, 1, 2, 4), TK(P_FP64, 4, 2, 1, 2, 4),
-    TK(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
-    TK(P_FP32, 2, 2, 4, 2, 4), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
+    TKN(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
+    TKN(P_FP32, 2, 2, 4, 4, 2), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
     TK(P_FP32, 4, 4, 2, 2, 3),
-    TKN(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 1, 4, 4, 2), TKN(P_FP32, 2, 2, 4, 2, 4), TK(P_FP32, 2, 2, 4, 4, 2),
-    TKN(P_FP32, 2, 2, 4, 4, 2), TK(P_FP32, 2, 2, 4, 6, 2), TKN(P_FP32, 2, 2, 4, 6, 2),
+    TK(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 1, 4, 4, 2), TK(P_FP32, 2, 2, 4, 2, 4), TKN(P_FP32, 2, 2, 4, 2, 4),
+    TK(P_FP32, 2, 2, 4, 4, 2), TK(P_FP32, 2, 2, 8, 2, 2), TKN(P_FP32, 2, 2, 8, 2, 2),
+    TK(P_FP32, 1, 1, 8, 2, 3), TKN(P_FP32, 1, 1, 8, 2, 3),
     TK1(P_FP64, 1, 4, 2, 4), TK1(P_FP64, 2, 2, 2, 4), TK1(P_FP64, 4, 1, 2, 4),
     TK1(P_FP32, 1, 4, 2, 4), TK1(P_FP32, 2, 4, 2, 4), TK1(P_FP32, 4, 2, 2, 4),
 };
