@@ -13,6 +13,7 @@
 
 #include "internal.h"
 #include "kernels.h"
+#include "krp.h"
 #include "mttkrp.h"
 #include "plan.h"
 #include "ttmc.h"
@@ -134,13 +135,32 @@ deinsum_status zero_bytes(void *p, int64_t n, hipStream_t s)
 
 // ------------------------------------------------------------------ MTTKRP
 struct MttkrpCall {
-    MttkrpProblem pb;
+    MttkrpProblem pb;                  // as planned (last two modes merged if `merged`)
+    MttkrpProblem orig;                // as called
     MttkrpPlan plan;
     const void *X;
-    const void *U[DEINSUM_MAX_ORDER];  // by mode
+    const void *U[DEINSUM_MAX_ORDER];  // by mode of the problem as called
     void *M;
     int out_dtype;
+    bool merged = false;
+    size_t krp_bytes = 0;              // merged factor at the start of the workspace (256-aligned)
 };
+
+size_t call_workspace(const MttkrpCall &c) { return c.krp_bytes + c.plan.workspace; }
+
+// The FX20, BF16 and BF16x3 matrix-core K step takes 32 contiguous elements of the
+// contiguous mode (8 per lane), so a short or ragged last mode leaves lanes idle.
+// When the free mode is n <= N-3, the last two modes are both contracted and X's
+// memory is also an order N-1 tensor with them merged; its factor is their
+// Khatri-Rao product (I_{N-2} I_{N-1} x R), built per call into the workspace.
+bool merge_last_two(const MttkrpProblem &pb, int plan_hint)
+{
+    if (plan_hint != 0 || pb.N < 3 || pb.n > pb.N - 3) return false;
+    if (pb.prec != P_FX20 && pb.prec != P_BF16 && pb.prec != P_BF16X3) return false;
+    const int64_t ia = pb.dims[pb.N - 2], ib = pb.dims[pb.N - 1];
+    if (ib % 32 == 0 && ib >= 256) return false;
+    return ia * ib * pb.R * static_cast<int64_t>(u_elem_bytes(pb.prec)) <= (int64_t(64) << 20);
+}
 
 deinsum_status prepare_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R,
                               const deinsum_opts &o, MttkrpCall *call)
@@ -156,13 +176,34 @@ deinsum_status prepare_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     pb.R = R;
     pb.prec = o.precision;
     call->out_dtype = o.out_dtype;
+    call->orig = pb;
+    call->merged = merge_last_two(pb, o.plan_hint);
+    call->krp_bytes = 0;
+    if (call->merged) {
+        const int64_t ia = pb.dims[pb.N - 2], ib = pb.dims[pb.N - 1];
+        call->krp_bytes = (static_cast<size_t>(ia * ib * R) * u_elem_bytes(pb.prec) + 255) / 256 * 256;
+        pb.dims[pb.N - 2] = ia * ib;
+        pb.dims[pb.N - 1] = 0;
+        pb.N -= 1;
+    }
     return plan_mttkrp(pb, o.plan_hint, o.split_hint, &call->plan);
 }
 
-deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
+deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
 {
     const MttkrpProblem &pb = c.pb;
     const MttkrpPlan &p = c.plan;
+    const void *Uf[DEINSUM_MAX_ORDER];  // factors by mode of the planned problem
+    for (int m = 0; m < c.orig.N; ++m) Uf[m] = c.U[m];
+    void *ws = ws_all;
+    if (c.merged) {
+        const int a = c.orig.N - 2;
+        if (deinsum_status st = launch_krp2(c.U[a], c.U[a + 1], c.orig.dims[a], c.orig.dims[a + 1], pb.R,
+                                            static_cast<int>(u_elem_bytes(pb.prec)), ws_all, s))
+            return st;
+        Uf[a] = ws_all;
+        ws = static_cast<char *>(ws_all) + c.krp_bytes;
+    }
     const int N = pb.N, n = pb.n;
     const bool kcontig = p.family == PLAN_MTTKRP_KCONTIG;
     const int gmode = kcontig ? N - 1 : N - 2;
@@ -184,7 +225,7 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
         const int64_t col0 = cb * cols_pad;
         const int ncols = static_cast<int>(std::min<int64_t>(cols_pad, pb.R - col0));
         auto ucol = [&](int m) {
-            return static_cast<const void *>(static_cast<const char *>(c.U[m]) + col0 * ub);
+            return static_cast<const void *>(static_cast<const char *>(Uf[m]) + col0 * ub);
         };
         StreamArgs a{};
         a.X = fx20 ? static_cast<const void *>(static_cast<const char *>(c.X) + kFx20Header) : c.X;
@@ -234,7 +275,10 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws, hipStream_t s)
     return DEINSUM_OK;
 }
 
-void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p, size_t ws_bytes)
+// pb: the problem as called (algorithmic bytes and flops); p: the plan that ran;
+// merged: the last two modes ran as one (" m2" ends the plan name).
+void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p, size_t ws_bytes,
+                 bool merged = false)
 {
     if (!r) return;
     std::memset(r, 0, sizeof(*r));
@@ -254,8 +298,8 @@ void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p
     // Two-stage flops: GEMM over one mode (2 nX R) + Hadamard of each stage-1 row.
     const int g = (pb.n == pb.N - 1) ? pb.N - 2 : pb.N - 1;
     r->alg_flops = 2.0 * nx * pb.R + 2.0 * (nx / static_cast<double>(pb.dims[g])) * pb.R * std::max(1, pb.N - 2);
-    std::snprintf(r->plan_name, sizeof(r->plan_name), "%s c%lld o%d x%d", p.name.c_str(),
-                  static_cast<long long>(p.n_chunks), p.order, p.xcd);
+    std::snprintf(r->plan_name, sizeof(r->plan_name), "%s c%lld o%d x%d%s", p.name.c_str(),
+                  static_cast<long long>(p.n_chunks), p.order, p.xcd, merged ? " m2" : "");
 }
 
 // Median of the event-timed durations of `reps` back-to-back runs (one warm-up first).
@@ -312,7 +356,7 @@ deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *d
     if (spec && spec->kind == DEINSUM_TTMC) return ttmc_workspace_size(spec, dims, ranks, o, bytes);
     MttkrpCall c{};
     if (deinsum_status st = prepare_mttkrp(spec, dims, ranks[0], o, &c)) return st;
-    *bytes = c.plan.workspace;
+    *bytes = call_workspace(c);
     clear_error();
     return DEINSUM_OK;
 }
@@ -364,12 +408,12 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     c.M = M;
     void *ws = o.workspace;
     if (ws) {
-        if (o.workspace_bytes < c.plan.workspace)
-            return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(c.plan.workspace) + " bytes");
-    } else if (deinsum_status st = pool_get(c.plan.workspace, &ws)) {
+        if (o.workspace_bytes < call_workspace(c))
+            return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(call_workspace(c)) + " bytes");
+    } else if (deinsum_status st = pool_get(call_workspace(c), &ws)) {
         return st;
     }
-    fill_report(o.report, c.pb, c.plan, c.plan.workspace);
+    fill_report(o.report, c.orig, c.plan, call_workspace(c), c.merged);
     if (deinsum_status st = run_mttkrp(c, ws, s)) return st;
     clear_error();
     return DEINSUM_OK;
@@ -419,7 +463,7 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
                 cc.plan.order = variant & 1;
                 cc.plan.xcd = variant >> 1;
                 void *ws = nullptr;
-                if (deinsum_status st = pool_get(cc.plan.workspace, &ws)) return st;
+                if (deinsum_status st = pool_get(call_workspace(cc), &ws)) return st;
                 double us = 0;
                 if (deinsum_status st = time_median([&] { return run_mttkrp(cc, ws, s); }, reps, s, &us)) return st;
                 if (verbose)
@@ -442,7 +486,9 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
     if (best_us < 0) return fail(DEINSUM_ERR_UNSUPPORTED, "tune: no candidate plan");
     tune_store(tune_key(TUNE_STREAM, c.pb), choice);
     if (best) {
-        fill_report(best, c.pb, best_plan, best_plan.workspace);
+        MttkrpCall cb = c;
+        cb.plan = best_plan;
+        fill_report(best, c.orig, best_plan, call_workspace(cb), c.merged);
         best->tuned_us = best_us;
     }
     clear_error();

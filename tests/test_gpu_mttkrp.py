@@ -194,3 +194,39 @@ def test_full_size_1024cubed_sampled_rows(dn, synth, oracle_mod):
             assert nrel(Mh[i], ref) <= 1e-12, (n, i)
     del X
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision,tol", [("fx20", 4e-6), ("bf16x3", 1e-5), ("bf16", 2e-2)])
+@pytest.mark.parametrize("dims", [(9, 7, 10, 80), (5, 6, 4, 9, 80), (3, 4, 33, 50)])
+def test_merged_last_modes_match_unmerged(dn, synth, oracle_mod, precision, tol, dims):
+    """Free mode n <= N-3 in the 32-element K-step forms: the default plan runs the last two
+    modes as one (their Khatri-Rao factor built per call, plan name ending " m2"); it and the
+    unmerged heuristic plan (plan_hint 1) both meet the form's bound against the oracle."""
+    N = len(dims)
+    R = 24
+    X = synth.x_tensor(4343 + N, dims)
+    rng = np.random.default_rng(N)
+    if precision == "fx20":
+        Xd = dn.to_fx20(to_dev(X))
+    elif precision == "bf16":
+        Xd = to_dev(X, torch.float32).to(torch.bfloat16)
+    else:
+        Xd = to_dev(X, torch.float32)
+    for n in range(N - 2):
+        U = factors_for(rng, dims, R, n)
+        U = [None if u is None else u.astype(np.float32).astype(np.float64) for u in U]
+        ref = oracle_mod.mttkrp(X, U, n)
+        ops = [to_dev(u, torch.float32) for u in operands(U, n)]
+        rep = dn.Report()
+        merged = dn.mttkrp(mttkrp_spec(N, n), Xd, ops, precision=precision, out_dtype=torch.float64, report=rep)
+        plain = dn.mttkrp(mttkrp_spec(N, n), Xd, ops, precision=precision, out_dtype=torch.float64, plan_hint=1)
+        torch.cuda.synchronize()
+        name = rep.plan_name.decode()
+        flush(f"{precision} dims={dims} n={n}: {name}")
+        assert name.endswith(" m2"), name
+        nx = float(np.prod(dims))
+        assert rep.alg_bytes == pytest.approx(nx * {"fx20": 3, "bf16": 2, "bf16x3": 4}[precision]
+                                              + sum(d * R * 4 for m, d in enumerate(dims) if m != n)
+                                              + dims[n] * R * 8)
+        assert nrel(merged.cpu().numpy(), ref) <= tol
+        assert nrel(plain.cpu().numpy(), ref) <= tol
