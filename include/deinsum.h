@@ -362,7 +362,11 @@ deinsum_status deinsum_server_destroy(deinsum_server *s);
  * that cache first when plan_hint = split_hint = 0, so a tuned problem keeps
  * its plan.  deinsum_tune_batch_mttkrp does the same for a job of the batched
  * launch (its column width and split), which deinsum_batch_add_mttkrp then
- * uses.  *best (optional) describes the winner, tuned_us its median time.
+ * uses.  For mode 0 of an order-3 FP64 problem (R <= 64) the candidates also
+ * include running it through the fused TTMc pass (every compiled variant) and
+ * taking the diagonal of the R x R result; that plan is also the default, untuned,
+ * for tensors of at least 2^26 elements whose last mode has at least 256 entries.
+ * *best (optional) describes the winner, tuned_us its median time.
  * The cache is keyed by path, order, free mode, precision, rank and dims; when
  * the environment variable DEINSUM_TUNE_CACHE names a file it is read on first
  * use and rewritten after every tuning call.  Host-synchronous.
@@ -379,8 +383,10 @@ deinsum_status deinsum_tune_batch_mttkrp(const deinsum_spec *spec, const int64_t
 deinsum_status deinsum_tune_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
                                  const void *const *U, void *Y, const deinsum_opts *opts, int32_t reps,
                                  deinsum_report *best, void *stream);
-/* Read entries from / write the whole cache to a text file (one entry per line;
- * for TTMc keys the split column holds the variant). */
+/* Read entries from / write the whole cache to a text file, one entry per line:
+ * key nt ni mt xnt split order xcd us.  For TTMc keys the split column holds the
+ * variant; an MTTKRP entry with order 2 runs through the fused TTMc pass with
+ * variant `split`. */
 deinsum_status deinsum_tune_load(const char *path);
 deinsum_status deinsum_tune_save(const char *path);
 /* Forget every cached plan. */

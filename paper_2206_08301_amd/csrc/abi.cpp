@@ -144,9 +144,22 @@ struct MttkrpCall {
     int out_dtype;
     bool merged = false;
     size_t krp_bytes = 0;              // merged factor at the start of the workspace (256-aligned)
+    bool via_ttmc = false;             // order-3 mode 0 through the fused TTMc pass
+    int ttmc_variant = 0;              // its TTMc plan_hint
+    size_t ttmc_bytes = 0;
 };
 
-size_t call_workspace(const MttkrpCall &c) { return c.krp_bytes + c.plan.workspace; }
+size_t call_workspace(const MttkrpCall &c) { return c.via_ttmc ? c.ttmc_bytes : c.krp_bytes + c.plan.workspace; }
+
+// Mode 0 of an order-3 FP64 tensor can run through the fused TTMc pass: there a wave
+// streams contiguous runs of one X row per K step, where the K-contiguous kernel
+// reads 16 rows I_1 I_2 elements apart; the extra stage-2 work (the full R x R
+// product whose diagonal is M) is small.  Taken when the tuner measured it faster,
+// else for long rows of a tensor of at least 2^26 elements.
+bool via_ttmc_eligible(const MttkrpProblem &pb, const deinsum_opts &o)
+{
+    return o.plan_hint == 0 && o.split_hint == 0 && pb.N == 3 && pb.n == 0 && pb.prec == P_FP64 && pb.R <= 64;
+}
 
 // The FX20, BF16 and BF16x3 matrix-core K step takes 32 contiguous elements of the
 // contiguous mode (8 per lane), so a short or ragged last mode leaves lanes idle.
@@ -186,6 +199,34 @@ deinsum_status prepare_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
         pb.dims[pb.N - 1] = 0;
         pb.N -= 1;
     }
+    call->via_ttmc = false;
+    if (!call->merged && via_ttmc_eligible(pb, o)) {
+        TuneChoice tc;
+        bool cached = tune_lookup(tune_key(TUNE_STREAM, pb), &tc);
+        if (cached && tc.order != kTuneViaTtmc) {  // a stream-kernel entry counts only if that kernel exists
+            int count = 0;
+            const StreamKernelInfo *table = stream_kernels(&count);
+            bool found = false;
+            for (int i = 0; i < count; ++i) {
+                const StreamKernelInfo &k = table[i];
+                found |= k.prec == pb.prec && k.layout == L_KCONTIG && k.nt == tc.nt && k.ni == tc.ni &&
+                         k.mt == tc.mt && k.xnt == tc.xnt;
+            }
+            cached = found;
+        }
+        if (cached) {
+            call->via_ttmc = tc.order == kTuneViaTtmc;
+            call->ttmc_variant = tc.split + 1;
+        } else {
+            call->via_ttmc = pb.dims[2] >= 256 && pb.dims[0] * pb.dims[1] * pb.dims[2] >= (int64_t(1) << 26);
+            call->ttmc_variant = 0;
+        }
+        if (call->via_ttmc &&
+            mttkrp_via_ttmc_workspace(pb.dims, R, pb.prec, call->ttmc_variant, &call->ttmc_bytes) != DEINSUM_OK) {
+            call->ttmc_variant = 0;  // a cached variant that is no longer compiled: the default one
+            if (deinsum_status st = mttkrp_via_ttmc_workspace(pb.dims, R, pb.prec, 0, &call->ttmc_bytes)) return st;
+        }
+    }
     return plan_mttkrp(pb, o.plan_hint, o.split_hint, &call->plan);
 }
 
@@ -193,6 +234,9 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
 {
     const MttkrpProblem &pb = c.pb;
     const MttkrpPlan &p = c.plan;
+    if (c.via_ttmc)
+        return run_mttkrp_via_ttmc(pb.dims, pb.R, c.X, c.U[1], c.U[2], c.M, pb.prec, c.out_dtype, c.ttmc_variant,
+                                   ws_all, c.ttmc_bytes, s);
     const void *Uf[DEINSUM_MAX_ORDER];  // factors by mode of the planned problem
     for (int m = 0; m < c.orig.N; ++m) Uf[m] = c.U[m];
     void *ws = ws_all;
@@ -276,9 +320,10 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
 }
 
 // pb: the problem as called (algorithmic bytes and flops); p: the plan that ran;
-// merged: the last two modes ran as one (" m2" ends the plan name).
+// merged: the last two modes ran as one (" m2" ends the plan name); ttmc_variant >= 0:
+// the call ran through the fused TTMc pass with that plan_hint (geometry fields zero).
 void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p, size_t ws_bytes,
-                 bool merged = false)
+                 bool merged = false, int ttmc_variant = -1)
 {
     if (!r) return;
     std::memset(r, 0, sizeof(*r));
@@ -300,6 +345,12 @@ void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p
     r->alg_flops = 2.0 * nx * pb.R + 2.0 * (nx / static_cast<double>(pb.dims[g])) * pb.R * std::max(1, pb.N - 2);
     std::snprintf(r->plan_name, sizeof(r->plan_name), "%s c%lld o%d x%d%s", p.name.c_str(),
                   static_cast<long long>(p.n_chunks), p.order, p.xcd, merged ? " m2" : "");
+    if (ttmc_variant >= 0) {
+        r->plan_id = 0;
+        r->tile_m = r->tile_k = r->waves_per_group = 0;
+        r->groups = r->partials = 0;
+        std::snprintf(r->plan_name, sizeof(r->plan_name), "mttkrp_via_ttmc hint%d", ttmc_variant);
+    }
 }
 
 // Median of the event-timed durations of `reps` back-to-back runs (one warm-up first).
@@ -413,7 +464,7 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     } else if (deinsum_status st = pool_get(call_workspace(c), &ws)) {
         return st;
     }
-    fill_report(o.report, c.orig, c.plan, call_workspace(c), c.merged);
+    fill_report(o.report, c.orig, c.plan, call_workspace(c), c.merged, c.via_ttmc ? c.ttmc_variant : -1);
     if (deinsum_status st = run_mttkrp(c, ws, s)) return st;
     clear_error();
     return DEINSUM_OK;
@@ -459,6 +510,7 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
         for (int si = 0; si < ns; ++si)
             for (int variant = 0; variant < 4; ++variant) {
                 MttkrpCall cc = c;
+                cc.via_ttmc = false;
                 if (deinsum_status st = plan_geometry(c.pb, &k, splits[si], &cc.plan)) return st;
                 cc.plan.order = variant & 1;
                 cc.plan.xcd = variant >> 1;
@@ -483,12 +535,38 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
                 }
             }
     }
+    int best_ttmc = -1;  // plan_hint of the fused TTMc pass when it wins
+    if (!c.merged && via_ttmc_eligible(c.pb, o)) {
+        for (int v = 1; v <= 64; ++v) {
+            MttkrpCall cc = c;
+            cc.via_ttmc = true;
+            cc.ttmc_variant = v;
+            if (mttkrp_via_ttmc_workspace(c.pb.dims, c.pb.R, c.pb.prec, v, &cc.ttmc_bytes) != DEINSUM_OK) break;
+            void *ws = nullptr;
+            if (deinsum_status st = pool_get(cc.ttmc_bytes, &ws)) return st;
+            double us = 0;
+            if (deinsum_status st = time_median([&] { return run_mttkrp(cc, ws, s); }, reps, s, &us)) return st;
+            if (verbose) std::fprintf(stderr, "[deinsum tune] mttkrp_via_ttmc hint %d: %.1f us\n", v, us);
+            if (best_us < 0 || us < best_us) {
+                best_us = us;
+                best_ttmc = v;
+                choice = TuneChoice{};
+                choice.nt = choice.ni = choice.mt = 1;
+                choice.order = kTuneViaTtmc;
+                choice.split = v - 1;
+                choice.us = us;
+            }
+        }
+    }
     if (best_us < 0) return fail(DEINSUM_ERR_UNSUPPORTED, "tune: no candidate plan");
     tune_store(tune_key(TUNE_STREAM, c.pb), choice);
     if (best) {
         MttkrpCall cb = c;
         cb.plan = best_plan;
-        fill_report(best, c.orig, best_plan, call_workspace(cb), c.merged);
+        cb.via_ttmc = best_ttmc >= 0;
+        if (cb.via_ttmc)
+            (void)mttkrp_via_ttmc_workspace(c.pb.dims, c.pb.R, c.pb.prec, best_ttmc, &cb.ttmc_bytes);
+        fill_report(best, c.orig, best_plan, call_workspace(cb), c.merged, best_ttmc);
         best->tuned_us = best_us;
     }
     clear_error();

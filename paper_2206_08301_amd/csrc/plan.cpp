@@ -102,7 +102,7 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
     int count = 0;
     const StreamKernelInfo *table = stream_kernels(&count);
     TuneChoice tc;
-    if (plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc)) {
+    if (plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc) && tc.order != kTuneViaTtmc) {
         for (int i = 0; i < count; ++i) {
             const StreamKernelInfo &k = table[i];
             if (k.prec == pb.prec && k.layout == layout && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt &&

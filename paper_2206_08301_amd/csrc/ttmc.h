@@ -38,4 +38,14 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
                         const void *const *U, void *Y, const deinsum_opts &o, void *ws, size_t ws_bytes,
                         hipStream_t s);
 
+// Mode-0 MTTKRP of an order-3 tensor through the fused TTMc pass, whose access
+// pattern streams whole rows of X: Y[i, b, c] = sum_{j,k} X[i,j,k] U1[j,b] U2[k,c]
+// with both ranks R (<= 64), then M[i, r] = Y[i, r, r] (with both as defined in
+// Sec. III-B, the MTTKRP is this TTMc's diagonal).  variant: as the TTMc plan_hint (0 = tuned or default, k >= 1
+// = compiled variant k-1).  prec: P_FP64 or P_FP32.
+deinsum_status mttkrp_via_ttmc_workspace(const int64_t *dims, int64_t R, int prec, int variant, size_t *bytes);
+deinsum_status run_mttkrp_via_ttmc(const int64_t *dims, int64_t R, const void *X, const void *U1, const void *U2,
+                                   void *M, int prec, int out_dtype, int variant, void *ws, size_t ws_bytes,
+                                   hipStream_t s);
+
 }  // namespace deinsum

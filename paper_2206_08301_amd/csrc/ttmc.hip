@@ -21,6 +21,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "internal.h"
 #include "kernels.h"
 #include "mttkrp.h"
 #include "ttmc.h"
@@ -902,6 +903,62 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         src = static_cast<const double *>(dst);
     }
     return DEINSUM_OK;
+}
+
+namespace {
+
+__global__ void __launch_bounds__(256) diag_kernel(const double *Y, int64_t I, int64_t R, void *M, int out_dtype)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= I * R) return;
+    const int64_t i = e / R, r = e % R;
+    const double v = Y[(i * R + r) * R + r];
+    if (out_dtype == DEINSUM_F64) static_cast<double *>(M)[e] = v;
+    else static_cast<float *>(M)[e] = static_cast<float>(v);
+}
+
+deinsum_status m0_ttmc_setup(const int64_t *dims, int64_t R, int prec, int variant, deinsum_spec *sp,
+                             deinsum_opts *o, size_t *ttmc_bytes)
+{
+    if (deinsum_status st = parse_spec("ijk,jb,kc->ibc", sp)) return st;
+    const int64_t ranks[2] = {R, R};
+    deinsum_opts_init(o);
+    o->precision = prec;
+    o->out_dtype = DEINSUM_F64;
+    o->plan_hint = variant;
+    return ttmc_workspace_size(sp, dims, ranks, *o, ttmc_bytes);
+}
+
+}  // namespace
+
+deinsum_status mttkrp_via_ttmc_workspace(const int64_t *dims, int64_t R, int prec, int variant, size_t *bytes)
+{
+    deinsum_spec sp;
+    deinsum_opts o;
+    size_t need = 0;
+    if (deinsum_status st = m0_ttmc_setup(dims, R, prec, variant, &sp, &o, &need)) return st;
+    *bytes = (need + 255) / 256 * 256 + static_cast<size_t>(dims[0] * R * R) * sizeof(double);
+    return DEINSUM_OK;
+}
+
+deinsum_status run_mttkrp_via_ttmc(const int64_t *dims, int64_t R, const void *X, const void *U1, const void *U2,
+                                   void *M, int prec, int out_dtype, int variant, void *ws, size_t ws_bytes,
+                                   hipStream_t s)
+{
+    deinsum_spec sp;
+    deinsum_opts o;
+    size_t need = 0;
+    if (deinsum_status st = m0_ttmc_setup(dims, R, prec, variant, &sp, &o, &need)) return st;
+    const size_t ybytes = static_cast<size_t>(dims[0] * R * R) * sizeof(double);
+    const size_t yoff = (need + 255) / 256 * 256;
+    if (ws_bytes < yoff + ybytes) return fail(DEINSUM_ERR_NO_MEMORY, "mttkrp via ttmc: workspace too small");
+    double *Y = reinterpret_cast<double *>(static_cast<char *>(ws) + yoff);
+    const int64_t ranks[2] = {R, R};
+    const void *U[2] = {U1, U2};
+    if (deinsum_status st = run_ttmc(&sp, dims, ranks, X, U, Y, o, ws, need, s)) return st;
+    const int64_t total = dims[0] * R;
+    diag_kernel<<<static_cast<unsigned>(cdivl(total, 256)), 256, 0, s>>>(Y, dims[0], R, M, out_dtype);
+    return check_launch("mttkrp_via_ttmc_diag");
 }
 
 }  // namespace deinsum

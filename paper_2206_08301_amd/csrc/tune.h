@@ -8,12 +8,15 @@
 namespace deinsum {
 
 enum TunePath { TUNE_STREAM = 0, TUNE_BATCH = 1 };
+constexpr int kTuneViaTtmc = 2;
 
 // A tuned choice: the tile shape (kernel variant) and the outer-chunk count.
 struct TuneChoice {
     int nt = 0, ni = 0, mt = 0, xnt = 0;
     int split = 0;
-    int order = 0, xcd = 0;  // unit order and XCD remap of the per-call kernel
+    int order = 0, xcd = 0;  // unit order and XCD remap of the per-call kernel; order
+                             // kTuneViaTtmc: mode 0 runs through the fused TTMc pass,
+                             // split holding its variant
     double us = 0;           // measured median time of the winner
 };
 

@@ -230,3 +230,34 @@ def test_merged_last_modes_match_unmerged(dn, synth, oracle_mod, precision, tol,
                                               + dims[n] * R * 8)
         assert nrel(merged.cpu().numpy(), ref) <= tol
         assert nrel(plain.cpu().numpy(), ref) <= tol
+
+
+@pytest.mark.parametrize("dims,R", [((33, 70, 130), 24), ((20, 64, 300), 64), ((17, 9, 40), 5)])
+def test_mode0_through_fused_ttmc_pass(dn, oracle_mod, tmp_path, dims, R):
+    """Order-3 mode 0 in FP64 through the fused TTMc pass (selected here by a plan-cache
+    entry with order 2), against the oracle and against the K-contiguous kernel."""
+    rng = np.random.default_rng(R + dims[2])
+    X = rng.uniform(-1, 1, dims)
+    U = factors_for(rng, dims, R, 0)
+    ref = oracle_mod.mttkrp(X, U, 0)
+    Xd, ops = to_dev(X), [to_dev(u) for u in operands(U, 0)]
+    dn.tune_clear()
+    dn.tune_mttkrp(SPEC3[0], Xd, ops, reps=1)
+    cache = tmp_path / "cache.txt"
+    dn.tune_save(str(cache))
+    key = [l.split()[0] for l in cache.read_text().splitlines() if l.strip() and not l.startswith("#")][0]
+    for hint in (1, 2):
+        cache.write_text(f"{key} 1 1 1 0 {hint - 1} 2 0 0\n")
+        dn.tune_clear()
+        dn.tune_load(str(cache))
+        rep = dn.Report()
+        got = dn.mttkrp(SPEC3[0], Xd, ops, report=rep)
+        torch.cuda.synchronize()
+        name = rep.plan_name.decode()
+        flush(f"dims={dims} R={R}: {name}")
+        assert name.startswith("mttkrp_via_ttmc"), name
+        assert nrel(got.cpu().numpy(), ref) <= 1e-12
+    dn.tune_clear()
+    plain = dn.mttkrp(SPEC3[0], Xd, ops, plan_hint=1)
+    torch.cuda.synchronize()
+    assert nrel(plain.cpu().numpy(), ref) <= 1e-12
