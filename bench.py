@@ -177,7 +177,7 @@ def alg_counts(dims, R, n, xbytes):
 def main():
     args = parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is not part of it",
+        print(json.dumps({"error": "this benchmark runs on one GPU; sharding across GPUs is not implemented",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
     import numpy as np
