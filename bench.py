@@ -224,7 +224,7 @@ def main():
     if steps:
         for n in range(3):
             if tune:  # the library's autotuner picks each mode's plan (untimed, cached)
-                dn.tune_mttkrp(SPECS[n], X, ops[n], out=outs[n], reps=3)
+                dn.tune_mttkrp(SPECS[n], X, ops[n], out=outs[n], reps=5)
             dn.mttkrp(SPECS[n], X, ops[n], out=outs[n], report=reports[n])
         for _ in range(warmup):
             step()
@@ -359,7 +359,7 @@ def main():
                   for m in (1, 2)]
             Y = torch.empty((1024, Rt, Rt), dtype=torch.float64, device=dev)
             if tune:
-                dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y, tune_reps=3)
+                dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y, tune_reps=7)
             for _ in range(2):
                 dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y)
             evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
