@@ -6,7 +6,7 @@ MTTKRP in every mode (0, 1, 2) in the plain FP64 form.  X and the factors are
 resident in HBM before the timed region.  The JSON line reports GFLOP/s of the
 two-stage method, the HBM roofline of the dominant kernel, the mixed-precision
 forms (X stored FP32 / BF16) with their error against the FP64 oracle on
-sampled rows, the Tucker-step TTMc (1024^3, ranks 32) and the CPU oracle timed
+sampled rows, the Tucker-step TTMc (1024^3, ranks 32; FP64, FP32, BF16) and the CPU oracle timed
 on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extras] [--no-cpu]
@@ -136,16 +136,20 @@ def more_workloads(dn, synth, torch, stream, tune):
     B = [torch.from_numpy(synth.orthonormal_factor(synth.config_seed(4, 1 + m), 192, R4)).to(dev) for m in (1, 2, 3)]
     X32 = torch.empty(D4, dtype=torch.float32, device=dev)
     dn.convert(X, X32)
+    X16 = torch.empty(D4, dtype=torch.bfloat16, device=dev)
+    dn.convert(X, X16)
     Y64 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
     Y32 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
+    Y16 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
     row = {}
     nx = 192 ** 4
-    for form, Xp, Bp, Y in (("fp64", X, B, Y64), ("fp32", X32, [b.float() for b in B], Y32)):
+    B32 = [b.float() for b in B]
+    for form, Xp, Bp, Y in (("fp64", X, B, Y64), ("fp32", X32, B32, Y32), ("bf16", X16, B32, Y16)):
         if tune:
             dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y, tune_reps=2)
         t = event_median(torch, stream, lambda: dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y))
-        xb = 8 if form == "fp64" else 4
-        byts = nx * xb + 3 * 192 * R4 * xb + 192 * R4 ** 3 * 8
+        xb = {"fp64": 8, "fp32": 4, "bf16": 2}[form]
+        byts = nx * xb + 3 * 192 * R4 * (8 if form == "fp64" else 4) + 192 * R4 ** 3 * 8
         e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
              "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         if form != "fp64":
@@ -156,7 +160,7 @@ def more_workloads(dn, synth, torch, stream, tune):
     print(f"[bench] ttmc order-4: {row}", file=sys.stderr, flush=True)
     out["ttmc_order4"] = {"workload": "TTMc order 4 mode 0, X 192^4 FP64 (10.9 GB), ranks 16, orthonormal factors",
                           "forms": row}
-    del X, X32, Y64, Y32
+    del X, X32, X16, Y64, Y32, Y16
     torch.cuda.empty_cache()
     return out
 
@@ -381,6 +385,27 @@ def main():
                               "ms": round(t, 4), "GB/s": round(b / (t / 1e3) / 1e9, 1),
                               "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                               "GFLOP/s": round(f / (t / 1e3) / 1e9, 1), "max_rel_err_sampled": max(errs)}
+            # reduced-precision forms of the same TTMc: X stored FP32 / BF16, FP32 factors
+            tforms = {}
+            B32 = [b_.float() for b_ in Bt]
+            for form, tdt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+                Xt = torch.empty(DIMS, dtype=tdt, device=dev)
+                dn.convert(X, Xt)
+                Yt = torch.empty_like(Y)
+                if tune:
+                    dn.ttmc("ijk,jb,kc->ibc", Xt, B32, precision=form, out=Yt, tune_reps=7)
+                tt = event_median(torch, stream, lambda: dn.ttmc("ijk,jb,kc->ibc", Xt, B32, precision=form, out=Yt))
+                xb = 4 if form == "fp32" else 2
+                bt = nx * xb + 2 * 1024 * Rt * 4 + 1024 * Rt * Rt * 8
+                torch.cuda.synchronize()
+                tforms[form] = {"ms": round(tt, 4), "GB/s": round(bt / (tt / 1e3) / 1e9, 1),
+                                "frac_hbm": round(bt / (tt / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "speedup_vs_fp64": round(t / tt, 3),
+                                "rel_err_vs_fp64": float((Yt - Y).norm() / Y.norm())}
+                del Xt, Yt
+                torch.cuda.empty_cache()
+            result["ttmc"]["forms"] = tforms
+            print(f"[bench] ttmc forms: {tforms}", file=sys.stderr, flush=True)
     result["checks"] = checks
 
     # ---- the other single-GPU workloads: order-5 MTTKRP and order-4 TTMc (extras)

@@ -33,11 +33,25 @@ namespace {
 
 constexpr int kMaxTtmcRank = 64;
 
+// Per form: X element, stage-1 factor element (UT), stage-2 factor element (CT),
+// accumulator tile, rows of the contracted mode a per matrix-core K step (KR) and
+// per lane (LR).  The factor copies the kernel reads are zero-padded to whole
+// column tiles: FP64 and FP32 in the form's type, row-major; BF16 stage-1 packed
+// per K block and lane (eight rows of one column per lane, one 16-byte load),
+// stage 2 in FP32.
 template <int P> struct TkTypes;
-template <> struct TkTypes<P_FP64> { using XT = double; using DT = f64x4; };
-template <> struct TkTypes<P_FP32> { using XT = float;  using DT = f32x4; };
-// The factor copies the fused kernel reads are zero-padded to whole column tiles
-// and stored in the form's element type (FP64 or FP32).
+template <> struct TkTypes<P_FP64> {
+    using XT = double; using UT = double; using CT = double; using DT = f64x4;
+    static constexpr int KR = 4, LR = 1;
+};
+template <> struct TkTypes<P_FP32> {
+    using XT = float; using UT = float; using CT = float; using DT = f32x4;
+    static constexpr int KR = 4, LR = 1;
+};
+template <> struct TkTypes<P_BF16> {
+    using XT = uint16_t; using UT = u16x8; using CT = float; using DT = f32x4;
+    static constexpr int KR = 32, LR = 8;
+};
 
 __device__ __forceinline__ int64_t tmin(int64_t a, int64_t b) { return a < b ? a : b; }
 
@@ -111,20 +125,22 @@ struct SlabWalk {
 template <int P, int NTA, int NTC, int MT, bool STAGE2, int UB, int NBUF, bool XNT>
 __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
 {
-    // UB: K-steps (of 4 rows) per ring step; NBUF: ring depth.
+    // UB: K-steps (of KR rows) per ring step; NBUF: ring depth.
     using XT = typename TkTypes<P>::XT;
-    using UT = XT;
+    using UT = typename TkTypes<P>::UT;
+    using CT = typename TkTypes<P>::CT;
     using DT = typename TkTypes<P>::DT;
+    constexpr int KR = TkTypes<P>::KR, LR = TkTypes<P>::LR;
     constexpr int TA = 16 * NTA, TC = 16 * NTC;
     // Stage-2 factor rows of the workgroup held in LDS when they fit in 32 KB (they
     // are the same for every slab); per-wave Z tiles summed after one barrier when
     // the workgroup's LDS stays within 40 KB (four workgroups per CU), else
     // accumulated wave by wave in one tile.
     constexpr int CROWS = 4 * 16 * MT;
-    constexpr size_t UC_BYTES = static_cast<size_t>(CROWS) * TC * sizeof(UT);
+    constexpr size_t UC_BYTES = static_cast<size_t>(CROWS) * TC * sizeof(CT);
     constexpr bool UC_LDS = STAGE2 && UC_BYTES <= 32768;
     constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) + (UC_LDS ? UC_BYTES : 0) <= 40960;
-    __shared__ UT lds_uc[UC_LDS ? CROWS * TC : 1];
+    __shared__ CT lds_uc[UC_LDS ? CROWS * TC : 1];
     __shared__ double lds[STAGE2 ? (Z_PAR ? 4 * TA * TC : TA * TC) : 1];
 
     const int lane = threadIdx.x & 63;
@@ -150,10 +166,11 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
     const int64_t s0 = sg * a.slabs_per_group;
     const int64_t s1 = tmin(a.n_slabs, s0 + a.slabs_per_group);
     const XT *__restrict__ X = static_cast<const XT *>(a.X);
-    const UT *__restrict__ Ua = static_cast<const UT *>(a.Ua);  // zero-padded copy, row stride TA
-    const UT *__restrict__ Uc = static_cast<const UT *>(a.Uc);  // zero-padded copy, row stride TC
-    const int64_t nsteps = (a.Ia + 4 * UB - 1) / (4 * UB);
-    const int64_t nfull = a.Ia / (4 * UB);            // ring steps whose rows are all in range
+    const XT *__restrict__ Ua = static_cast<const XT *>(a.Ua);  // zero-padded copy (row stride TA, or packed)
+    const CT *__restrict__ Uc = static_cast<const CT *>(a.Uc);  // zero-padded copy, row stride TC
+    const int64_t nsteps = (a.Ia + KR * UB - 1) / (KR * UB);
+    const int64_t nfull = a.Ia / (KR * UB);           // ring steps whose rows are all in range
+    const int64_t nkb = (a.Ia + KR - 1) / KR;         // K steps with any row in range
     const int64_t nsp = (nsteps + NBUF - 1) / NBUF * NBUF;  // whole ring turns per slab
 
     const int64_t crow0 = static_cast<int64_t>(cgroup) * a.nwaves * 16 * MT;
@@ -161,14 +178,18 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
         const int n = a.nwaves * 16 * MT * TC;
         for (int i = threadIdx.x; i < n; i += 64 * a.nwaves) {
             const int64_t row = crow0 + i / TC;
-            lds_uc[i] = row < a.Ic ? Uc[row * TC + i % TC] : UT{};
+            lds_uc[i] = row < a.Ic ? Uc[row * TC + i % TC] : CT{};
         }
         __syncthreads();
     }
 
     auto run = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        XT xb[NBUF][UB][MT];
+        // The lane's LR rows of X per K step, MT indices each (BF16: two per 32-bit word).
+        static_assert(P != P_BF16 || MT % 2 == 0, "BF16 tiles hold whole words");
+        constexpr int XWN = (P == P_BF16) ? MT / 2 : MT;
+        using XWT = std::conditional_t<P == P_BF16, uint32_t, XT>;
+        XWT xb[NBUF][UB][LR][XWN];
         UT ub[NBUF][UB][NTA];
         // Ring step st of the slab at xsrc into ring slot `slot`.  FULL and unguarded:
         // a fixed sequence of unmasked vector loads, so the compiler waits for exactly
@@ -176,24 +197,48 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
         auto issue = [&](int slot, const XT *xsrc, int64_t st, bool guard, bool live) {
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
-                const int64_t r = (st * UB + u) * 4 + g;
-                const bool rv = live && (!guard || r < a.Ia);
+                const int64_t kb = st * UB + u;  // K step
+                if constexpr (P == P_BF16) {
+                    // B operand: eight rows of one column, packed per lane by the pad kernel.
+                    const bool bv = live && kb < nkb;
 #pragma unroll
-                for (int nt = 0; nt < NTA; ++nt) ub[slot][u][nt] = rv ? Ua[r * TA + nt * 16 + c] : UT{};
-                if constexpr (FULL && (V * sizeof(XT)) % 8 == 0) {
-                    if (rv) {
+                    for (int nt = 0; nt < NTA; ++nt)
+                        ub[slot][u][nt] = bv ? *reinterpret_cast<const u16x8 *>(Ua + ((kb * NTA + nt) * 64 + lane) * 8)
+                                             : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                }
 #pragma unroll
-                        for (int j = 0; j < NCH; ++j)
-                            load_vec_n<XT, V, XNT>(xb[slot][u] + j * V, xsrc + r * a.stride_a + j * 16 * V);
-                    } else {
+                for (int q = 0; q < LR; ++q) {
+                    // lane group g holds K slots LR*g .. LR*g + LR-1 of the step (KR = 4 * LR rows)
+                    const int64_t r = kb * KR + LR * g + q;
+                    const bool rv = live && (!guard || r < a.Ia);
+                    if constexpr (P != P_BF16) {
 #pragma unroll
-                        for (int i = 0; i < MT; ++i) xb[slot][u][i] = XT{};
+                        for (int nt = 0; nt < NTA; ++nt) ub[slot][u][nt] = rv ? Ua[r * TA + nt * 16 + c] : UT{};
                     }
-                } else {
+                    if constexpr (FULL && (V * sizeof(XT)) % 8 == 0) {
+                        if (rv) {
 #pragma unroll
-                    for (int i = 0; i < MT; ++i) {
-                        const int64_t e = (i / V) * 16 * V + i % V;
-                        xb[slot][u][i] = (rv && ibase + e < a.Ic) ? xsrc[r * a.stride_a + e] : XT{};
+                            for (int j = 0; j < NCH; ++j)
+                                load_vec_n<XWT, V * sizeof(XT) / sizeof(XWT), XNT>(
+                                    xb[slot][u][q] + j * V * sizeof(XT) / sizeof(XWT),
+                                    reinterpret_cast<const XWT *>(xsrc + r * a.stride_a + j * 16 * V));
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < XWN; ++i) xb[slot][u][q][i] = XWT{};
+                        }
+                    } else {
+                        auto elem = [&](int i) {
+                            const int64_t e = (i / V) * 16 * V + i % V;
+                            return (rv && ibase + e < a.Ic) ? xsrc[r * a.stride_a + e] : XT{};
+                        };
+#pragma unroll
+                        for (int i = 0; i < XWN; ++i) {
+                            if constexpr (P == P_BF16)
+                                xb[slot][u][q][i] = static_cast<uint32_t>(elem(2 * i)) |
+                                                    (static_cast<uint32_t>(elem(2 * i + 1)) << 16);
+                            else
+                                xb[slot][u][q][i] = elem(i);
+                        }
                     }
                 }
             }
@@ -203,14 +248,29 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
 #pragma unroll
             for (int u = 0; u < UB; ++u)
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                for (int mt = 0; mt < MT; ++mt) {
+                    if constexpr (P == P_BF16) {
+                        // A operand: index mt of the lane's eight rows, two BF16 values per word
+                        uint32_t w4[4];
+                        constexpr uint32_t kLo = 0x05040100u, kHi = 0x07060302u;  // low / high halves
 #pragma unroll
-                    for (int nt = 0; nt < NTA; ++nt) {
-                        if constexpr (P == P_FP64)
-                            d[mt][nt] = mfma_f64(xb[slot][u][mt], ub[slot][u][nt], d[mt][nt]);
-                        else
-                            d[mt][nt] = mfma_f32(xb[slot][u][mt], ub[slot][u][nt], d[mt][nt]);
+                        for (int k = 0; k < 4; ++k)
+                            w4[k] = __builtin_amdgcn_perm(xb[slot][u][2 * k + 1][mt / 2], xb[slot][u][2 * k][mt / 2],
+                                                          (mt & 1) ? kHi : kLo);
+                        u16x8 av;
+                        __builtin_memcpy(&av, w4, 16);
+#pragma unroll
+                        for (int nt = 0; nt < NTA; ++nt) d[mt][nt] = mfma_bf16(av, ub[slot][u][nt], d[mt][nt]);
+                    } else {
+#pragma unroll
+                        for (int nt = 0; nt < NTA; ++nt) {
+                            if constexpr (P == P_FP64)
+                                d[mt][nt] = mfma_f64(xb[slot][u][0][mt], ub[slot][u][nt], d[mt][nt]);
+                            else
+                                d[mt][nt] = mfma_f32(xb[slot][u][0][mt], ub[slot][u][nt], d[mt][nt]);
+                        }
                     }
+                }
         };
 
         SlabWalk walk;
@@ -265,9 +325,9 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                         const bool rv = ctile < a.n_ctiles && rowc < a.Ic;
 #pragma unroll
                         for (int tc = 0; tc < NTC; ++tc) {
-                            UT u;
+                            CT u;
                             if constexpr (UC_LDS) u = lds_uc[(rowc - crow0) * TC + tc * 16 + c];  // zero past I_c
-                            else u = rv ? Uc[rowc * TC + tc * 16 + c] : UT{};
+                            else u = rv ? Uc[rowc * TC + tc * 16 + c] : CT{};
 #pragma unroll
                             for (int ta = 0; ta < NTA; ++ta) {
                                 if constexpr (P == P_FP64)
@@ -345,6 +405,30 @@ __global__ void __launch_bounds__(256) pad_factor_kernel(const T *src, int64_t r
     const int64_t i = e / ldd;
     const int j = static_cast<int>(e % ldd);
     dst[e] = (j < r) ? src[i * r + j] : T{};
+}
+
+// BF16 stage-1 factor: for K step kb (rows 32 kb ..), column tile nt and lane
+// (g, c), the eight BF16 values of rows 32 kb + 8 g .. + 7 in column 16 nt + c,
+// contiguous (one 16-byte load per lane); zero past the factor's rows and columns.
+__global__ void __launch_bounds__(256) pack_factor_bf16_kernel(const float *src, int64_t rows, int r, int nta,
+                                                              int64_t nkb, uint16_t *dst)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nkb * nta * 512) return;
+    const int q = static_cast<int>(e % 8);
+    const int lane = static_cast<int>((e / 8) % 64);
+    const int nt = static_cast<int>((e / 512) % nta);
+    const int64_t kb = e / (512 * static_cast<int64_t>(nta));
+    const int64_t row = kb * 32 + 8 * (lane >> 4) + q;
+    const int col = nt * 16 + (lane & 15);
+    dst[e] = (row < rows && col < r) ? f32_to_bf16_bits(src[row * r + col]) : uint16_t{0};
+}
+
+// Bytes of the padded stage-1 factor copy of a rows x (16 nta) tile set.
+size_t stage1_factor_bytes(int prec, int64_t rows, int nta)
+{
+    if (prec == P_BF16) return static_cast<size_t>((rows + 31) / 32) * nta * 512 * sizeof(uint16_t);
+    return static_cast<size_t>(rows) * 16 * nta * (prec == P_FP64 ? 8 : 4);
 }
 
 // Sum `parts` padded partial tensors and scatter into a strided destination.
@@ -523,8 +607,14 @@ const TkEntry kTkTable[] = {
     TK(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 1, 4, 4, 2), TK(P_FP32, 2, 2, 4, 2, 4), TKN(P_FP32, 2, 2, 4, 2, 4),
     TK(P_FP32, 2, 2, 4, 4, 2), TK(P_FP32, 2, 2, 8, 2, 2), TKN(P_FP32, 2, 2, 8, 2, 2),
     TK(P_FP32, 1, 1, 8, 2, 3), TKN(P_FP32, 1, 1, 8, 2, 3),
+    TKN(P_BF16, 1, 1, 4, 1, 3), TK(P_BF16, 1, 2, 4, 1, 3), TK(P_BF16, 1, 4, 4, 1, 3), TK(P_BF16, 2, 1, 4, 1, 3),
+    TK(P_BF16, 2, 2, 4, 1, 3), TK(P_BF16, 2, 4, 4, 1, 2), TK(P_BF16, 4, 1, 4, 1, 2), TK(P_BF16, 4, 2, 4, 1, 2),
+    TK(P_BF16, 4, 4, 2, 1, 2),
+    TK(P_BF16, 1, 1, 4, 1, 3), TK(P_BF16, 1, 1, 8, 1, 2), TKN(P_BF16, 2, 2, 4, 1, 3), TK(P_BF16, 2, 2, 4, 1, 2),
+    TKN(P_BF16, 2, 2, 4, 1, 2),
     TK1(P_FP64, 1, 4, 2, 4), TK1(P_FP64, 2, 2, 2, 4), TK1(P_FP64, 4, 1, 2, 4),
     TK1(P_FP32, 1, 4, 2, 4), TK1(P_FP32, 2, 4, 2, 4), TK1(P_FP32, 4, 2, 2, 4),
+    TK1(P_BF16, 1, 4, 1, 3), TK1(P_BF16, 2, 4, 1, 2), TK1(P_BF16, 4, 4, 1, 2),
 };
 #undef TK
 #undef TKN
@@ -592,8 +682,8 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
             return fail(DEINSUM_ERR_SHAPE, "TTMc ranks must be 1.." + std::to_string(kMaxTtmcRank));
         p.Rm[m] = r;
     }
-    if (prec != P_FP64 && prec != P_FP32)
-        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64 and FP32 forms");
+    if (prec != P_FP64 && prec != P_FP32 && prec != P_BF16)
+        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64, FP32 and BF16 forms");
     const int N = p.N, n = p.n;
     if (N == 2 && n == 0) {  // a single product over the contiguous mode: the MTTKRP kernel computes it
         p.via_mttkrp = true;
@@ -655,7 +745,8 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
         p.t_bytes = static_cast<size_t>(mx) * 8;
     }
     auto align = [](size_t x) { return (x + 255) / 256 * 256; };
-    p.pad_bytes = align(static_cast<size_t>(p.I[p.a]) * TA * 8) + (p.stage2 ? align(static_cast<size_t>(p.I[p.c]) * TC * 8) : 0);
+    p.pad_bytes = align(stage1_factor_bytes(prec, p.I[p.a], p.nta)) +
+                  (p.stage2 ? align(static_cast<size_t>(p.I[p.c]) * TC * 8) : 0);
     p.total = align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes) + p.pad_bytes;
     *out = p;
     return DEINSUM_OK;
@@ -696,7 +787,8 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     if (o.plan_hint < 0) return fail(DEINSUM_ERR_INVALID_ARG, "TTMc plan_hint must be >= 0");
     if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, o.plan_hint, &p)) return st;
     const int N = p.N, n = p.n;
-    const size_t xb = o.precision == P_FP64 ? 8 : 4, ub = xb;
+    const size_t xb = o.precision == P_FP64 ? 8 : (o.precision == P_FP32 ? 4 : 2);
+    const size_t ub = o.precision == P_FP64 ? 8 : 4;  // factors: FP64, else FP32
     const size_t ob = o.out_dtype == DEINSUM_F64 ? 8 : 4;
     const void *Um[DEINSUM_MAX_ORDER] = {nullptr};
     int64_t nx = 1, ny = 1;
@@ -745,7 +837,7 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     double *T0 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes));
     double *T1 = reinterpret_cast<double *>(base + align(p.p_bytes) + align(p.z_bytes) + align(p.t_bytes));
     char *Ua_pad = base + align(p.p_bytes) + align(p.z_bytes) + 2 * align(p.t_bytes);
-    char *Uc_pad = Ua_pad + align(static_cast<size_t>(p.I[p.a]) * 16 * p.nta * 8);
+    char *Uc_pad = Ua_pad + align(stage1_factor_bytes(o.precision, p.I[p.a], p.nta));
     {
         auto pad = [&](int m, int ld, char *dst) {
             const int64_t n = p.I[m] * ld;
@@ -757,7 +849,14 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
                 pad_factor_kernel<float><<<grid, 256, 0, s>>>(static_cast<const float *>(Um[m]), p.I[m],
                                                               static_cast<int>(p.Rm[m]), ld, reinterpret_cast<float *>(dst));
         };
-        pad(p.a, 16 * p.nta, Ua_pad);
+        if (o.precision == P_BF16) {
+            const int64_t nkb = cdivl(p.I[p.a], 32), n = nkb * p.nta * 512;
+            pack_factor_bf16_kernel<<<static_cast<unsigned>(cdivl(n, 256)), 256, 0, s>>>(
+                static_cast<const float *>(Um[p.a]), p.I[p.a], static_cast<int>(p.Rm[p.a]), p.nta, nkb,
+                reinterpret_cast<uint16_t *>(Ua_pad));
+        } else {
+            pad(p.a, 16 * p.nta, Ua_pad);
+        }
         if (p.stage2) pad(p.c, 16 * p.ntc, Uc_pad);
         if (deinsum_status st = check_launch("ttmc_pad_factor")) return st;
     }
@@ -893,7 +992,7 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         }
         t.U = Um[m];
         t.ldu = p.Rm[m];
-        t.uprec = o.precision;
+        t.uprec = o.precision == P_FP64 ? P_FP64 : P_FP32;  // factor storage
         t.out = dst;
         t.out_dtype = last ? o.out_dtype : DEINSUM_F64;
         const size_t ubytes = static_cast<size_t>(t.Im * cdivl(p.Rm[m], kTtmRB) * kTtmRB) * 8;

@@ -46,15 +46,35 @@ def test_ttmc_all_modes(dn, oracle_mod, dims, ranks, precision, tol):
         assert nrel(got.cpu().numpy(), ref) <= tol, (dims, n)
 
 
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_ttmc_bf16_all_modes(dn, synth, oracle_mod, dims, ranks):
+    """BF16 form on inputs already representable in BF16 (X and factors rounded on the host):
+    what remains is FP32 accumulation inside a matrix-core step, FP64 beyond."""
+    rng = np.random.default_rng(sum(dims) + 16)
+    X = synth.bf16_round(rng.uniform(-1, 1, dims)).astype(np.float64)
+    Xd = to_dev(X, torch.float32).to(torch.bfloat16)
+    for n in range(len(dims)):
+        flush(f"ttmc bf16 dims={dims} n={n}")
+        U = [None if m == n else synth.bf16_round(rng.standard_normal((d, ranks[m]))).astype(np.float64)
+             for m, d in enumerate(dims)]
+        ref = oracle_mod.ttmc(X, U, n)
+        got = dn.einsum(ttmc_spec(len(dims), n), Xd, *[to_dev(u, torch.float32) for u in U if u is not None],
+                        precision="bf16", out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert nrel(got.cpu().numpy(), ref) <= 1e-5, (dims, n)
+
+
 def test_ttmc_integer_exact(dn, synth, oracle_mod):
     dims = (40, 64, 96)
     X = synth.x_tensor(99, dims, "int5")
     rng = np.random.default_rng(1)
-    for precision, dt in [("fp64", torch.float64), ("fp32", torch.float32)]:
+    for precision, dt in [("fp64", torch.float64), ("fp32", torch.float32), ("bf16", torch.bfloat16)]:
+        udt = torch.float64 if precision == "fp64" else torch.float32
         for n in range(3):
             U = [None if m == n else rng.integers(-2, 3, (d, 16)).astype(np.float64) for m, d in enumerate(dims)]
             ref = oracle_mod.ttmc(X, U, n)
-            got = dn.einsum(ttmc_spec(3, n), to_dev(X, dt), *[to_dev(u, dt) for u in U if u is not None],
+            Xd = to_dev(X, torch.float32).to(torch.bfloat16) if dt == torch.bfloat16 else to_dev(X, dt)
+            got = dn.einsum(ttmc_spec(3, n), Xd, *[to_dev(u, udt) for u in U if u is not None],
                             precision=precision, out_dtype=torch.float64)
             torch.cuda.synchronize()
             assert np.array_equal(got.cpu().numpy(), ref), (precision, n)
@@ -120,5 +140,31 @@ def test_ttmc_every_kernel_variant(dn, oracle_mod, dims, ranks):
         torch.cuda.synchronize()
         flush(f"ttmc variant {v} dims={dims}: {nrel(got.cpu().numpy(), ref):.2e}")
         assert nrel(got.cpu().numpy(), ref) <= 1e-12, v
+        seen += 1
+    assert seen >= 1
+
+
+@pytest.mark.parametrize("dims,ranks", [((40, 70, 130), (8, 32, 24)), ((24, 60, 50, 70), (3, 40, 20, 64)),
+                                        ((6, 33, 70), (4, 16, 16))])
+def test_ttmc_bf16_every_kernel_variant(dn, synth, oracle_mod, dims, ranks):
+    """Every compiled BF16 fused-kernel variant for the ranks, on BF16-representable inputs."""
+    rng = np.random.default_rng(sum(dims) + 3)
+    X = synth.bf16_round(rng.uniform(-1, 1, dims)).astype(np.float64)
+    Xd = to_dev(X, torch.float32).to(torch.bfloat16)
+    U = [None] + [synth.bf16_round(rng.standard_normal((d, ranks[m]))).astype(np.float64)
+                  for m, d in enumerate(dims) if m > 0]
+    ref = oracle_mod.ttmc(X, U, 0)
+    Ud = [to_dev(u, torch.float32) for u in U[1:]]
+    seen = 0
+    for v in range(8):
+        try:
+            got = dn.ttmc(ttmc_spec(len(dims), 0), Xd, Ud, precision="bf16", out_dtype=torch.float64, variant=v)
+        except dn.DeinsumError as e:
+            assert e.status == -1  # no such variant
+            break
+        torch.cuda.synchronize()
+        err = nrel(got.cpu().numpy(), ref)
+        flush(f"ttmc bf16 variant {v} dims={dims}: {err:.2e}")
+        assert err <= 1e-5, v
         seen += 1
     assert seen >= 1
