@@ -87,9 +87,11 @@ def event_median(torch, stream, fn, reps=10):
 
 
 def more_workloads(dn, synth, torch, stream, tune):
-    """Order-5 MTTKRP (80^5, R=24, modes 0 and 2: FP64, FP32, FX20) and order-4 TTMc
-    (192^4, ranks 16, mode 0: FP64, FP32).  Reduced forms report their error against
-    the FP64 result of the same call (which the GPU tests pin to the oracle)."""
+    """Order-5 MTTKRP (80^5, R=24, modes 0 and 2: FP64, FP32, FX20), order-4 TTMc (192^4,
+    ranks 16, mode 0: FP64, FP32, BF16), and the paper's order-5 forms at 60^5, R=24
+    (MTTKRP mode 4: FP64, FP32, FX20; TTMc mode 0: FP64, FP32, BF16).  Reduced forms
+    report their error against the FP64 result of the same call (which the GPU tests
+    pin to the oracle)."""
     dev = torch.device("cuda:0")
     out = {}
     D5, R5 = (80,) * 5, 24
@@ -161,6 +163,64 @@ def more_workloads(dn, synth, torch, stream, tune):
     out["ttmc_order4"] = {"workload": "TTMc order 4 mode 0, X 192^4 FP64 (10.9 GB), ranks 16, orthonormal factors",
                           "forms": row}
     del X, X32, X16, Y64, Y32, Y16
+    torch.cuda.empty_cache()
+
+    # The paper's order-5 forms at I = 60, R = 24: MTTKRP in the last mode, TTMc in mode 0.
+    D6, R6 = (60,) * 5, 24
+    nx = 60 ** 5
+    X = torch.empty(D6, dtype=torch.float64, device=dev)
+    dn.synth_fill(X, synth.config_seed(3, 60))
+    U = [torch.from_numpy(synth.normal_factor(synth.config_seed(3, 61 + m), 60, R6)).to(dev) for m in range(5)]
+    U32 = [u.float() for u in U]
+    X32 = torch.empty(D6, dtype=torch.float32, device=dev)
+    dn.convert(X, X32)
+    X16 = torch.empty(D6, dtype=torch.bfloat16, device=dev)
+    dn.convert(X, X16)
+    Xf = dn.to_fx20(X)
+    spec = "abcde,az,bz,cz,dz->ez"
+    M64 = torch.empty((60, R6), dtype=torch.float64, device=dev)
+    M32 = torch.empty((60, R6), dtype=torch.float64, device=dev)
+    row = {}
+    for form, Xp, opsp in (("fp64", X, U[:4]), ("fp32", X32, U32[:4]), ("fx20", Xf, U32[:4])):
+        M = M64 if form == "fp64" else M32
+        if tune:
+            dn.tune_mttkrp(spec, Xp, opsp, precision=form, out=M, reps=3)
+        t = event_median(torch, stream, lambda: dn.mttkrp(spec, Xp, opsp, precision=form, out=M))
+        xb = {"fp64": 8, "fp32": 4, "fx20": 3}[form]
+        byts = nx * xb + 4 * 60 * R6 * (8 if form == "fp64" else 4) + 60 * R6 * 8
+        e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
+             "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if form != "fp64":
+            torch.cuda.synchronize()
+            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
+            e["rel_err_vs_fp64"] = float((M - M64).norm() / M64.norm())
+        row[form] = e
+    print(f"[bench] order-5 60^5 mttkrp mode 4: {row}", file=sys.stderr, flush=True)
+    out["mttkrp_order5_last_mode"] = {"workload": "MTTKRP order 5, X 60^5 FP64 (6.2 GB), R=24, mode 4 (last)",
+                                      "forms": row}
+    del Xf
+    tspec = "abcde,bw,cx,dy,ez->awxyz"
+    Y64 = torch.empty((60, R6, R6, R6, R6), dtype=torch.float64, device=dev)
+    Yr = torch.empty_like(Y64)
+    row = {}
+    for form, Xp, Bp in (("fp64", X, U[1:]), ("fp32", X32, U32[1:]), ("bf16", X16, U32[1:])):
+        Y = Y64 if form == "fp64" else Yr
+        if tune:
+            dn.ttmc(tspec, Xp, Bp, precision=form, out=Y, tune_reps=3)
+        t = event_median(torch, stream, lambda: dn.ttmc(tspec, Xp, Bp, precision=form, out=Y))
+        xb = {"fp64": 8, "fp32": 4, "bf16": 2}[form]
+        byts = nx * xb + 4 * 60 * R6 * (8 if form == "fp64" else 4) + 60 * R6 ** 4 * 8
+        e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
+             "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if form != "fp64":
+            torch.cuda.synchronize()
+            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
+            e["rel_err_vs_fp64"] = float((Y - Y64).norm() / Y64.norm())
+        row[form] = e
+    print(f"[bench] order-5 60^5 ttmc mode 0: {row}", file=sys.stderr, flush=True)
+    out["ttmc_order5"] = {"workload": "TTMc order 5 mode 0, X 60^5 FP64 (6.2 GB), ranks 24, N(0,1) factors",
+                          "forms": row}
+    del X, X32, X16, Y64, Yr
     torch.cuda.empty_cache()
     return out
 

@@ -26,7 +26,7 @@ struct TkArgs {
     int vec_ok;
     int xcd_remap;           // 1: the workgroups of one XCD take one contiguous range of units
     int64_t n_groups;        // grid size
-    double *P;               // stage2: [cgroup][slab][16*NTA][16*NTC]; else [slab][n_ctiles*16*MT][16*NTA]
+    double *P;               // stage2: [cgroup][slab][ra][rc]; else [slab][n_ctiles*16*MT][16*NTA]
 };
 
 deinsum_status ttmc_workspace_size(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,

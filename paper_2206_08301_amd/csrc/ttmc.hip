@@ -119,6 +119,25 @@ struct SlabWalk {
 };
 
 // Fused two-mode pass.  Per slab, the K loop over i_a runs in ring steps of
+// LDS of the fused kernel.  Stage-2 factor rows of the workgroup are held in LDS
+// when a four-wave workgroup's rows fit in 32 KB (they are the same for every
+// slab); per-wave Z tiles are summed after one barrier when four of them and those
+// rows stay within 40 KB, else accumulated wave by wave in one tile.  Sized at
+// launch for the workgroup's actual wave count (dynamic shared memory).
+template <int P, int NTA, int NTC, int MT, bool STAGE2>
+struct TkLds {
+    using CT = typename TkTypes<P>::CT;
+    static constexpr int TA = 16 * NTA, TC = 16 * NTC;
+    static constexpr size_t UC_BYTES = static_cast<size_t>(4 * 16 * MT) * TC * sizeof(CT);
+    static constexpr bool UC_LDS = STAGE2 && UC_BYTES <= 32768;
+    static constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) + (UC_LDS ? UC_BYTES : 0) <= 40960;
+    __host__ __device__ static size_t z_elems(int nwaves) { return STAGE2 ? static_cast<size_t>(Z_PAR ? nwaves : 1) * TA * TC : 0; }
+    __host__ __device__ static size_t bytes(int nwaves)
+    {
+        return z_elems(nwaves) * sizeof(double) + (UC_LDS ? static_cast<size_t>(nwaves) * 16 * MT * TC * sizeof(CT) : 0);
+    }
+};
+
 // UB K-steps (4*UB rows), prefetched NBUF-1 steps ahead; complete steps issue
 // a fixed sequence of unmasked loads (the factors are zero-padded to whole
 // column tiles), so the compiler waits for exactly the oldest step.
@@ -132,16 +151,11 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
     using DT = typename TkTypes<P>::DT;
     constexpr int KR = TkTypes<P>::KR, LR = TkTypes<P>::LR;
     constexpr int TA = 16 * NTA, TC = 16 * NTC;
-    // Stage-2 factor rows of the workgroup held in LDS when they fit in 32 KB (they
-    // are the same for every slab); per-wave Z tiles summed after one barrier when
-    // the workgroup's LDS stays within 40 KB (four workgroups per CU), else
-    // accumulated wave by wave in one tile.
-    constexpr int CROWS = 4 * 16 * MT;
-    constexpr size_t UC_BYTES = static_cast<size_t>(CROWS) * TC * sizeof(CT);
-    constexpr bool UC_LDS = STAGE2 && UC_BYTES <= 32768;
-    constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) + (UC_LDS ? UC_BYTES : 0) <= 40960;
-    __shared__ CT lds_uc[UC_LDS ? CROWS * TC : 1];
-    __shared__ double lds[STAGE2 ? (Z_PAR ? 4 * TA * TC : TA * TC) : 1];
+    using L = TkLds<P, NTA, NTC, MT, STAGE2>;
+    constexpr bool UC_LDS = L::UC_LDS, Z_PAR = L::Z_PAR;
+    extern __shared__ double tk_lds[];
+    double *lds = tk_lds;                                                     // Z tiles
+    CT *lds_uc = reinterpret_cast<CT *>(tk_lds + L::z_elems(a.nwaves));       // stage-2 factor rows
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -227,17 +241,34 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                             for (int i = 0; i < XWN; ++i) xb[slot][u][q][i] = XWT{};
                         }
                     } else {
+                        // Ragged tile: chunks wholly in range still take one vector load.
+                        constexpr int VW = V * static_cast<int>(sizeof(XT)) / static_cast<int>(sizeof(XWT));
                         auto elem = [&](int i) {
                             const int64_t e = (i / V) * 16 * V + i % V;
                             return (rv && ibase + e < a.Ic) ? xsrc[r * a.stride_a + e] : XT{};
                         };
 #pragma unroll
-                        for (int i = 0; i < XWN; ++i) {
-                            if constexpr (P == P_BF16)
-                                xb[slot][u][q][i] = static_cast<uint32_t>(elem(2 * i)) |
-                                                    (static_cast<uint32_t>(elem(2 * i + 1)) << 16);
-                            else
-                                xb[slot][u][q][i] = elem(i);
+                        for (int j = 0; j < NCH; ++j) {
+                            const int64_t e0 = static_cast<int64_t>(j) * 16 * V;
+                            bool done = false;
+                            if constexpr ((V * sizeof(XT)) % 8 == 0) {
+                                if (a.vec_ok && rv && ibase + e0 + V <= a.Ic) {
+                                    load_vec_n<XWT, VW, XNT>(xb[slot][u][q] + j * VW,
+                                                             reinterpret_cast<const XWT *>(xsrc + r * a.stride_a + e0));
+                                    done = true;
+                                }
+                            }
+                            if (!done) {
+#pragma unroll
+                                for (int k = 0; k < VW; ++k) {
+                                    if constexpr (P == P_BF16)
+                                        xb[slot][u][q][j * VW + k] =
+                                            static_cast<uint32_t>(elem(j * V + 2 * k)) |
+                                            (static_cast<uint32_t>(elem(j * V + 2 * k + 1)) << 16);
+                                    else
+                                        xb[slot][u][q][j * VW + k] = elem(j * V + k);
+                                }
+                            }
                         }
                     }
                 }
@@ -337,8 +368,10 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                             }
                         }
                     }
-                // Fixed-order reduction over the workgroup's c-tiles (wave order).
-                double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * (TA * TC);
+                // Fixed-order reduction over the workgroup's c-tiles (wave order); the
+                // partial tile is stored unpadded, r_a x r_c.
+                const int zn = a.ra * a.rc;
+                double *out = a.P + (static_cast<int64_t>(cgroup) * a.n_slabs + slab) * zn;
                 if constexpr (Z_PAR) {
 #pragma unroll
                     for (int tc = 0; tc < NTC; ++tc)
@@ -349,9 +382,10 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                                 lds[w * TA * TC + (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v)] =
                                     static_cast<double>(z[tc][ta][v]);
                     __syncthreads();
-                    for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) {
-                        double acc = lds[i];
-                        for (int ww = 1; ww < a.nwaves; ++ww) acc += lds[ww * TA * TC + i];
+                    for (int i = threadIdx.x; i < zn; i += 64 * a.nwaves) {
+                        const int j = (i / a.rc) * TC + i % a.rc;
+                        double acc = lds[j];
+                        for (int ww = 1; ww < a.nwaves; ++ww) acc += lds[ww * TA * TC + j];
                         out[i] = acc;
                     }
                 } else {
@@ -370,7 +404,7 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                         }
                         __syncthreads();
                     }
-                    for (int i = threadIdx.x; i < TA * TC; i += 64 * a.nwaves) out[i] = lds[i];
+                    for (int i = threadIdx.x; i < zn; i += 64 * a.nwaves) out[i] = lds[(i / a.rc) * TC + i % a.rc];
                 }
                 __syncthreads();
             } else {
@@ -575,7 +609,8 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
 template <int P, int NTA, int NTC, int MT, bool S2, int UB, int NB, bool XNT>
 void launch_tk(const TkArgs &a, int64_t grid, hipStream_t s)
 {
-    ttmc_fused_kernel<P, NTA, NTC, MT, S2, UB, NB, XNT><<<static_cast<unsigned>(grid), 64 * a.nwaves, 0, s>>>(a);
+    const size_t lds = TkLds<P, NTA, NTC, MT, S2>::bytes(a.nwaves);
+    ttmc_fused_kernel<P, NTA, NTC, MT, S2, UB, NB, XNT><<<static_cast<unsigned>(grid), 64 * a.nwaves, lds, s>>>(a);
 }
 
 using TkLaunch = void (*)(const TkArgs &, int64_t, hipStream_t);
@@ -599,7 +634,8 @@ const TkEntry kTkTable[] = {
     // alternatives (plan_hint 1, 2, ...)
     TK(P_FP64, 1, 1, 4, 3, 2), TKN(P_FP64, 1, 1, 4, 3, 2), TK(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 3, 2),
     TKN(P_FP64, 1, 2, 4, 3, 2), TK(P_FP64, 2, 1, 4, 3, 2), TKN(P_FP64, 2, 1, 4, 3, 2), TK(P_FP64, 2, 2, 4, 2, 3),
-    TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 1, 2, 2, 4),
+    TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 2, 1, 2, 4),
+    TK(P_FP64, 2, 2, 1, 4, 2), TK(P_FP64, 2, 1, 2, 2, 4),
     TK(P_FP64, 4, 1, 1, 2, 4), TK(P_FP64, 4, 2, 1, 2, 4),
     TKN(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
     TKN(P_FP32, 2, 2, 4, 4, 2), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
@@ -726,7 +762,7 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
     p.spg = std::max<int64_t>(1, (p.n_slabs * p.n_cgroups) / 4096);
     p.groups = p.n_cgroups * cdivl(p.n_slabs, p.spg);
     const int64_t TA = 16 * p.nta, TC = 16 * p.ntc;
-    if (p.stage2) p.p_bytes = static_cast<size_t>(p.n_cgroups * p.n_slabs * TA * TC) * 8;
+    if (p.stage2) p.p_bytes = static_cast<size_t>(p.n_cgroups * p.n_slabs * p.Rm[p.a] * p.Rm[p.c]) * 8;
     else p.p_bytes = static_cast<size_t>(p.n_slabs * p.n_ctiles * 16 * p.mt * TA) * 8;
     // Intermediate after the fused pass, then ping-pong buffers for the remaining products.
     int64_t zel = p.n_slabs * p.Rm[p.a] * (p.stage2 ? p.Rm[p.c] : p.I[n]);
@@ -902,11 +938,11 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     for (int k = 0; k < r.nd; ++k) r.sdim[k] = p.I[p.slab_modes[k]];
     if (p.stage2) {
         r.parts = p.n_cgroups;
-        r.part_stride = p.n_slabs * TA * TC;
+        r.part_stride = p.n_slabs * p.Rm[p.a] * p.Rm[p.c];
         r.X1 = p.Rm[p.a];
-        r.PX = TA;
+        r.PX = p.Rm[p.a];  // stage-2 tiles are stored unpadded
         r.Y1 = p.Rm[p.c];
-        r.PY = TC;
+        r.PY = p.Rm[p.c];
     } else {
         r.parts = 1;
         r.part_stride = 0;

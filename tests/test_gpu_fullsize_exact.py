@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import SPEC3, flush, to_dev, ttmc_spec
+from gpu_common import SPEC3, flush, mttkrp_spec, to_dev, ttmc_spec
 
 pytestmark = pytest.mark.gpu
 
@@ -78,4 +78,39 @@ def test_ttmc_full_size_integer_exact(dn, synth, oracle_mod, dims, rank):
             ref = oracle_mod.ttmc(synth.x_slab(seed, dims, 0, i, dist="int3"), U, 0)[0]
             assert np.array_equal(Y[i].cpu().numpy(), ref), (prec, i)
     del X, X32
+    torch.cuda.empty_cache()
+
+
+def test_order5_60_last_mode_and_ttmc(dn, synth, oracle_mod):
+    """The paper's order-5 forms at I = 60, R = 24: MTTKRP in the last mode (FP64, sampled
+    rows against the oracle) and TTMc in mode 0 (FP64 on integer inputs, sampled slabs
+    exact; FP32 and BF16 forms within their bounds against the FP64 result)."""
+    dims, R = (60,) * 5, 24
+    seed = synth.config_seed(3, 70)
+    X = torch.empty(dims, dtype=torch.float64, device="cuda")
+    dn.synth_fill(X, seed, dist="int3")
+    U = [synth.int_factor(seed + 1 + m, 60, R, -1, 1) for m in range(5)]
+    flush("60^5 MTTKRP mode 4")
+    M = dn.mttkrp(mttkrp_spec(5, 4), X, [to_dev(U[m]) for m in range(4)])
+    torch.cuda.synchronize()
+    for i in (0, 37, 59):
+        ref = oracle_mod.mttkrp(synth.x_slab(seed, dims, 4, i, dist="int3"), [U[0], U[1], U[2], U[3], None], 4)[0]
+        assert np.array_equal(M[i].cpu().numpy(), ref), i
+    flush("60^5 TTMc mode 0")
+    Y = dn.ttmc(ttmc_spec(5, 0), X, [to_dev(U[m]) for m in range(1, 5)])
+    torch.cuda.synchronize()
+    for i in (1, 42):
+        ref = oracle_mod.ttmc(synth.x_slab(seed, dims, 0, i, dist="int3"), [None] + U[1:], 0)[0]
+        assert np.array_equal(Y[i].cpu().numpy(), ref), i
+    X32 = torch.empty(dims, dtype=torch.float32, device="cuda")
+    dn.convert(X, X32)
+    X16 = torch.empty(dims, dtype=torch.bfloat16, device="cuda")
+    dn.convert(X, X16)
+    for prec, Xp in (("fp32", X32), ("bf16", X16)):
+        flush(f"60^5 TTMc mode 0 {prec}")
+        Yp = dn.ttmc(ttmc_spec(5, 0), Xp, [to_dev(U[m], torch.float32) for m in range(1, 5)], precision=prec,
+                     out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert torch.equal(Yp, Y), prec  # integer inputs: exact in every form
+    del X, X32, X16, Y
     torch.cuda.empty_cache()
