@@ -185,7 +185,7 @@ __device__ __forceinline__ void load_tile(typename Tile<P, L, NI, MT>::XT *x,
 #pragma unroll
                     for (int i = 0; i < MT; ++i) dst[i] = src[i];
                 } else {
-                    load_contig<XT, MT>(dst, src, false, r < lim ? ivalid : 0);
+                    load_contig<XT, MT>(dst, src, a.vec_ok != 0, r < lim ? ivalid : 0);  // whole runs: one load
                 }
             }
     }
