@@ -241,9 +241,10 @@ deinsum_status deinsum_convert(const void *src, int32_t src_dtype, void *dst, in
  * Batched launch (many MTTKRP jobs of uneven shape and rank, e.g. the
  * per-mode products of CP-ALS sweeps over many tensors).  Jobs added to a
  * batch run in ONE persistent kernel inside a hipGraph that is captured once
- * and replayed at every launch: descriptor upload -> outer-weight tables ->
- * persistent kernel (workgroups pull units of all jobs from one device work
- * queue) -> fixed-order reduction of every job.  A job's result depends only
+ * and replayed at every launch, after an asynchronous upload of the launched
+ * jobs' descriptors: outer-weight tables -> persistent kernel (workgroups pull
+ * units of all jobs from one device work queue) -> fixed-order reduction of
+ * every job.  A job's result depends only
  * on its own shape and plan, so it is bitwise identical whether it runs alone
  * or with other jobs.  FP64 and FP32 forms, ranks 1..64.
  *

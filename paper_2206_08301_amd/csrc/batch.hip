@@ -1,8 +1,9 @@
 // batch.hip -- many MTTKRP jobs of uneven shape and rank in one persistent launch.
 //
-// An epoch is one replay of a captured hipGraph:
-//   descriptor copy (pinned host -> device)
-//   -> queue reset (a kernel; no memset node)
+// An epoch is an asynchronous copy of the jobs' descriptors (pinned host ->
+// device, only the jobs of this launch) followed by one replay of a captured
+// hipGraph:
+//   queue reset (a kernel; no memset node)
 //   -> batched outer-weight table of every job
 //   -> ONE persistent kernel: each workgroup takes the next unit of the global
 //      work queue (a vector atomic counter), finds its job by binary search over
@@ -241,7 +242,6 @@ deinsum_status capture_graph(deinsum_batch *b)
     const BatchJob *jobs = reinterpret_cast<const BatchJob *>(b->d_desc + sizeof(BatchHeader));
     if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(DEINSUM_ERR_DEVICE, "batch: stream capture failed to begin");
-    (void)hipMemcpyAsync(b->d_desc, b->pinned, desc_bytes(b->capacity), hipMemcpyHostToDevice, b->cap_stream);
     batch_reset_kernel<<<1, 1, 0, b->cap_stream>>>(b->d_queue);
     batch_weights_kernel<<<kAuxGrid, 256, 0, b->cap_stream>>>(h, jobs);
     batch_main_kernel<<<b->persistent_groups, 256, 0, b->cap_stream>>>(h, jobs, b->d_queue);
@@ -571,6 +571,12 @@ deinsum_status deinsum_batch_launch(deinsum_batch *b, void *stream)
     }
     if (!b->exec)
         if (deinsum_status st = capture_graph(b)) return st;
+    // Descriptors of this launch's jobs only (the graph reads h->njobs of them).
+    if (hipMemcpyAsync(b->d_desc, b->pinned, desc_bytes(static_cast<int>(b->jobs.size())), hipMemcpyHostToDevice, s) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DEINSUM_ERR_DEVICE, "batch_launch: descriptor upload failed");
+    }
     if (hipGraphLaunch(b->exec, s) != hipSuccess) {
         (void)hipGetLastError();
         return fail(DEINSUM_ERR_DEVICE, "batch_launch: graph launch failed");

@@ -193,9 +193,17 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
         return false;
     }
     if (s->cfg.als_update) {
-        (void)hipMemcpyAsync(s->als_dev[e], s->als_pinned[e], sizeof(AlsJob) * ep.reqs.size(), hipMemcpyHostToDevice,
-                             s->stream[e]);
-        if (launch_als_batch(s->als_dev[e], static_cast<int>(ep.reqs.size()), als_total, s->stream[e]) != DEINSUM_OK) {
+        // One request: its update job goes as a kernel argument (the same kernels, no
+        // descriptor copy); several: one table upload and one batched launch.
+        deinsum_status st;
+        if (ep.reqs.size() == 1) {
+            st = launch_als_one(s->als_pinned[e][0], s->stream[e]);
+        } else {
+            (void)hipMemcpyAsync(s->als_dev[e], s->als_pinned[e], sizeof(AlsJob) * ep.reqs.size(),
+                                 hipMemcpyHostToDevice, s->stream[e]);
+            st = launch_als_batch(s->als_dev[e], static_cast<int>(ep.reqs.size()), als_total, s->stream[e]);
+        }
+        if (st != DEINSUM_OK) {
             set_failed(s, std::string("serve: ") + deinsum_last_error());
             return false;
         }
