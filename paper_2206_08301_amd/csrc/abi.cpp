@@ -589,19 +589,30 @@ deinsum_status deinsum_tune_ttmc(const deinsum_spec *spec, const int64_t *dims, 
     double best_us = -1;
     int best_v = 0;
     const int nvar = (spec->order == 2 && spec->free_mode == 0) ? 1 : 64;  // that case runs the MTTKRP kernel
+    int count = 0;
     for (int v = 0; v < nvar; ++v) {
         o.plan_hint = v + 1;
         size_t need = 0;
         if (deinsum_workspace_size(spec, dims, ranks, &o, &need) != DEINSUM_OK) break;  // no variant v
-        double us = 0;
-        if (deinsum_status st = time_median([&] { return deinsum_ttmc(spec, dims, ranks, X, U, Y, &o, stream); },
-                                            reps, s, &us))
-            return st;
-        if (best_us < 0 || us < best_us) {
-            best_us = us;
+        count = v + 1;
+    }
+    // Two interleaved passes over the variants, each variant keeping its faster median,
+    // so that clock or thermal drift during the sweep does not favour one position.
+    std::vector<double> us_of(static_cast<size_t>(count), -1.0);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int v = 0; v < count; ++v) {
+            o.plan_hint = v + 1;
+            double us = 0;
+            if (deinsum_status st = time_median([&] { return deinsum_ttmc(spec, dims, ranks, X, U, Y, &o, stream); },
+                                                reps, s, &us))
+                return st;
+            if (us_of[v] < 0 || us < us_of[v]) us_of[v] = us;
+        }
+    for (int v = 0; v < count; ++v)
+        if (best_us < 0 || us_of[v] < best_us) {
+            best_us = us_of[v];
             best_v = v;
         }
-    }
     TuneChoice c;
     c.nt = c.ni = c.mt = 1;
     c.split = best_v;  // TTMc entries: the fused-kernel variant
