@@ -60,7 +60,7 @@ typedef enum deinsum_status {
     DEINSUM_ERR_BUSY = -7         /* resource temporarily unavailable     */
 } deinsum_status;
 
-typedef enum deinsum_kind { DEINSUM_MTTKRP = 1, DEINSUM_TTMC = 2 } deinsum_kind;
+typedef enum deinsum_kind { DEINSUM_MTTKRP = 1, DEINSUM_TTMC = 2, DEINSUM_MTTKRP_MM = 3 } deinsum_kind;
 
 typedef enum deinsum_dtype { DEINSUM_F64 = 0, DEINSUM_F32 = 1, DEINSUM_BF16 = 2 } deinsum_dtype;
 
@@ -159,7 +159,8 @@ deinsum_status deinsum_parse(const char *spec, deinsum_spec *out);
 
 /*
  * Workspace (device bytes) a call with these arguments needs.  ranks: for
- * MTTKRP ranks[0] = R; for TTMc one rank per factor operand (operand order).
+ * MTTKRP ranks[0] = R; for TTMc one rank per factor operand (operand order);
+ * for the MTTKRP-GEMM chain ranks[0] = R, ranks[1] = L.
  */
 deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *dims,
                                       const int64_t *ranks, const deinsum_opts *opts,
@@ -176,6 +177,24 @@ deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *d
  * M     : device I_n x R output, dtype opts->out_dtype.
  * opts  : NULL for defaults.
  */
+/*
+ * The MTTKRP-GEMM chain of the paper's running example (Sec. II-A), e.g.
+ * "ijk,ja,ka,al->il": the MTTKRP operands followed by one more operand
+ * "<rank letter><l>", output "<free letter><l>":
+ *   Y[i_n, l] = sum_r M[i_n, r] * C[r, l],  M the mode-n MTTKRP above.
+ * spec : parsed DEINSUM_MTTKRP_MM spec (factor_mode, free_mode as for MTTKRP).
+ * R, L : rank (1..256) and the chain's output width (1..4096).
+ * X, U : as for deinsum_mttkrp (U: the N-1 factor operands in operand order).
+ * C    : device R x L matrix, row-major, f64 for FP64 and f32 otherwise.
+ * Y    : device I_n x L output, dtype opts->out_dtype; must not overlap the inputs.
+ * M is formed in FP64 in the workspace (deinsum_workspace_size with ranks
+ * {R, L}) and the product is summed in FP64 in increasing r.  Errors as for
+ * deinsum_mttkrp; asynchronous on `stream`.
+ */
+deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, int64_t R, int64_t L,
+                                 const void *X, const void *const *U, const void *C, void *Y,
+                                 const deinsum_opts *opts, void *stream);
+
 deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R,
                               const void *X, const void *const *U, void *M,
                               const deinsum_opts *opts, void *stream);

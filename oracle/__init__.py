@@ -11,6 +11,9 @@ The arithmetic lives in ``oracle.c`` (plain loops, FP64, no FMA contraction):
   * ``ttm``     -- one mode product (Sec. III-B);
   * ``ttmc``    -- the TTM chain over all modes but one (Sec. III-B).
 This module only marshals numpy arrays to that library, except for
+  * ``mttkrp_mm`` -- the MTTKRP followed by a matrix product, the chain of the
+    paper's running example (Sec. II-A, ``ijk,ja,ka,al->il``): ``mttkrp``
+    then one numpy matrix product, in that order;
   * ``als_update`` -- one CP-ALS factor update built on ``mttkrp`` (numpy).
     The paper names MTTKRP as the main kernel of the CP decomposition (Sec. I)
     but does not state the update; this is the textbook alternating
@@ -140,6 +143,15 @@ def ttmc(X, U, n):
     if rc:
         raise RuntimeError(f"oracle_ttmc failed with {rc}")
     return Y
+
+
+def mttkrp_mm(X, U, n, C):
+    """Y[i_n, l] = sum_r M[i_n, r] C[r, l] with M = mttkrp(X, U, n) (Sec. II-A chain)."""
+    C = _f64(C)
+    M = mttkrp(X, U, n)
+    if C.ndim != 2 or C.shape[0] != M.shape[1]:
+        raise ValueError("C must be R x L")
+    return M @ C
 
 
 def als_update(X, U, n):

@@ -22,6 +22,7 @@ from ._lib import DeinsumError, Report, Spec  # noqa: F401
 
 MTTKRP = 1
 TTMC = 2
+MTTKRP_MM = 3
 F64, F32, BF16 = 0, 1, 2
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fx20": 4}
 _X_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16, "bf16x3": torch.float32,
@@ -275,11 +276,56 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
     return out
 
 
+def mttkrp_mm(spec, X, U, C, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None):
+    """MTTKRP followed by a matrix product, e.g. "ijk,ja,ka,al->il" (the paper's running
+    example): ``U`` lists the MTTKRP factor operands, ``C`` is the R x L matrix."""
+    sp = _spec(spec)
+    if sp.kind != MTTKRP_MM:
+        raise ValueError("spec is not an MTTKRP-GEMM chain")
+    if precision == "fx20":
+        if not isinstance(X, FX20):
+            raise TypeError("the fx20 form takes X from to_fx20()")
+    else:
+        _check_tensor(X, _X_DTYPE[precision], "X")
+    if X.dim() != sp.order or len(U) != sp.n_factors:
+        raise ValueError("operand count or order does not match the spec")
+    R = None
+    for k, u in enumerate(U):
+        _check_tensor(u, _U_DTYPE[precision], f"U[{k}]")
+        m = sp.factor_mode[k]
+        if u.dim() != 2 or u.shape[0] != X.shape[m] or (R is not None and u.shape[1] != R):
+            raise ValueError(f"factor {k} must be {X.shape[m]} x R with one shared R")
+        R = u.shape[1]
+    _check_tensor(C, _U_DTYPE[precision], "C")
+    if C.dim() != 2 or C.shape[0] != R:
+        raise ValueError("C must be R x L")
+    L = C.shape[1]
+    out_dtype = out_dtype or (out.dtype if out is not None else _default_out_dtype(precision))
+    n = sp.free_mode
+    if out is None:
+        out = torch.empty((X.shape[n], L), dtype=out_dtype, device=X.device)
+    else:
+        _check_tensor(out, out_dtype, "out")
+        if tuple(out.shape) != (X.shape[n], L):
+            raise ValueError("out has the wrong shape")
+    ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+    o = _opts(precision, out_dtype, workspace, 0, 0, report)
+    xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
+    with torch.cuda.device(X.device):
+        _lib.check(_lib.load().deinsum_mttkrp_mm(ctypes.byref(sp), _i64(X.shape), int(R), int(L),
+                                                 ctypes.c_void_p(xptr), ptrs, ctypes.c_void_p(C.data_ptr()),
+                                                 ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), _stream(stream)))
+    return out
+
+
 def einsum(spec: str, X, *U, precision="fp64", out=None, **kw):
-    """Dispatch an MTTKRP or TTMc einsum string (Tab. IV forms) to the library."""
+    """Dispatch an MTTKRP, TTMc or MTTKRP-GEMM einsum string (Tab. IV forms and the
+    chain of Sec. II-A) to the library."""
     sp = parse(spec)
     if sp.kind == MTTKRP:
         return mttkrp(sp, X, list(U), precision=precision, out=out, **kw)
+    if sp.kind == MTTKRP_MM:
+        return mttkrp_mm(sp, X, list(U[:-1]), U[-1], precision=precision, out=out, **kw)
     return ttmc(sp, X, list(U), precision=precision, out=out, **kw)
 
 

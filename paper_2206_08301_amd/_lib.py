@@ -90,7 +90,7 @@ EXPORTS = (
     "deinsum_server_submit", "deinsum_server_replay", "deinsum_server_drain", "deinsum_server_results",
     "deinsum_server_stats", "deinsum_server_destroy", "deinsum_tune_mttkrp", "deinsum_tune_batch_mttkrp",
     "deinsum_tune_load", "deinsum_tune_save", "deinsum_tune_clear", "deinsum_tune_entries",
-    "deinsum_fx20_size", "deinsum_fx20_encode", "deinsum_tune_ttmc",
+    "deinsum_fx20_size", "deinsum_fx20_encode", "deinsum_tune_ttmc", "deinsum_mttkrp_mm",
 )
 
 _lib = None
@@ -120,6 +120,9 @@ def load():
     lib.deinsum_ttmc.argtypes = [ctypes.POINTER(Spec), i64p, i64p, vp, ctypes.POINTER(vp), vp,
                                  ctypes.POINTER(Opts), vp]
     lib.deinsum_ttmc.restype = ctypes.c_int
+    lib.deinsum_mttkrp_mm.argtypes = [ctypes.POINTER(Spec), i64p, ctypes.c_int64, ctypes.c_int64, vp,
+                                      ctypes.POINTER(vp), vp, vp, ctypes.POINTER(Opts), vp]
+    lib.deinsum_mttkrp_mm.restype = ctypes.c_int
     lib.deinsum_last_error.argtypes = []
     lib.deinsum_last_error.restype = ctypes.c_char_p
     lib.deinsum_synth_fill.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,

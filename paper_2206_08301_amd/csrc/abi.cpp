@@ -405,6 +405,15 @@ deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *d
     deinsum_opts o;
     if (deinsum_status st = resolve_opts(opts, &o)) return st;
     if (spec && spec->kind == DEINSUM_TTMC) return ttmc_workspace_size(spec, dims, ranks, o, bytes);
+    if (spec && spec->kind == DEINSUM_MTTKRP_MM) {  // the MTTKRP's, then M in FP64
+        deinsum_spec ms = *spec;
+        ms.kind = DEINSUM_MTTKRP;
+        MttkrpCall c{};
+        if (deinsum_status st = prepare_mttkrp(&ms, dims, ranks[0], o, &c)) return st;
+        *bytes = (call_workspace(c) + 255) / 256 * 256 + static_cast<size_t>(dims[spec->free_mode] * ranks[0]) * 8;
+        clear_error();
+        return DEINSUM_OK;
+    }
     MttkrpCall c{};
     if (deinsum_status st = prepare_mttkrp(spec, dims, ranks[0], o, &c)) return st;
     *bytes = call_workspace(c);
@@ -466,6 +475,51 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     }
     fill_report(o.report, c.orig, c.plan, call_workspace(c), c.merged, c.via_ttmc ? c.ttmc_variant : -1);
     if (deinsum_status st = run_mttkrp(c, ws, s)) return st;
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, int64_t R, int64_t L,
+                                 const void *X, const void *const *U, const void *C, void *Y,
+                                 const deinsum_opts *opts, void *stream)
+{
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (deinsum_status st = check_dims(spec, dims)) return st;
+    if (spec->kind != DEINSUM_MTTKRP_MM) return fail(DEINSUM_ERR_INVALID_ARG, "spec is not an MTTKRP-GEMM chain");
+    if (R < 1 || R > DEINSUM_MAX_RANK)
+        return fail(DEINSUM_ERR_SHAPE, "rank must be 1.." + std::to_string(DEINSUM_MAX_RANK));
+    if (L < 1 || L > 4096) return fail(DEINSUM_ERR_SHAPE, "chain width L must be 1..4096");
+    if (!C || !Y) return fail(DEINSUM_ERR_INVALID_ARG, "null C or Y");
+    const int n = spec->free_mode;
+    const size_t cb = u_elem_bytes(o.precision), yb = dtype_bytes(o.out_dtype);
+    const size_t ybytes = static_cast<size_t>(dims[n] * L) * yb;
+    if (overlaps(Y, ybytes, C, static_cast<size_t>(R * L) * cb)) return fail(DEINSUM_ERR_INVALID_ARG, "Y overlaps C");
+    deinsum_spec ms = *spec;
+    ms.kind = DEINSUM_MTTKRP;
+    const int64_t ranks[2] = {R, L};
+    size_t total = 0;
+    if (deinsum_status st = deinsum_workspace_size(spec, dims, ranks, &o, &total)) return st;
+    const size_t mbytes = static_cast<size_t>(dims[n] * R) * 8;
+    const size_t mws = total - mbytes;  // the MTTKRP's workspace, 256-aligned
+    void *ws = o.workspace;
+    if (ws) {
+        if (o.workspace_bytes < total)
+            return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(total) + " bytes");
+    } else if (deinsum_status st = pool_get(total, &ws)) {
+        return st;
+    }
+    double *M = reinterpret_cast<double *>(static_cast<char *>(ws) + mws);
+    if (overlaps(Y, ybytes, M, mbytes)) return fail(DEINSUM_ERR_INVALID_ARG, "Y overlaps the workspace");
+    deinsum_opts o2 = o;
+    o2.out_dtype = DEINSUM_F64;
+    o2.workspace = ws;
+    o2.workspace_bytes = mws;
+    o2.report = o.report;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (deinsum_status st = deinsum_mttkrp(&ms, dims, R, X, U, M, &o2, stream)) return st;
+    if (dims[n] == 0) return DEINSUM_OK;
+    if (deinsum_status st = launch_chain_mm(M, C, static_cast<int>(cb), dims[n], R, L, Y, o.out_dtype, s)) return st;
     clear_error();
     return DEINSUM_OK;
 }

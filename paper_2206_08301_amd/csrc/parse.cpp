@@ -6,6 +6,8 @@
 // library accepts the two families the hot path implements:
 //   MTTKRP  "<X>,<m1 r>,...,<m_{N-1} r>-><n r>"          (one shared rank letter)
 //   TTMc    "<X>,<m1 r1>,...,<m_{N-1} r_{N-1}>-><X with each m_k -> r_k>"
+//   MTTKRP followed by a matrix product (the paper's running example, Sec. II-A)
+//           "<X>,<m1 r>,...,<m_{N-1} r>,<r l>-><n l>"
 #include <cctype>
 #include <cstring>
 #include <string>
@@ -71,9 +73,11 @@ deinsum_status parse_spec(const char *text, deinsum_spec *out)
     if (N < 2 || N > DEINSUM_MAX_ORDER)
         return fail(DEINSUM_ERR_UNSUPPORTED, "parse: tensor order must be 2.." +
                                                  std::to_string(DEINSUM_MAX_ORDER));
-    if (static_cast<int>(ops.size()) != N)
+    // One operand beyond the N-1 factors: the matrix of an MTTKRP-GEMM chain.
+    const bool chain = static_cast<int>(ops.size()) == N + 1;
+    if (static_cast<int>(ops.size()) != N && !chain)
         return fail(DEINSUM_ERR_UNSUPPORTED,
-                    "parse: an order-N tensor needs exactly N-1 factor operands");
+                    "parse: an order-N tensor needs exactly N-1 factor operands (plus one matrix for a chain)");
 
     deinsum_spec sp;
     std::memset(&sp, 0, sizeof(sp));
@@ -131,7 +135,17 @@ deinsum_status parse_spec(const char *text, deinsum_spec *out)
     for (int m = 0; m < N; ++m)
         if (m != free_mode) ttmc_out[m] = rank_of_mode[m];
 
-    if (shared && rhs == mttkrp_out) {
+    if (chain) {
+        const std::string &c = ops[N];
+        const char r = rank_of_mode[first_contracted];
+        if (!shared || c.size() != 2 || c[0] != r || X.find(c[1]) != std::string::npos || c[1] == r)
+            return fail(DEINSUM_ERR_UNSUPPORTED, "parse: a chain is an MTTKRP (one shared rank letter) followed by "
+                                                 "'<rank letter><new letter>'");
+        const std::string chain_out = std::string(1, X[free_mode]) + c[1];
+        if (rhs != chain_out)
+            return fail(DEINSUM_ERR_UNSUPPORTED, "parse: output '" + rhs + "' is not '" + chain_out + "' (MTTKRP-GEMM)");
+        sp.kind = DEINSUM_MTTKRP_MM;
+    } else if (shared && rhs == mttkrp_out) {
         sp.kind = DEINSUM_MTTKRP;
     } else if (distinct && rhs == ttmc_out) {
         sp.kind = DEINSUM_TTMC;

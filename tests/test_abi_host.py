@@ -65,6 +65,14 @@ def test_parse_ttmc_other_modes(dn):
     assert s.kind == 1  # order 2: the MTTKRP and TTMc outputs coincide
 
 
+def test_parse_mttkrp_gemm_chain(dn):
+    """The MTTKRP followed by a matrix product (the paper's running example)."""
+    s = dn.parse("ijk,ja,ka,al->il")
+    assert s.kind == 3 and s.order == 3 and s.free_mode == 0 and s.n_factors == 2
+    s = dn.parse(" ijkl , ia , ka , la , ab -> jb ")
+    assert s.kind == 3 and s.free_mode == 1 and list(s.factor_mode[:3]) == [0, 2, 3]
+
+
 @pytest.mark.parametrize("bad,status", [
     ("ijk,ja,ka", -2),            # implicit output
     ("...k,ka->...a", -2),        # ellipsis
@@ -81,6 +89,11 @@ def test_parse_ttmc_other_modes(dn):
     ("i,ia->a", -3),              # order 1
     ("abcdefghi,ba,cz,dz,ez,fz,gz,hz,iz->az", -3),  # order 9
     ("ijk,jaa,ka->ia", -2),
+    ("ijk,ja,ka,bl->il", -3),     # chain matrix not indexed by the rank letter
+    ("ijk,ja,ka,aj->ij", -3),     # chain letter taken from X
+    ("ijk,ja,ka,al->li", -3),     # chain output permuted
+    ("ijk,jb,kc,bl->il", -3),     # chain after TTMc-style factors
+    ("ijk,ja,ka,aa->ia", -2),     # repeated letter in the chain matrix
 ])
 def test_parse_rejects(dn, bad, status):
     with pytest.raises(dn.DeinsumError) as e:

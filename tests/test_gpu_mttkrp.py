@@ -261,3 +261,53 @@ def test_mode0_through_fused_ttmc_pass(dn, oracle_mod, tmp_path, dims, R):
     plain = dn.mttkrp(SPEC3[0], Xd, ops, plan_hint=1)
     torch.cuda.synchronize()
     assert nrel(plain.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,R,L", [((33, 70, 130), 24, 16), ((9, 11, 13, 17), 5, 3), ((64, 64, 64), 16, 40)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 1e-5), ("fx20", 4e-6)])
+def test_mttkrp_gemm_chain(dn, oracle_mod, dims, R, L, precision, tol):
+    """The MTTKRP-GEMM chain of the paper's running example through the C ABI, every mode."""
+    N = len(dims)
+    rng = np.random.default_rng(sum(dims) + R + L)
+    X = rng.uniform(-1, 1, dims)
+    if precision == "fp64":
+        Xd, udt = to_dev(X), torch.float64
+    elif precision == "fx20":
+        Xd, udt = dn.to_fx20(to_dev(X)), torch.float32
+    else:
+        X = X.astype(np.float32).astype(np.float64)
+        Xd, udt = to_dev(X, torch.float32), torch.float32
+    letters = "ijklmnop"[:N]
+    for n in range(N):
+        U = factors_for(rng, dims, R, n)
+        if udt == torch.float32:
+            U = [None if u is None else u.astype(np.float32).astype(np.float64) for u in U]
+        C = rng.standard_normal((R, L))
+        if udt == torch.float32:
+            C = C.astype(np.float32).astype(np.float64)
+        spec = letters + "," + ",".join(letters[m] + "z" for m in range(N) if m != n) + ",zy->" + letters[n] + "y"
+        got = dn.einsum(spec, Xd, *[to_dev(u, udt) for u in operands(U, n)], to_dev(C, udt), precision=precision,
+                        out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        ref = oracle_mod.mttkrp_mm(X, U, n, C)
+        err = nrel(got.cpu().numpy(), ref)
+        flush(f"chain {precision} dims={dims} n={n}: {err:.2e}")
+        assert got.shape == (dims[n], L)
+        assert err <= tol, (precision, dims, n)
+
+
+def test_mttkrp_gemm_chain_1024cubed(dn, synth, oracle_mod):
+    """"ijk,ja,ka,al->il" at the one-GPU tile shape (R=24, L=16), sampled rows."""
+    dims, R, L = (1024, 1024, 1024), 24, 16
+    seed = synth.config_seed(2, 80)
+    X = torch.empty(dims, dtype=torch.float64, device="cuda")
+    dn.synth_fill(X, seed)
+    U = [synth.normal_factor(seed + 1 + m, 1024, R) for m in range(3)]
+    C = np.random.default_rng(seed).standard_normal((R, L))
+    Y = dn.einsum("ijk,ja,ka,al->il", X, to_dev(U[1]), to_dev(U[2]), to_dev(C))
+    torch.cuda.synchronize()
+    for i in (0, 777):
+        ref = oracle_mod.mttkrp_mm(synth.x_slab(seed, dims, 0, i), [None, U[1], U[2]], 0, C)[0]
+        assert nrel(Y[i].cpu().numpy(), ref) <= 1e-12, i
+    del X
+    torch.cuda.empty_cache()

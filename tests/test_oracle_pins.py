@@ -91,6 +91,29 @@ def test_mttkrp_brute_force(oracle_mod, dims, R):
         assert nrel(oracle_mod.mttkrp(X, U, n), brute_mttkrp(X, U, n)) <= 1e-14
 
 
+@pytest.mark.parametrize("dims", [(3, 4, 5), (2, 3, 2, 3)])
+def test_mttkrp_gemm_chain_brute_force(oracle_mod, dims):
+    """Y[i_n, l] = sum over every other index and the rank of X * prod U * C[r, l], by loops;
+    an identity C returns the MTTKRP itself."""
+    rng = np.random.default_rng(21 + len(dims))
+    X = rng.uniform(-1, 1, dims)
+    R, L = 3, 2
+    for n in range(len(dims)):
+        U = factors(rng, dims, R, n)
+        C = rng.standard_normal((R, L))
+        Y = np.zeros((dims[n], L))
+        for idx in np.ndindex(*dims):
+            for r in range(R):
+                p = X[idx]
+                for m in range(len(dims)):
+                    if m != n:
+                        p *= U[m][idx[m], r]
+                for l in range(L):
+                    Y[idx[n], l] += p * C[r, l]
+        assert nrel(oracle_mod.mttkrp_mm(X, U, n, C), Y) <= 1e-14
+        assert np.array_equal(oracle_mod.mttkrp_mm(X, U, n, np.eye(R)), oracle_mod.mttkrp(X, U, n))
+
+
 @pytest.mark.parametrize("dims", [(3, 4), (3, 4, 5), (2, 3, 2, 3)])
 def test_ttmc_brute_force(oracle_mod, dims):
     rng = np.random.default_rng(5 + len(dims))
