@@ -171,12 +171,17 @@ deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *d
  *   M[i_n, r] = sum_{i_m, m != n} X[i_0..i_{N-1}] * prod_{m != n} U^{m}[i_m, r]
  * spec  : parsed MTTKRP spec; dims: N host sizes of X in its letter order.
  * R     : rank, 1 <= R <= 256.
- * X     : device tensor, dtype by precision (FP64: f64; FP32, BF16X3: f32; BF16: bf16).
+ * X     : device tensor, dtype by precision (FP64: f64; FP32, BF16X3: f32; BF16: bf16;
+ *         FX20: the buffer written by deinsum_fx20_encode, 256-byte aligned).
  * U     : host array of N-1 device pointers in OPERAND order (operand k is
  *         I_{factor_mode[k]} x R; f64 for FP64, f32 otherwise).
  * M     : device I_n x R output, dtype opts->out_dtype.
  * opts  : NULL for defaults.
  */
+deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R,
+                              const void *X, const void *const *U, void *M,
+                              const deinsum_opts *opts, void *stream);
+
 /*
  * The MTTKRP-GEMM chain of the paper's running example (Sec. II-A), e.g.
  * "ijk,ja,ka,al->il": the MTTKRP operands followed by one more operand
@@ -195,15 +200,13 @@ deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, 
                                  const void *X, const void *const *U, const void *C, void *Y,
                                  const deinsum_opts *opts, void *stream);
 
-deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int64_t R,
-                              const void *X, const void *const *U, void *M,
-                              const deinsum_opts *opts, void *stream);
-
 /*
  * Mode-n TTMc (Sec. III-B, Tab. IV): the chain X x_m U^{m} over every m != n,
  * each product contracting the factor's first index (I_m x R_m):
  *   Y[r_0..i_n..r_{N-1}] = sum_{i_m, m != n} X[i] * prod_{m != n} U^{m}[i_m, r_m]
- * ranks : host array of N-1 ranks in operand order, each 1..256.
+ * ranks : host array of N-1 ranks in operand order, each 1..64.
+ * Forms: FP64 (X, U f64), FP32 (X, U f32) and BF16 (X bf16, U f32; BF16 matrix
+ * cores for the first contraction, FP32 for the second, FP64 sums beyond).
  * Other arguments as for deinsum_mttkrp.
  */
 deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
