@@ -634,8 +634,8 @@ const TkEntry kTkTable[] = {
     // alternatives (plan_hint 1, 2, ...)
     TK(P_FP64, 1, 1, 4, 3, 2), TKN(P_FP64, 1, 1, 4, 3, 2), TK(P_FP64, 1, 1, 4, 2, 4), TK(P_FP64, 1, 2, 4, 3, 2),
     TKN(P_FP64, 1, 2, 4, 3, 2), TK(P_FP64, 2, 1, 4, 3, 2), TKN(P_FP64, 2, 1, 4, 3, 2), TK(P_FP64, 2, 2, 4, 2, 3),
-    TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TK(P_FP64, 2, 2, 1, 2, 4),
-    TK(P_FP64, 2, 2, 1, 4, 2), TK(P_FP64, 2, 1, 2, 2, 4),
+    TK(P_FP64, 2, 2, 4, 3, 2), TKN(P_FP64, 2, 2, 4, 3, 2), TK(P_FP64, 2, 2, 2, 2, 4), TKN(P_FP64, 2, 2, 4, 2, 2),
+    TK(P_FP64, 2, 1, 2, 2, 4),
     TK(P_FP64, 4, 1, 1, 2, 4), TK(P_FP64, 4, 2, 1, 2, 4),
     TKN(P_FP32, 1, 1, 4, 2, 4), TK(P_FP32, 1, 2, 4, 2, 4), TK(P_FP32, 1, 4, 4, 2, 4), TK(P_FP32, 2, 1, 4, 2, 4),
     TKN(P_FP32, 2, 2, 4, 4, 2), TK(P_FP32, 2, 4, 4, 2, 4), TK(P_FP32, 4, 1, 2, 2, 4), TK(P_FP32, 4, 2, 2, 2, 4),
