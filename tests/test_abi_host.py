@@ -190,6 +190,25 @@ def test_tune_cache_stale_variant_falls_back(dn, tmp_path):
     dn.tune_clear()
 
 
+def test_tune_cache_mode0_through_ttmc(dn, tmp_path):
+    """Order-3 mode 0 (FP64, large): by default through the fused TTMc pass; a cache entry
+    with order 2 names its variant (a variant no longer compiled falls back to the default
+    one); an entry for a stream kernel selects that kernel's smaller workspace."""
+    spec, dims = "ijk,ja,ka->ia", [1024, 1024, 1024]
+    dn.tune_clear()
+    default = dn.workspace_size(spec, dims, [24])
+    stream = dn.workspace_size(spec, dims, [24], split_hint=1)  # a hint keeps the stream kernel
+    assert default > stream  # the TTMc pass holds R x R tiles and a padded factor copy
+    f = tmp_path / "ttmc.txt"
+    for line, want in ((f"{KEY_1024_M0} 1 1 1 0 2 2 0 1.0\n", default), (f"{KEY_1024_M0} 1 1 1 0 99 2 0 1.0\n", default),
+                       (f"{KEY_1024_M0} 2 16 1 0 1 0 0 1.0\n", stream)):
+        f.write_text(line)
+        dn.tune_clear()
+        dn.tune_load(f)
+        assert dn.workspace_size(spec, dims, [24]) == want, line
+    dn.tune_clear()
+
+
 def test_tune_rejects_bad_input(dn, tmp_path):
     f = tmp_path / "bad.txt"
     f.write_text("s:N3:n0:p0:R24:8x8x8 two 16 1 0 1 0 0 1.0\n")
