@@ -495,6 +495,17 @@ deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, 
     const size_t cb = u_elem_bytes(o.precision), yb = dtype_bytes(o.out_dtype);
     const size_t ybytes = static_cast<size_t>(dims[n] * L) * yb;
     if (overlaps(Y, ybytes, C, static_cast<size_t>(R * L) * cb)) return fail(DEINSUM_ERR_INVALID_ARG, "Y overlaps C");
+    {
+        int64_t nx = 1;
+        for (int m = 0; m < spec->order; ++m) nx *= dims[m];
+        const size_t xbytes = o.precision == DEINSUM_PREC_FX20 ? static_cast<size_t>(fx20_bytes(nx))
+                                                                : static_cast<size_t>(nx) * x_elem_bytes(o.precision);
+        if (overlaps(Y, ybytes, X, xbytes)) return fail(DEINSUM_ERR_INVALID_ARG, "Y overlaps X");
+        if (U)
+            for (int k = 0; k < spec->order - 1; ++k)
+                if (overlaps(Y, ybytes, U[k], static_cast<size_t>(dims[spec->factor_mode[k]] * R) * cb))
+                    return fail(DEINSUM_ERR_INVALID_ARG, "Y overlaps factor operand " + std::to_string(k));
+    }
     deinsum_spec ms = *spec;
     ms.kind = DEINSUM_MTTKRP;
     const int64_t ranks[2] = {R, L};

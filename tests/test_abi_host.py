@@ -142,6 +142,25 @@ def test_mttkrp_argument_errors_before_enqueue(dn):
     assert lib.deinsum_mttkrp(ctypes.byref(s), d, 2, X, (ctypes.c_void_p * 2)(B, C), M, None, None) == -1  # TTMc spec
 
 
+def test_mttkrp_gemm_chain_argument_errors_before_enqueue(dn):
+    # Fake (never dereferenced) addresses: validation must reject before any launch.
+    X, B, C, D, Y = 0x10000000, 0x20000000, 0x30000000, 0x50000000, 0x60000000
+    lib = dn._lib.load()
+    s = dn.parse("ijk,ja,ka,al->il")
+    d = (ctypes.c_int64 * 3)(4, 4, 4)
+    U = (ctypes.c_void_p * 2)(B, C)
+    call = lambda R, L, Dp, Yp, spec=s: lib.deinsum_mttkrp_mm(ctypes.byref(spec), d, R, L, X, U, Dp, Yp, None, None)
+    assert call(0, 3, D, Y) == -4            # R < 1
+    assert call(2, 0, D, Y) == -4            # L < 1
+    assert call(2, 5000, D, Y) == -4         # L too large
+    assert call(2, 3, None, Y) == -1         # null C
+    assert call(2, 3, D, D + 8) == -1        # Y overlaps C
+    assert call(2, 3, D, X + 8) == -1        # Y overlaps X
+    assert call(2, 3, D, B) == -1            # Y overlaps a factor
+    assert call(2, 3, D, Y, dn.parse("ijk,ja,ka->ia")) == -1  # not a chain spec
+    assert dn.last_error()
+
+
 def test_ttmc_rank_limit(dn):
     with pytest.raises(dn.DeinsumError):
         dn.workspace_size("ijk,jb,kc->ibc", [8, 8, 8], [65, 4])
