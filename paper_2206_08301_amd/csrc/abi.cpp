@@ -166,9 +166,11 @@ bool via_ttmc_eligible(const MttkrpProblem &pb, const deinsum_opts &o)
 // When the free mode is n <= N-3, the last two modes are both contracted and X's
 // memory is also an order N-1 tensor with them merged; its factor is their
 // Khatri-Rao product (I_{N-2} I_{N-1} x R), built per call into the workspace.
+// Only for N >= 4: at N = 3 the two merged modes are all the contracted modes, so
+// their product would be the whole Khatri-Rao product, which is never stored.
 bool merge_last_two(const MttkrpProblem &pb, int plan_hint)
 {
-    if (plan_hint != 0 || pb.N < 3 || pb.n > pb.N - 3) return false;
+    if (plan_hint != 0 || pb.N < 4 || pb.n > pb.N - 3) return false;
     if (pb.prec != P_FX20 && pb.prec != P_BF16 && pb.prec != P_BF16X3) return false;
     const int64_t ia = pb.dims[pb.N - 2], ib = pb.dims[pb.N - 1];
     if (ib % 32 == 0 && ib >= 256) return false;

@@ -70,12 +70,34 @@ def x_tensor(seed: int, dims, dist: str = "uniform") -> np.ndarray:
     return x_values(seed, np.arange(n, dtype=np.uint64), dist).reshape(dims)
 
 
-def x_range(seed: int, start: int, count: int, dist: str = "uniform", chunk: int = 1 << 22) -> np.ndarray:
-    """Entries at linear indices [start, start + count), generated in chunks."""
-    out = np.empty(count, dtype=np.float64)
-    for c0 in range(0, count, chunk):
+def _threads() -> int:
+    import os
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def x_range(seed: int, start: int, count: int, dist: str = "uniform", chunk: int = 1 << 22,
+            out: np.ndarray | None = None) -> np.ndarray:
+    """Entries at linear indices [start, start + count), generated in chunks (numpy
+    releases the GIL inside its ufuncs, so the chunks run on a thread pool)."""
+    if out is None:
+        out = np.empty(count, dtype=np.float64)
+    starts = list(range(0, count, chunk))
+
+    def one(c0):
         c1 = min(count, c0 + chunk)
         out[c0:c1] = x_values(seed, np.arange(start + c0, start + c1, dtype=np.uint64), dist)
+
+    if len(starts) <= 1:
+        for c0 in starts:
+            one(c0)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(_threads(), len(starts))) as ex:
+            list(ex.map(one, starts))
     return out
 
 
@@ -96,6 +118,37 @@ def x_slab(seed: int, dims, mode: int, index: int, dist: str = "uniform") -> np.
         g = grids[m] + (np.uint64(index) if m == mode else np.uint64(0))
         lin += g * strides[m]
     return x_values(seed, lin, dist)
+
+
+def x_rows(seed: int, dims, mode: int, indices, dist: str = "uniform") -> np.ndarray:
+    """The sub-tensor whose mode-``mode`` index runs over ``indices`` (in that order):
+    shape = dims with dims[mode] = len(indices)."""
+    dims = [int(d) for d in dims]
+    idx = [int(i) for i in indices]
+    outer = int(np.prod(dims[:mode])) if mode else 1
+    inner = int(np.prod(dims[mode + 1:])) if mode + 1 < len(dims) else 1
+    sub = list(dims)
+    sub[mode] = len(idx)
+    out = np.empty((outer, len(idx), inner), dtype=np.float64)
+    if inner >= (1 << 20):  # long contiguous runs: generate each run directly
+        for a in range(outer):
+            for p, i in enumerate(idx):
+                x_range(seed, (a * dims[mode] + i) * inner, inner, dist, out=out[a, p])
+        return out.reshape(sub)
+    b = np.arange(inner, dtype=np.uint64)
+    rows_per = max(1, (1 << 22) // max(1, inner))
+
+    def one(a0):
+        a1 = min(outer, a0 + rows_per)
+        a = np.arange(a0, a1, dtype=np.uint64)
+        for p, i in enumerate(idx):
+            lin = ((a * np.uint64(dims[mode]) + np.uint64(i)) * np.uint64(inner))[:, None] + b[None, :]
+            out[a0:a1, p, :] = x_values(seed, lin, dist)
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(one, range(0, outer, rows_per)))
+    return out.reshape(sub)
 
 
 def normal_factor(seed: int, rows: int, cols: int) -> np.ndarray:

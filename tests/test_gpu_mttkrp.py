@@ -311,3 +311,31 @@ def test_mttkrp_gemm_chain_1024cubed(dn, synth, oracle_mod):
         assert nrel(Y[i].cpu().numpy(), ref) <= 1e-12, i
     del X
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fx20", "bf16", "bf16x3"])
+@pytest.mark.parametrize("dims", [(64, 64, 64), (20, 30, 45)])
+def test_order3_mode0_never_merges_last_modes(dn, synth, oracle_mod, precision, dims):
+    """Order 3, free mode 0, a short or ragged last mode: the two contracted modes are all
+    the other modes, so merging them would store the whole Khatri-Rao product; the plan
+    must stay unmerged (no " m2") and still meet the form's bound against the oracle."""
+    R = 16
+    X = synth.x_tensor(4545, dims)
+    rng = np.random.default_rng(45)
+    if precision == "fx20":
+        Xd = dn.to_fx20(to_dev(X))
+    elif precision == "bf16":
+        Xd = to_dev(X, torch.float32).to(torch.bfloat16)
+    else:
+        Xd = to_dev(X, torch.float32)
+    U = factors_for(rng, dims, R, 0)
+    U = [None if u is None else u.astype(np.float32).astype(np.float64) for u in U]
+    rep = dn.Report()
+    got = dn.mttkrp(SPEC3[0], Xd, [to_dev(u, torch.float32) for u in operands(U, 0)], precision=precision,
+                    out_dtype=torch.float64, report=rep)
+    torch.cuda.synchronize()
+    name = rep.plan_name.decode()
+    flush(f"{precision} dims={dims}: {name}")
+    assert not name.endswith(" m2"), name
+    tol = {"fx20": 4e-6, "bf16x3": 1e-5, "bf16": 2e-2}[precision]
+    assert nrel(got.cpu().numpy(), oracle_mod.mttkrp(X, U, 0)) <= tol
