@@ -183,6 +183,32 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
                               const deinsum_opts *opts, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): deinsum_mttkrp with its
+ * workspace (partial output tiles, outer-weight table, merged factor) taken from
+ * a fixed library-owned device array of DEINSUM_NOALLOC_SCRATCH_BYTES per device
+ * instead of the library pool or a caller buffer.  The call allocates nothing:
+ * no hipMalloc / hipFree, no allocating library routine.  The array is set aside
+ * when the library's code object is loaded on a device and held until the
+ * process ends; its device address is looked up on the first call on each device.
+ * Arguments, results and plans are those of deinsum_mttkrp (bitwise the same
+ * output), except:
+ *   - opts->workspace must be NULL (DEINSUM_ERR_INVALID_ARG otherwise);
+ *   - a problem whose plan needs more than DEINSUM_NOALLOC_SCRATCH_BYTES of
+ *     workspace (deinsum_workspace_size) is rejected with DEINSUM_ERR_NO_MEMORY
+ *     before anything is enqueued (e.g. 80^5 FP64, R = 24, needs 133 MiB).
+ * Every call on one device shares that device's array and leaves its contents
+ * behind (nothing in it needs to start at zero: each call writes every workspace
+ * byte it reads).  Calls that overlap on one device -- on different streams,
+ * or from different threads without ordering -- race on the array and give
+ * wrong results; order them on one stream or with events.
+ */
+#define DEINSUM_NOALLOC_SCRATCH_BYTES (64u << 20)
+deinsum_status deinsum_mttkrp_noalloc(const deinsum_spec *spec, const int64_t *dims, int64_t R,
+                                      const void *X, const void *const *U, void *M,
+                                      const deinsum_opts *opts, void *stream);
+
+/*
  * The MTTKRP-GEMM chain of the paper's running example (Sec. II-A), e.g.
  * "ijk,ja,ka,al->il": the MTTKRP operands followed by one more operand
  * "<rank letter><l>", output "<free letter><l>":

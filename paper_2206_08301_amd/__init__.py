@@ -147,7 +147,7 @@ def workspace_size(spec, dims, ranks, precision="fp64", out_dtype=None, plan_hin
 
 
 def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None, plan_hint=0,
-           split_hint=0, report=None, stream=None):
+           split_hint=0, report=None, stream=None, _entry="deinsum_mttkrp"):
     """Mode-n MTTKRP.  ``U`` lists the factor operands in the spec's operand order."""
     sp = _spec(spec)
     if sp.kind != MTTKRP:
@@ -182,10 +182,24 @@ def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=Non
     o = _opts(precision, out_dtype, workspace, plan_hint, split_hint, report)
     xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
     with torch.cuda.device(X.device):
-        _lib.check(_lib.load().deinsum_mttkrp(ctypes.byref(sp), _i64(X.shape), R, ctypes.c_void_p(xptr),
-                                              ptrs, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o),
-                                              _stream(stream)))
+        _lib.check(getattr(_lib.load(), _entry)(ctypes.byref(sp), _i64(X.shape), R, ctypes.c_void_p(xptr),
+                                                ptrs, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o),
+                                                _stream(stream)))
     return out
+
+
+def mttkrp_noalloc(spec, X, U, precision="fp64", out=None, out_dtype=None, plan_hint=0, split_hint=0,
+                   report=None, stream=None):
+    """deinsum_mttkrp_noalloc: the MTTKRP with its workspace in the library's fixed
+    per-device scratch array (no device allocation by the library; ``out`` is allocated
+    here by torch when not given).  Problems whose plan needs more than
+    NOALLOC_SCRATCH_BYTES of workspace raise DeinsumError (NO_MEMORY)."""
+    return mttkrp(spec, X, U, precision=precision, out=out, out_dtype=out_dtype, workspace=None,
+                  plan_hint=plan_hint, split_hint=split_hint, report=report, stream=stream,
+                  _entry="deinsum_mttkrp_noalloc")
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def tune_mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, reps=5, batched=False, stream=None):

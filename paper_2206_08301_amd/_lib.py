@@ -91,6 +91,7 @@ EXPORTS = (
     "deinsum_server_stats", "deinsum_server_destroy", "deinsum_tune_mttkrp", "deinsum_tune_batch_mttkrp",
     "deinsum_tune_load", "deinsum_tune_save", "deinsum_tune_clear", "deinsum_tune_entries",
     "deinsum_fx20_size", "deinsum_fx20_encode", "deinsum_tune_ttmc", "deinsum_mttkrp_mm",
+    "deinsum_mttkrp_noalloc",
 )
 
 _lib = None
@@ -117,6 +118,8 @@ def load():
     lib.deinsum_mttkrp.argtypes = [ctypes.POINTER(Spec), i64p, ctypes.c_int64, vp,
                                    ctypes.POINTER(vp), vp, ctypes.POINTER(Opts), vp]
     lib.deinsum_mttkrp.restype = ctypes.c_int
+    lib.deinsum_mttkrp_noalloc.argtypes = lib.deinsum_mttkrp.argtypes
+    lib.deinsum_mttkrp_noalloc.restype = ctypes.c_int
     lib.deinsum_ttmc.argtypes = [ctypes.POINTER(Spec), i64p, i64p, vp, ctypes.POINTER(vp), vp,
                                  ctypes.POINTER(Opts), vp]
     lib.deinsum_ttmc.restype = ctypes.c_int

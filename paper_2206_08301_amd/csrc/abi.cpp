@@ -70,6 +70,35 @@ deinsum_status pool_get(size_t bytes, void **out)
     return DEINSUM_OK;
 }
 
+// ------------------------------------------------------------------ no-alloc scratch
+// Workspace of deinsum_mttkrp_noalloc: a fixed device array that every device holding
+// the library keeps until the process ends.  Host code never passes `scratch` itself
+// (on the host it names a stand-in, not device memory): the device address is looked
+// up once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[DEINSUM_NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64];
+
+deinsum_status scratch_get(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(DEINSUM_ERR_DEVICE, "mttkrp_noalloc: no current HIP device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(DEINSUM_ERR_DEVICE, std::string("mttkrp_noalloc: hipGetSymbolAddress(scratch) failed: ") +
+                                                hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DEINSUM_OK;
+}
+
 size_t x_elem_bytes(int prec)
 {
     switch (prec) {
@@ -479,6 +508,30 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     if (deinsum_status st = run_mttkrp(c, ws, s)) return st;
     clear_error();
     return DEINSUM_OK;
+}
+
+deinsum_status deinsum_mttkrp_noalloc(const deinsum_spec *spec, const int64_t *dims, int64_t R, const void *X,
+                                      const void *const *U, void *M, const deinsum_opts *opts, void *stream)
+{
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (o.workspace) return fail(DEINSUM_ERR_INVALID_ARG, "mttkrp_noalloc: opts.workspace must be NULL");
+    // The plan's workspace must fit the fixed array; checked before anything is enqueued.
+    if (deinsum_status st = check_dims(spec, dims)) return st;
+    if (spec->kind != DEINSUM_MTTKRP) return fail(DEINSUM_ERR_INVALID_ARG, "spec is not an MTTKRP");
+    const int64_t r[1] = {R};
+    size_t need = 0;
+    if (deinsum_status st = deinsum_workspace_size(spec, dims, r, &o, &need)) return st;
+    if (need > DEINSUM_NOALLOC_SCRATCH_BYTES)
+        return fail(DEINSUM_ERR_NO_MEMORY, "mttkrp_noalloc: the plan needs " + std::to_string(need) +
+                                               " bytes of workspace, more than the fixed " +
+                                               std::to_string(static_cast<size_t>(DEINSUM_NOALLOC_SCRATCH_BYTES)) +
+                                               "-byte scratch array; call deinsum_mttkrp");
+    void *ptr = nullptr;
+    if (deinsum_status st = scratch_get(&ptr)) return st;
+    o.workspace = ptr;
+    o.workspace_bytes = DEINSUM_NOALLOC_SCRATCH_BYTES;
+    return deinsum_mttkrp(spec, dims, R, X, U, M, &o, stream);
 }
 
 deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, int64_t R, int64_t L,
