@@ -62,7 +62,9 @@ typedef enum deinsum_status {
 
 typedef enum deinsum_kind { DEINSUM_MTTKRP = 1, DEINSUM_TTMC = 2, DEINSUM_MTTKRP_MM = 3 } deinsum_kind;
 
-typedef enum deinsum_dtype { DEINSUM_F64 = 0, DEINSUM_F32 = 1, DEINSUM_BF16 = 2 } deinsum_dtype;
+/* Element types.  DEINSUM_FX20 names X held in the FX20 storage below
+ * (deinsum_fx20_encode); it is only a storage code of X (opts.x_dtype). */
+typedef enum deinsum_dtype { DEINSUM_F64 = 0, DEINSUM_F32 = 1, DEINSUM_BF16 = 2, DEINSUM_FX20 = 3 } deinsum_dtype;
 
 /*
  * Arithmetic form.  The paper fixes no precision (Sec. VI-A); FP64 is the
@@ -85,13 +87,25 @@ typedef enum deinsum_dtype { DEINSUM_F64 = 0, DEINSUM_F32 = 1, DEINSUM_BF16 = 2 
  *            FP64 beyond one slice.  Free mode = last mode: X decoded to FP32,
  *            FP32 matrix-core products.  Output FP32 or FP64.  Reads 3 bytes
  *            per element of X instead of 8.
+ *   AUTO   : the library picks the form from opts.tol and the storage of the
+ *            operands (opts.x_dtype, opts.u_dtype): among the compiled forms
+ *            that read that storage, the cheapest whose estimated error
+ *            (deinsum_estimate_error) is at most tol.  Forms by X storage:
+ *            F64 -> FP64; F32 -> BF16X3, FP32 (BF16X3 first: the same bytes
+ *            and the faster of the two); BF16 -> BF16; FX20 -> FX20.  When no
+ *            form reading that storage meets tol the call fails with
+ *            DEINSUM_ERR_UNSUPPORTED before anything is enqueued (pick the
+ *            storage with deinsum_choose_storage).  The report names the form
+ *            that ran and its estimate.  MTTKRP, MTTKRP-GEMM chain and TTMc
+ *            (TTMc forms: FP64, FP32, BF16).
  */
 typedef enum deinsum_precision {
     DEINSUM_PREC_FP64 = 0,
     DEINSUM_PREC_FP32 = 1,
     DEINSUM_PREC_BF16 = 2,
     DEINSUM_PREC_BF16X3 = 3,
-    DEINSUM_PREC_FX20 = 4
+    DEINSUM_PREC_FX20 = 4,
+    DEINSUM_PREC_AUTO = 5
 } deinsum_precision;
 
 /* Parsed einsum (deinsum_parse).  Letters are ASCII a-z / A-Z. */
@@ -119,6 +133,8 @@ typedef struct deinsum_report {
     double alg_flops;           /* flops of the two-stage method                 */
     char plan_name[48];
     double tuned_us;            /* deinsum_tune_*: median time of the chosen plan */
+    int32_t precision;          /* the form that ran (resolves DEINSUM_PREC_AUTO) */
+    double est_err;             /* deinsum_estimate_error of that form for this call */
 } deinsum_report;
 
 typedef struct deinsum_opts {
@@ -134,9 +150,19 @@ typedef struct deinsum_opts {
                                  for the ranks (tests, tuning)                        */
     int32_t split_hint;       /* 0 = planner choice; else outer-chunk count          */
     deinsum_report *report;   /* optional host out-parameter                         */
+    double tol;               /* DEINSUM_PREC_AUTO: largest acceptable estimated
+                                 normwise relative error (> 0)                        */
+    int32_t x_dtype;          /* DEINSUM_PREC_AUTO: storage of X (deinsum_dtype)     */
+    int32_t u_dtype;          /* DEINSUM_PREC_AUTO: factor dtype, DEINSUM_F64 or
+                                 DEINSUM_F32 (the FP64 form takes F64 factors, every
+                                 other form F32)                                      */
+    int32_t deterministic;    /* 1 (default): bitwise reproducible results.  Every
+                                 compiled path reduces in a fixed order, so 0 is
+                                 accepted and gives the same results               */
 } deinsum_opts;
 
-/* Fill *opts with defaults: FP64, F64 output, library workspace, planner choice. */
+/* Fill *opts with defaults: FP64, F64 output, library workspace, planner choice,
+ * tol 1e-12, x_dtype = u_dtype = F64, deterministic 1. */
 void deinsum_opts_init(deinsum_opts *opts);
 
 /*
@@ -265,7 +291,14 @@ deinsum_status deinsum_synth_fill(void *X, int32_t dtype, int64_t count, uint64_
  * 2^-19 * max|X| / rms(X) (3.3e-6 for uniform data, about 1e-6 in practice).
  * Layout of the buffer (256-byte aligned, deinsum_fx20_size bytes):
  *   bytes [0, 256)                 header: uint32 magic 0x30325846 ("FX20"),
- *                                  int32 e, int64 count, double max|X|, zeros;
+ *                                  int32 e, int64 count, double max|X|,
+ *                                  uint64 S = sum of (x 2^-(e+19))^2 in units
+ *                                  of 2^-24, uint64 E = sum of the squared
+ *                                  rounding errors (x - m 2^e)^2 2^-2e in units
+ *                                  of 2^-28 (both from per-wave FP64 sums,
+ *                                  rounded, added as integers: deterministic),
+ *                                  so ||X - X_fx20|| / ||X|| = 2^-21 sqrt(E/S);
+ *                                  zeros;
  *   bytes [256, 256 + A(2 count))  FP16 plane: h[i] as IEEE binary16 (exact);
  *   then A(count) bytes            int8 plane: l[i] (two's complement),
  * with A(b) = b rounded up to a multiple of 256.  X keeps its row-major index
@@ -280,6 +313,62 @@ deinsum_status deinsum_fx20_size(int64_t count, size_t *bytes);
  * 256-byte aligned).  Asynchronous on `stream`; deterministic. */
 deinsum_status deinsum_fx20_encode(const void *src, int32_t src_dtype, int64_t count, void *dst, size_t dst_bytes,
                                    void *stream);
+
+/*
+ * Error estimate of an arithmetic form: the rule behind DEINSUM_PREC_AUTO and
+ * deinsum_report.est_err.  *est_err estimates the normwise relative error
+ * ||M - M*||_F / ||M*||_F against the exact result for the FP64 operands the
+ * caller's storage was rounded from.  It is a root-sum-square model of
+ * independent rounding errors, for data whose sums do not cancel much more than
+ * sums of random-sign terms (it is not a bound for adversarial data), doubled
+ * as a margin:
+ *   est = 2 sqrt(dx^2 + d_op^2 + (N-2) d_st^2 + d_drop^2 + d_acc^2)
+ * with u = 2^-53 (FP64), 2^-24 (FP32), 2^-8 (BF16), 2^-11 (FP16) and a value
+ * rounded to nearest carrying a relative error of rms u/sqrt(3), a hi + lo
+ * split of one format u^2/3:
+ *   dx     : X as the form reads it -- 0 (F64), 2^-24/sqrt3 (F32),
+ *            2^-8/sqrt3 (BF16), sqrt((2^-24/sqrt3)^2 + (2^-16/3)^2) (BF16X3),
+ *            and for FX20 the exact value recorded in the buffer's header;
+ *   d_op   : the factor operand of the matrix-core product, likewise (FP32
+ *            factors; BF16-rounded, BF16-split or FP16-split on the device);
+ *   d_st   : each of the other N-2 factors, applied in FP64 from FP32 storage
+ *            (2^-24/sqrt3; 0 in the FP64 form);
+ *   d_drop : product terms left out -- BF16X3 lo*lo (2^-16/3), FX20 l*u_lo
+ *            (2^-22/3);
+ *   d_acc  : 2^-53 sqrt(L/3) for FP64 sums over the L = prod_{m != n} I_m
+ *            terms, plus 2^-24 sqrt(k/3) for the k terms summed in FP32 before
+ *            each fold into FP64 (MTTKRP: the plan's slice of the matrix-core
+ *            mode; fused TTMc pass: I_a + I_c), doubled for FX20 (its FP32 tile
+ *            holds an offset removed after the fold).
+ * opts->precision names the form, or DEINSUM_PREC_AUTO with tol / x_dtype /
+ * u_dtype to ask which form AUTO picks (*precision receives it).  X is read
+ * only for FX20: its header is copied to the host on `stream`, which this
+ * synchronises; X may be NULL otherwise.  Host only otherwise.
+ */
+deinsum_status deinsum_estimate_error(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
+                                      const void *X, const deinsum_opts *opts, int32_t *precision,
+                                      double *est_err, void *stream);
+
+/*
+ * Storage of X for a tolerance (host only): the cheapest storage of X -- bytes
+ * per element BF16 2, FX20 3, F32 4, F64 8 -- for which a form reading it has
+ * deinsum_estimate_error <= tol for this problem (factors F32, or F64 for the
+ * F64 storage).  FX20 is considered only when max_abs > 0 and rms > 0 (max |x|
+ * and the root-mean-square of X, e.g. from deinsum_tensor_stats); its storage
+ * error is then modelled as 2^(e-1) / (sqrt(3) rms), e the FX20 exponent of
+ * max_abs.  *x_dtype receives the storage, *precision the form AUTO then runs,
+ * *est_err its estimate.  No storage meets tol: DEINSUM_ERR_UNSUPPORTED.
+ */
+deinsum_status deinsum_choose_storage(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
+                                      double tol, double max_abs, double rms, int32_t *x_dtype,
+                                      int32_t *precision, double *est_err);
+
+/* max |x| and sqrt(mean x^2) over `count` elements of the device array X (F64,
+ * F32 or BF16).  Synchronises `stream` and returns the values on the host.
+ * Deterministic (integer-exact max; squares summed per wave in a fixed order and
+ * added in fixed point).  Uses the library's workspace pool (16 bytes). */
+deinsum_status deinsum_tensor_stats(const void *X, int32_t dtype, int64_t count, double *max_abs, double *rms,
+                                    void *stream);
 
 /* Elementwise conversion f64 -> f32 / bf16 or f32 -> bf16, round to nearest even. */
 deinsum_status deinsum_convert(const void *src, int32_t src_dtype, void *dst, int32_t dst_dtype,
@@ -387,15 +476,41 @@ deinsum_status deinsum_server_submit(deinsum_server *s, int32_t tensor_id, int32
 deinsum_status deinsum_server_replay(deinsum_server *s, int64_t n, const double *arrival_s, const int32_t *tensor_id,
                                      const int32_t *mode);
 
-/* Block until every submitted request has completed (or the server failed). */
+/* Block until every submitted request has finished, successfully or not.
+ * Returns DEINSUM_OK when all succeeded, else the status of the first failed
+ * request (deinsum_last_error names it and counts the failures). */
 deinsum_status deinsum_server_drain(deinsum_server *s);
+
+/* State of one request (deinsum_server_poll).  A failed request holds the
+ * negative deinsum_status it failed with: DEINSUM_ERR_NO_MEMORY when its MTTKRP
+ * workspace alone exceeds hbm_budget_bytes (it is never admitted), the status of
+ * the library call that could not be enqueued, or DEINSUM_ERR_DEVICE when the
+ * device reported an error for the launch that carried it.  A failure ends that
+ * request only: other requests, and later requests of the same tensor (which
+ * then see the factors as they were), are served as usual. */
+typedef enum deinsum_request_status {
+    DEINSUM_REQ_DONE = 0,     /* served; result written                         */
+    DEINSUM_REQ_PENDING = 1,  /* submitted, not yet launched                    */
+    DEINSUM_REQ_RUNNING = 2   /* launched on the device                         */
+} deinsum_request_status;
+/* Flag of a served request: the factor update's V had a pivot below
+ * 1e-14 * max diag(V) (rank deficiency) and was regularised by that floor, so
+ * the update is not the exact least-squares solution. */
+#define DEINSUM_REQ_REGULARISED 1
+
+/* Non-blocking query of request `request_id`: *status (deinsum_request_status or
+ * a negative deinsum_status), *flags (DEINSUM_REQ_* bits, valid when DONE) and
+ * *done_s (seconds since start when it finished, -1 before).  Thread-safe; any
+ * output may be NULL. */
+deinsum_status deinsum_server_poll(const deinsum_server *s, int64_t request_id, int32_t *status, int32_t *flags,
+                                   double *done_s);
 
 /* Per request i < n: arrival, completion (seconds since start, -1 if not done)
  * and the epoch (batched) or launch index that served it.  Arrays may be NULL. */
 deinsum_status deinsum_server_results(const deinsum_server *s, int64_t n, double *arrival_s, double *done_s,
                                       int64_t *epoch);
 
-/* Requests completed, epochs (or launches) issued, largest epoch. */
+/* Requests served successfully, epochs (or launches) issued, largest epoch. */
 deinsum_status deinsum_server_stats(const deinsum_server *s, int64_t *completed, int64_t *epochs, int64_t *max_batch);
 
 /* Stop the scheduler after the submitted requests finish, free everything. */

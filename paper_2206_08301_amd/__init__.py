@@ -23,8 +23,10 @@ from ._lib import DeinsumError, Report, Spec  # noqa: F401
 MTTKRP = 1
 TTMC = 2
 MTTKRP_MM = 3
-F64, F32, BF16 = 0, 1, 2
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fx20": 4}
+F64, F32, BF16, FX20_STORAGE = 0, 1, 2, 3
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3, "fx20": 4, "auto": 5}
+PRECISION_NAMES = {v: k for k, v in PRECISIONS.items()}
+STORAGE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", FX20_STORAGE: "fx20"}
 _X_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.bfloat16, "bf16x3": torch.float32,
             "fx20": None}
 _U_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32, "bf16x3": torch.float32,
@@ -58,11 +60,17 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _opts(precision, out_dtype, workspace, plan_hint, split_hint, report):
+def _opts(precision, out_dtype, workspace, plan_hint, split_hint, report, tol=None, x_dtype=None, u_dtype=None):
     o = _lib.Opts()
     _lib.load().deinsum_opts_init(ctypes.byref(o))
     o.precision = PRECISIONS[precision]
     o.out_dtype = _DT_CODE[out_dtype]
+    if tol is not None:
+        o.tol = float(tol)
+    if x_dtype is not None:
+        o.x_dtype = int(x_dtype)
+    if u_dtype is not None:
+        o.u_dtype = int(u_dtype)
     if workspace is not None:
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -96,11 +104,16 @@ class FX20:
         return self.buf.device
 
     def header(self) -> dict:
-        """Header fields (copies 24 bytes to the host)."""
+        """Header fields (copies 40 bytes to the host), with the storage error
+        ||X - X_fx20|| / ||X|| and rms(X) derived from the recorded sums."""
+        import math
         import struct
-        raw = bytes(self.buf[:24].cpu().numpy().tobytes())
-        magic, e, count, mx = struct.unpack("<Iiqd", raw)
-        return {"magic": magic, "exp2": e, "count": count, "max_abs": mx}
+        raw = bytes(self.buf[:40].cpu().numpy().tobytes())
+        magic, e, count, mx, ssq, esq = struct.unpack("<IiqdQQ", raw)
+        rel = math.sqrt(esq / ssq) * 2.0 ** -21 if ssq else 0.0
+        rms = math.sqrt(ssq * 2.0 ** -24 / count) * 2.0 ** (e + 19) if count else 0.0
+        return {"magic": magic, "exp2": e, "count": count, "max_abs": mx, "sumsq_q": ssq, "errsq_q": esq,
+                "storage_rel_err": rel, "rms": rms}
 
 
 def fx20_size(count: int) -> int:
@@ -123,6 +136,37 @@ def to_fx20(X: torch.Tensor, stream=None) -> FX20:
     return FX20(buf, X.shape)
 
 
+def _storage_code(X):
+    """opts.x_dtype of X: its dtype, or FX20 for an FX20 buffer."""
+    if isinstance(X, FX20):
+        return FX20_STORAGE
+    if not isinstance(X, torch.Tensor) or X.dtype not in _DT_CODE:
+        raise TypeError("X must be a float64 / float32 / bfloat16 device tensor or an FX20 buffer")
+    return _DT_CODE[X.dtype]
+
+
+def _x_check(X, precision):
+    if precision == "fx20":
+        if not isinstance(X, FX20):
+            raise TypeError("the fx20 form takes X from to_fx20()")
+    elif precision == "auto":
+        if not isinstance(X, FX20):
+            if not isinstance(X, torch.Tensor) or X.device.type != "cuda" or not X.is_contiguous():
+                raise TypeError("X must be a contiguous CUDA (HIP) tensor or an FX20 buffer")
+            _storage_code(X)
+    else:
+        _check_tensor(X, _X_DTYPE[precision], "X")
+
+
+def _u_dtype_for(precision, U):
+    if precision != "auto":
+        return _U_DTYPE[precision]
+    dt = U[0].dtype
+    if dt not in (torch.float64, torch.float32):
+        raise TypeError("factors must be float64 or float32")
+    return dt
+
+
 def _check_tensor(t, dtype, name):
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
@@ -133,7 +177,7 @@ def _check_tensor(t, dtype, name):
 
 
 def _default_out_dtype(precision):
-    return torch.float64 if precision == "fp64" else torch.float32
+    return torch.float64 if precision in ("fp64", "auto") else torch.float32
 
 
 def workspace_size(spec, dims, ranks, precision="fp64", out_dtype=None, plan_hint=0, split_hint=0) -> int:
@@ -147,23 +191,23 @@ def workspace_size(spec, dims, ranks, precision="fp64", out_dtype=None, plan_hin
 
 
 def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None, plan_hint=0,
-           split_hint=0, report=None, stream=None, _entry="deinsum_mttkrp"):
-    """Mode-n MTTKRP.  ``U`` lists the factor operands in the spec's operand order."""
+           split_hint=0, report=None, stream=None, tol=None, _entry="deinsum_mttkrp"):
+    """Mode-n MTTKRP.  ``U`` lists the factor operands in the spec's operand order.
+    ``precision="auto"`` with ``tol`` lets the library pick the cheapest form that reads
+    X's storage (its dtype, or an FX20 buffer) within the tolerance; ``report`` then
+    names the form (``report.precision``) and its estimated error (``report.est_err``)."""
     sp = _spec(spec)
     if sp.kind != MTTKRP:
         raise ValueError("spec is not an MTTKRP")
-    if precision == "fx20":
-        if not isinstance(X, FX20):
-            raise TypeError("the fx20 form takes X from to_fx20()")
-    else:
-        _check_tensor(X, _X_DTYPE[precision], "X")
+    _x_check(X, precision)
+    udt = _u_dtype_for(precision, U)
     if X.dim() != sp.order:
         raise ValueError(f"X has {X.dim()} modes, spec has {sp.order}")
     if len(U) != sp.n_factors:
         raise ValueError(f"expected {sp.n_factors} factors, got {len(U)}")
     R = None
     for k, u in enumerate(U):
-        _check_tensor(u, _U_DTYPE[precision], f"U[{k}]")
+        _check_tensor(u, udt, f"U[{k}]")
         m = sp.factor_mode[k]
         if u.dim() != 2 or u.shape[0] != X.shape[m]:
             raise ValueError(f"factor {k} must be {X.shape[m]} x R")
@@ -179,7 +223,8 @@ def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=Non
         if tuple(out.shape) != (X.shape[n], R):
             raise ValueError("out has the wrong shape")
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
-    o = _opts(precision, out_dtype, workspace, plan_hint, split_hint, report)
+    o = _opts(precision, out_dtype, workspace, plan_hint, split_hint, report, tol=tol,
+              x_dtype=_storage_code(X), u_dtype=_DT_CODE[udt])
     xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
     with torch.cuda.device(X.device):
         _lib.check(getattr(_lib.load(), _entry)(ctypes.byref(sp), _i64(X.shape), R, ctypes.c_void_p(xptr),
@@ -189,38 +234,36 @@ def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=Non
 
 
 def mttkrp_noalloc(spec, X, U, precision="fp64", out=None, out_dtype=None, plan_hint=0, split_hint=0,
-                   report=None, stream=None):
+                   report=None, stream=None, tol=None):
     """deinsum_mttkrp_noalloc: the MTTKRP with its workspace in the library's fixed
     per-device scratch array (no device allocation by the library; ``out`` is allocated
     here by torch when not given).  Problems whose plan needs more than
     NOALLOC_SCRATCH_BYTES of workspace raise DeinsumError (NO_MEMORY)."""
     return mttkrp(spec, X, U, precision=precision, out=out, out_dtype=out_dtype, workspace=None,
-                  plan_hint=plan_hint, split_hint=split_hint, report=report, stream=stream,
+                  plan_hint=plan_hint, split_hint=split_hint, report=report, stream=stream, tol=tol,
                   _entry="deinsum_mttkrp_noalloc")
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
-def tune_mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, reps=5, batched=False, stream=None):
+def tune_mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, reps=5, batched=False, stream=None,
+                tol=None):
     """Autotune the MTTKRP plan for this problem (runs it; ``out`` is overwritten) and
     cache the fastest; later calls with the same shape use it.  Returns the winner's Report."""
     sp = _spec(spec)
     if sp.kind != MTTKRP:
         raise ValueError("spec is not an MTTKRP")
-    if precision == "fx20":
-        if not isinstance(X, FX20):
-            raise TypeError("the fx20 form takes X from to_fx20()")
-    else:
-        _check_tensor(X, _X_DTYPE[precision], "X")
+    _x_check(X, precision)
+    udt = _u_dtype_for(precision, U)
     R = U[0].shape[1]
     for k, u in enumerate(U):
-        _check_tensor(u, _U_DTYPE[precision], f"U[{k}]")
+        _check_tensor(u, udt, f"U[{k}]")
     out_dtype = out_dtype or (out.dtype if out is not None else _default_out_dtype(precision))
     if out is None:
         out = torch.empty((X.shape[sp.free_mode], R), dtype=out_dtype, device=X.device)
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
-    o = _opts(precision, out_dtype, None, 0, 0, None)
+    o = _opts(precision, out_dtype, None, 0, 0, None, tol=tol, x_dtype=_storage_code(X), u_dtype=_DT_CODE[udt])
     rep = Report()
     fn = _lib.load().deinsum_tune_batch_mttkrp if batched else _lib.load().deinsum_tune_mttkrp
     xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
@@ -250,20 +293,23 @@ def tune_entries() -> int:
 
 
 def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None,
-         variant=None, tune_reps=0):
+         variant=None, tune_reps=0, tol=None):
     """Mode-n TTMc.  ``U`` lists the factor operands in the spec's operand order.
     ``variant`` picks a compiled fused kernel for the ranks (None = the autotuned one if
     cached, else the default); ``tune_reps`` > 0 autotunes first (``out`` is overwritten)."""
     sp = _spec(spec)
     if sp.kind != TTMC:
         raise ValueError("spec is not a TTMc")
-    _check_tensor(X, _X_DTYPE[precision], "X")
+    if precision == "fx20" or isinstance(X, FX20):
+        raise TypeError("TTMc has no FX20 form")
+    _x_check(X, precision)
+    udt = _u_dtype_for(precision, U)
     if X.dim() != sp.order or len(U) != sp.n_factors:
         raise ValueError("operand count or order does not match the spec")
     ranks = []
     shape = list(X.shape)
     for k, u in enumerate(U):
-        _check_tensor(u, _U_DTYPE[precision], f"U[{k}]")
+        _check_tensor(u, udt, f"U[{k}]")
         m = sp.factor_mode[k]
         if u.dim() != 2 or u.shape[0] != X.shape[m]:
             raise ValueError(f"factor {k} must be {X.shape[m]} x R_{m}")
@@ -277,7 +323,8 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
         if list(out.shape) != shape:
             raise ValueError("out has the wrong shape")
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
-    o = _opts(precision, out_dtype, workspace, 0 if variant is None else int(variant) + 1, 0, report)
+    o = _opts(precision, out_dtype, workspace, 0 if variant is None else int(variant) + 1, 0, report, tol=tol,
+              x_dtype=_storage_code(X), u_dtype=_DT_CODE[udt])
     if tune_reps:
         rep = Report()
         with torch.cuda.device(X.device):
@@ -290,27 +337,25 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
     return out
 
 
-def mttkrp_mm(spec, X, U, C, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None):
+def mttkrp_mm(spec, X, U, C, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None,
+              tol=None):
     """MTTKRP followed by a matrix product, e.g. "ijk,ja,ka,al->il" (the paper's running
     example): ``U`` lists the MTTKRP factor operands, ``C`` is the R x L matrix."""
     sp = _spec(spec)
     if sp.kind != MTTKRP_MM:
         raise ValueError("spec is not an MTTKRP-GEMM chain")
-    if precision == "fx20":
-        if not isinstance(X, FX20):
-            raise TypeError("the fx20 form takes X from to_fx20()")
-    else:
-        _check_tensor(X, _X_DTYPE[precision], "X")
+    _x_check(X, precision)
+    udt = _u_dtype_for(precision, U)
     if X.dim() != sp.order or len(U) != sp.n_factors:
         raise ValueError("operand count or order does not match the spec")
     R = None
     for k, u in enumerate(U):
-        _check_tensor(u, _U_DTYPE[precision], f"U[{k}]")
+        _check_tensor(u, udt, f"U[{k}]")
         m = sp.factor_mode[k]
         if u.dim() != 2 or u.shape[0] != X.shape[m] or (R is not None and u.shape[1] != R):
             raise ValueError(f"factor {k} must be {X.shape[m]} x R with one shared R")
         R = u.shape[1]
-    _check_tensor(C, _U_DTYPE[precision], "C")
+    _check_tensor(C, udt, "C")
     if C.dim() != 2 or C.shape[0] != R:
         raise ValueError("C must be R x L")
     L = C.shape[1]
@@ -323,7 +368,8 @@ def mttkrp_mm(spec, X, U, C, precision="fp64", out=None, out_dtype=None, workspa
         if tuple(out.shape) != (X.shape[n], L):
             raise ValueError("out has the wrong shape")
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
-    o = _opts(precision, out_dtype, workspace, 0, 0, report)
+    o = _opts(precision, out_dtype, workspace, 0, 0, report, tol=tol, x_dtype=_storage_code(X),
+              u_dtype=_DT_CODE[udt])
     xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
     with torch.cuda.device(X.device):
         _lib.check(_lib.load().deinsum_mttkrp_mm(ctypes.byref(sp), _i64(X.shape), int(R), int(L),
@@ -341,6 +387,68 @@ def einsum(spec: str, X, *U, precision="fp64", out=None, **kw):
     if sp.kind == MTTKRP_MM:
         return mttkrp_mm(sp, X, list(U[:-1]), U[-1], precision=precision, out=out, **kw)
     return ttmc(sp, X, list(U), precision=precision, out=out, **kw)
+
+
+def estimate_error(spec, dims, ranks, precision="fp64", X=None, tol=None, x_dtype=None, u_dtype=None, stream=None):
+    """deinsum_estimate_error: (form, estimated normwise relative error).  With
+    precision="auto" the form is the one AUTO picks for ``tol`` and the storage codes
+    ``x_dtype`` / ``u_dtype`` (F64, F32, BF16, FX20_STORAGE); X (an FX20 buffer) is
+    needed only for the FX20 form, whose header holds its storage error."""
+    sp = _spec(spec)
+    o = _opts(precision, torch.float64 if precision in ("fp64", "auto") else torch.float32, None, 0, 0, None,
+              tol=tol, x_dtype=x_dtype, u_dtype=u_dtype)
+    p = ctypes.c_int32(-1)
+    e = ctypes.c_double(0)
+    xptr = None
+    if X is not None:
+        xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
+    _lib.check(_lib.load().deinsum_estimate_error(ctypes.byref(sp), _i64(dims), _i64(ranks), xptr, ctypes.byref(o),
+                                                  ctypes.byref(p), ctypes.byref(e),
+                                                  _stream(stream) if X is not None else None))
+    return PRECISION_NAMES[p.value], e.value
+
+
+def choose_storage(spec, dims, ranks, tol, max_abs=0.0, rms=0.0):
+    """deinsum_choose_storage: (storage, form, estimate) -- the cheapest storage of X
+    ("bf16", "fx20", "f32", "f64") with a form whose estimated error is within ``tol``.
+    FX20 is considered only given max_abs and rms of X (tensor_stats)."""
+    sp = _spec(spec)
+    x = ctypes.c_int32(-1)
+    p = ctypes.c_int32(-1)
+    e = ctypes.c_double(0)
+    _lib.check(_lib.load().deinsum_choose_storage(ctypes.byref(sp), _i64(dims), _i64(ranks), float(tol),
+                                                  float(max_abs), float(rms), ctypes.byref(x), ctypes.byref(p),
+                                                  ctypes.byref(e)))
+    return STORAGE_NAMES[x.value], PRECISION_NAMES[p.value], e.value
+
+
+def tensor_stats(X: torch.Tensor, stream=None):
+    """(max |x|, rms) of a device tensor, computed on the device (synchronising)."""
+    if X.device.type != "cuda" or not X.is_contiguous() or X.dtype not in _DT_CODE:
+        raise TypeError("tensor_stats needs a contiguous float64 / float32 / bfloat16 device tensor")
+    mx = ctypes.c_double(0)
+    rms = ctypes.c_double(0)
+    with torch.cuda.device(X.device):
+        _lib.check(_lib.load().deinsum_tensor_stats(ctypes.c_void_p(X.data_ptr()), _DT_CODE[X.dtype], X.numel(),
+                                                    ctypes.byref(mx), ctypes.byref(rms), _stream(stream)))
+    return mx.value, rms.value
+
+
+def prepare(X: torch.Tensor, spec, ranks, tol, stream=None):
+    """Store an FP64 device tensor for a tolerance: measures max |x| and rms, asks
+    choose_storage for the cheapest storage whose form meets ``tol`` on this problem,
+    and returns X in it (X itself for F64; a new BF16 / FP32 tensor or FX20 buffer
+    otherwise) with the storage name.  Pass the result with precision="auto", tol=tol."""
+    if X.dtype != torch.float64:
+        raise TypeError("prepare takes the FP64 tensor")
+    mx, rms = tensor_stats(X, stream)
+    storage, _, _ = choose_storage(spec, X.shape, ranks, tol, mx, rms)
+    if storage == "f64":
+        return X, storage
+    if storage == "fx20":
+        return to_fx20(X, stream), storage
+    dst = torch.empty(X.shape, dtype=torch.float32 if storage == "f32" else torch.bfloat16, device=X.device)
+    return convert(X, dst, stream), storage
 
 
 def synth_fill(t: torch.Tensor, seed: int, dist: str = "uniform", offset: int = 0, stream=None):
@@ -499,8 +607,13 @@ class Server:
             t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), m.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         self._n += len(a)
 
-    def drain(self):
-        _lib.check(_lib.load().deinsum_server_drain(self._h))
+    def drain(self, check=True):
+        """Wait until every submitted request has finished.  With check=True a failed
+        request raises DeinsumError (after all have finished); poll() gives each one's state."""
+        st = _lib.load().deinsum_server_drain(self._h)
+        if check:
+            _lib.check(st)
+        return st
 
     def results(self):
         """(arrival, done, epoch) numpy arrays over all submitted requests (after drain)."""
@@ -512,6 +625,19 @@ class Server:
             self._h, n, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
             done.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ep.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
         return arr, done, ep
+
+    REQUEST_STATES = {0: "done", 1: "pending", 2: "running"}
+
+    def poll(self, request_id: int) -> dict:
+        """State of one request: status ("done", "pending", "running", or the name of the
+        error it failed with), its raw code, flags ({"regularised"} when the factor update
+        needed the pivot floor) and completion time (seconds since start, -1 before)."""
+        st, fl, done = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _lib.check(_lib.load().deinsum_server_poll(self._h, int(request_id), ctypes.byref(st), ctypes.byref(fl),
+                                                   ctypes.byref(done)))
+        name = self.REQUEST_STATES.get(st.value) or _lib.STATUS_NAMES.get(st.value, str(st.value))
+        flags = {"regularised"} if fl.value & 1 else set()
+        return {"status": name, "code": st.value, "flags": flags, "done": done.value}
 
     def stats(self) -> dict:
         c, e, mb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

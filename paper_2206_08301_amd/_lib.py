@@ -54,6 +54,8 @@ class Report(ctypes.Structure):
         ("alg_flops", ctypes.c_double),
         ("plan_name", ctypes.c_char * 48),
         ("tuned_us", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("est_err", ctypes.c_double),
     ]
 
 
@@ -77,6 +79,10 @@ class Opts(ctypes.Structure):
         ("plan_hint", ctypes.c_int32),
         ("split_hint", ctypes.c_int32),
         ("report", ctypes.POINTER(Report)),
+        ("tol", ctypes.c_double),
+        ("x_dtype", ctypes.c_int32),
+        ("u_dtype", ctypes.c_int32),
+        ("deterministic", ctypes.c_int32),
     ]
 
 
@@ -91,7 +97,8 @@ EXPORTS = (
     "deinsum_server_stats", "deinsum_server_destroy", "deinsum_tune_mttkrp", "deinsum_tune_batch_mttkrp",
     "deinsum_tune_load", "deinsum_tune_save", "deinsum_tune_clear", "deinsum_tune_entries",
     "deinsum_fx20_size", "deinsum_fx20_encode", "deinsum_tune_ttmc", "deinsum_mttkrp_mm",
-    "deinsum_mttkrp_noalloc",
+    "deinsum_mttkrp_noalloc", "deinsum_estimate_error", "deinsum_choose_storage", "deinsum_tensor_stats",
+    "deinsum_server_poll",
 )
 
 _lib = None
@@ -171,6 +178,8 @@ def load():
     lib.deinsum_server_drain.restype = ctypes.c_int
     lib.deinsum_server_results.argtypes = [vp, ctypes.c_int64, f64p, f64p, i64p]
     lib.deinsum_server_results.restype = ctypes.c_int
+    lib.deinsum_server_poll.argtypes = [vp, ctypes.c_int64, i32p, i32p, f64p]
+    lib.deinsum_server_poll.restype = ctypes.c_int
     lib.deinsum_server_stats.argtypes = [vp, i64p, i64p, i64p]
     lib.deinsum_server_stats.restype = ctypes.c_int
     lib.deinsum_server_destroy.argtypes = [vp]
@@ -194,6 +203,16 @@ def load():
     lib.deinsum_fx20_size.restype = ctypes.c_int
     lib.deinsum_fx20_encode.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, ctypes.c_size_t, vp]
     lib.deinsum_fx20_encode.restype = ctypes.c_int
+    lib.deinsum_estimate_error.argtypes = [ctypes.POINTER(Spec), i64p, i64p, vp, ctypes.POINTER(Opts),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double), vp]
+    lib.deinsum_estimate_error.restype = ctypes.c_int
+    lib.deinsum_choose_storage.argtypes = [ctypes.POINTER(Spec), i64p, i64p, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]
+    lib.deinsum_choose_storage.restype = ctypes.c_int
+    lib.deinsum_tensor_stats.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double), vp]
+    lib.deinsum_tensor_stats.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -11,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "accuracy.h"
 #include "internal.h"
 #include "kernels.h"
 #include "krp.h"
@@ -28,8 +30,6 @@ deinsum_status check_launch(const char *what)
         return fail(DEINSUM_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
     return DEINSUM_OK;
 }
-
-namespace {
 
 // ------------------------------------------------------------------ workspace pool
 // One grow-only device buffer per device.  Calls that use the pool must be
@@ -69,6 +69,8 @@ deinsum_status pool_get(size_t bytes, void **out)
     *out = p.ptr;
     return DEINSUM_OK;
 }
+
+namespace {
 
 // ------------------------------------------------------------------ no-alloc scratch
 // Workspace of deinsum_mttkrp_noalloc: a fixed device array that every device holding
@@ -121,7 +123,7 @@ deinsum_status resolve_opts(const deinsum_opts *in, deinsum_opts *o)
 {
     deinsum_opts_init(o);
     if (in) *o = *in;
-    if (o->precision < DEINSUM_PREC_FP64 || o->precision > DEINSUM_PREC_FX20)
+    if (o->precision < DEINSUM_PREC_FP64 || o->precision > DEINSUM_PREC_AUTO)
         return fail(DEINSUM_ERR_INVALID_ARG, "opts.precision is not a deinsum_precision");
     if (o->out_dtype != DEINSUM_F64 && o->out_dtype != DEINSUM_F32)
         return fail(DEINSUM_ERR_INVALID_ARG, "opts.out_dtype must be DEINSUM_F64 or DEINSUM_F32");
@@ -129,8 +131,51 @@ deinsum_status resolve_opts(const deinsum_opts *in, deinsum_opts *o)
         return fail(DEINSUM_ERR_INVALID_ARG, "the FP64 form writes an F64 output");
     if (o->workspace == nullptr && o->workspace_bytes != 0)
         return fail(DEINSUM_ERR_INVALID_ARG, "opts.workspace_bytes set without a workspace");
+    if (o->deterministic != 0 && o->deterministic != 1)
+        return fail(DEINSUM_ERR_INVALID_ARG, "opts.deterministic must be 0 or 1");
+    if (o->precision == DEINSUM_PREC_AUTO) {
+        if (!(o->tol > 0)) return fail(DEINSUM_ERR_INVALID_ARG, "DEINSUM_PREC_AUTO needs opts.tol > 0");
+        if (o->x_dtype < DEINSUM_F64 || o->x_dtype > DEINSUM_FX20)
+            return fail(DEINSUM_ERR_INVALID_ARG, "opts.x_dtype is not a deinsum_dtype");
+        if (o->u_dtype != DEINSUM_F64 && o->u_dtype != DEINSUM_F32)
+            return fail(DEINSUM_ERR_INVALID_ARG, "opts.u_dtype must be DEINSUM_F64 or DEINSUM_F32");
+    }
     return DEINSUM_OK;
 }
+
+// ------------------------------------------------------------------ form choice (AUTO)
+// Forms reading X stored as x_dtype with factors of u_dtype, cheapest first.
+int form_candidates(int kind, int x_dtype, int u_dtype, int out[2])
+{
+    if (u_dtype == DEINSUM_F64) {
+        if (x_dtype != DEINSUM_F64) return 0;
+        out[0] = P_FP64;
+        return 1;
+    }
+    switch (x_dtype) {
+    case DEINSUM_F32:
+        if (kind == DEINSUM_TTMC) {
+            out[0] = P_FP32;
+            return 1;
+        }
+        out[0] = P_BF16X3;
+        out[1] = P_FP32;
+        return 2;
+    case DEINSUM_BF16: out[0] = P_BF16; return 1;
+    case DEINSUM_FX20:
+        if (kind == DEINSUM_TTMC) return 0;
+        out[0] = P_FX20;
+        return 1;
+    default: return 0;
+    }
+}
+
+const char *form_name(int p)
+{
+    static const char *names[] = {"FP64", "FP32", "BF16", "BF16X3", "FX20", "AUTO"};
+    return (p >= 0 && p <= 5) ? names[p] : "?";
+}
+
 
 deinsum_status check_dims(const deinsum_spec *spec, const int64_t *dims)
 {
@@ -261,6 +306,117 @@ deinsum_status prepare_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     return plan_mttkrp(pb, o.plan_hint, o.split_hint, &call->plan);
 }
 
+// Estimated error (accuracy.cpp) of the MTTKRP of this problem in form `prec`: the FP32
+// chain length is the plan's slice of the matrix-core mode.  X is read only for FX20
+// (its header, synchronising `s`); NULL there means the storage error is not known.
+deinsum_status mttkrp_estimate(const deinsum_spec *spec, const int64_t *dims, int64_t R, int prec, const void *X,
+                               hipStream_t s, double *est)
+{
+    deinsum_spec ms = *spec;
+    ms.kind = DEINSUM_MTTKRP;
+    deinsum_opts o;
+    deinsum_opts_init(&o);
+    o.precision = prec;
+    o.out_dtype = prec == P_FP64 ? DEINSUM_F64 : DEINSUM_F32;
+    ErrInputs in;
+    in.prec = prec;
+    in.order = spec->order;
+    double nx = 1;
+    bool empty = false;
+    for (int m = 0; m < spec->order; ++m) {
+        nx *= static_cast<double>(dims[m]);
+        empty |= dims[m] == 0;
+    }
+    if (empty) {  // an empty sum (M = 0) or an empty output: exact
+        *est = 0;
+        return DEINSUM_OK;
+    }
+    in.L = nx / static_cast<double>(dims[spec->free_mode]);
+    if (prec != P_FP64) {
+        MttkrpCall c{};
+        if (deinsum_status st = prepare_mttkrp(&ms, dims, R, o, &c)) return st;
+        in.k32 = c.plan.slice;
+    }
+    if (prec == P_FX20 && X) {
+        double e = 0;
+        if (deinsum_status st = fx20_storage_error(X, static_cast<int64_t>(nx), s, &e)) return st;
+        in.x_storage = e;
+    }
+    *est = estimate_error(in);
+    return DEINSUM_OK;
+}
+
+// The same for TTMc: the fused pass sums over modes a and c in FP32 in the reduced forms.
+double ttmc_estimate(const deinsum_spec *spec, const int64_t *dims, int prec)
+{
+    const int N = spec->order, n = spec->free_mode;
+    ErrInputs in;
+    in.prec = prec;
+    in.order = N;
+    double nx = 1;
+    for (int m = 0; m < N; ++m) nx *= static_cast<double>(dims[m]);
+    if (nx == 0) return 0;
+    in.L = nx / static_cast<double>(dims[n]);
+    if (N == 2) {
+        in.k32 = static_cast<double>(dims[1 - n]);
+    } else {
+        const int c = N - 1, a = (n == N - 1 || N - 2 != n) ? N - 2 : N - 3;
+        in.k32 = static_cast<double>(dims[a]) + (n == N - 1 ? 0.0 : static_cast<double>(dims[c]));
+    }
+    return estimate_error(in);
+}
+
+// Resolves opts->precision when it is DEINSUM_PREC_AUTO: the cheapest form reading
+// opts->x_dtype / u_dtype storage whose estimate is at most opts->tol.  Without X
+// (workspace queries) the FX20 form is taken unchecked: it is the only form reading
+// that storage.  *est receives the chosen form's estimate (for an explicit form too
+// when want_est; NaN when it was not computed).
+deinsum_status resolve_form(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, const void *X,
+                            deinsum_opts *o, bool want_est, hipStream_t s, double *est)
+{
+    *est = NAN;
+    if (deinsum_status st = check_dims(spec, dims)) return st;
+    if (!ranks) return fail(DEINSUM_ERR_INVALID_ARG, "null ranks");
+    const bool ttmc = spec->kind == DEINSUM_TTMC;
+    auto estimate = [&](int prec, const void *x, double *e) -> deinsum_status {
+        if (ttmc) {
+            *e = ttmc_estimate(spec, dims, prec);
+            return DEINSUM_OK;
+        }
+        return mttkrp_estimate(spec, dims, ranks[0], prec, x, s, e);
+    };
+    if (o->precision != DEINSUM_PREC_AUTO) {
+        if (want_est) return estimate(o->precision, X, est);
+        return DEINSUM_OK;
+    }
+    int cand[2];
+    const int nc = form_candidates(spec->kind, o->x_dtype, o->u_dtype, cand);
+    if (nc == 0)
+        return fail(DEINSUM_ERR_UNSUPPORTED, std::string("DEINSUM_PREC_AUTO: no compiled ") +
+                                                 (ttmc ? "TTMc" : "MTTKRP") + " form reads this X / factor storage");
+    double best = INFINITY;
+    for (int i = 0; i < nc; ++i) {
+        double e = 0;
+        if (cand[i] == P_FX20 && !X) {
+            o->precision = P_FX20;
+            return DEINSUM_OK;
+        }
+        if (deinsum_status st = estimate(cand[i], X, &e)) return st;
+        if (e <= o->tol) {
+            o->precision = cand[i];
+            *est = e;
+            return DEINSUM_OK;
+        }
+        best = std::min(best, e);
+    }
+    char msg[192];
+    std::snprintf(msg, sizeof(msg),
+                  "DEINSUM_PREC_AUTO: no form reading this storage meets tol %.3g (best estimate %.3g); "
+                  "store X for the tolerance (deinsum_choose_storage)",
+                  o->tol, best);
+    return fail(DEINSUM_ERR_UNSUPPORTED, msg);
+}
+
 deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
 {
     const MttkrpProblem &pb = c.pb;
@@ -354,10 +510,12 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
 // merged: the last two modes ran as one (" m2" ends the plan name); ttmc_variant >= 0:
 // the call ran through the fused TTMc pass with that plan_hint (geometry fields zero).
 void fill_report(deinsum_report *r, const MttkrpProblem &pb, const MttkrpPlan &p, size_t ws_bytes,
-                 bool merged = false, int ttmc_variant = -1)
+                 bool merged = false, int ttmc_variant = -1, double est = NAN)
 {
     if (!r) return;
     std::memset(r, 0, sizeof(*r));
+    r->precision = pb.prec;
+    r->est_err = est;
     r->plan_id = p.family;
     r->tile_m = p.tile_rows;
     r->tile_k = p.slice;
@@ -423,6 +581,10 @@ void deinsum_opts_init(deinsum_opts *opts)
     std::memset(opts, 0, sizeof(*opts));
     opts->precision = DEINSUM_PREC_FP64;
     opts->out_dtype = DEINSUM_F64;
+    opts->tol = 1e-12;
+    opts->x_dtype = DEINSUM_F64;
+    opts->u_dtype = DEINSUM_F64;
+    opts->deterministic = 1;
 }
 
 const char *deinsum_version(void) { return "deinsum-mi355x 0.1 (gfx950)"; }
@@ -435,6 +597,10 @@ deinsum_status deinsum_workspace_size(const deinsum_spec *spec, const int64_t *d
     if (!bytes || !ranks) return fail(DEINSUM_ERR_INVALID_ARG, "null ranks or bytes");
     deinsum_opts o;
     if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (o.precision == DEINSUM_PREC_AUTO) {
+        double est = 0;
+        if (deinsum_status st = resolve_form(spec, dims, ranks, nullptr, &o, false, nullptr, &est)) return st;
+    }
     if (spec && spec->kind == DEINSUM_TTMC) return ttmc_workspace_size(spec, dims, ranks, o, bytes);
     if (spec && spec->kind == DEINSUM_MTTKRP_MM) {  // the MTTKRP's, then M in FP64
         deinsum_spec ms = *spec;
@@ -463,6 +629,14 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     if (R < 1 || R > DEINSUM_MAX_RANK)
         return fail(DEINSUM_ERR_SHAPE, "rank must be 1.." + std::to_string(DEINSUM_MAX_RANK));
     if (!U || !M) return fail(DEINSUM_ERR_INVALID_ARG, "null factor table or output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double est = NAN;
+    if (o.precision == DEINSUM_PREC_AUTO || o.report) {
+        const int64_t r1[1] = {R};
+        if (deinsum_status st = resolve_form(spec, dims, r1, X, &o, o.report != nullptr, s, &est)) return st;
+        if (o.precision == DEINSUM_PREC_FP64 && o.out_dtype != DEINSUM_F64)
+            return fail(DEINSUM_ERR_INVALID_ARG, "the FP64 form writes an F64 output");
+    }
     const int N = spec->order, n = spec->free_mode;
     int64_t nx = 1;
     bool empty = false;
@@ -487,7 +661,6 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
         reinterpret_cast<uintptr_t>(X) % (fx20 ? 256 : xb) != 0)
         return fail(DEINSUM_ERR_INVALID_ARG, fx20 ? "an FX20 X buffer must be 256-byte aligned"
                                                   : "X and M must be aligned to their element size");
-    hipStream_t s = static_cast<hipStream_t>(stream);
     if (dims[n] == 0) { clear_error(); return DEINSUM_OK; }
     if (empty) {  // an empty sum: M = 0
         if (deinsum_status st = zero_bytes(M, static_cast<int64_t>(mbytes), s)) return st;
@@ -504,7 +677,7 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     } else if (deinsum_status st = pool_get(call_workspace(c), &ws)) {
         return st;
     }
-    fill_report(o.report, c.orig, c.plan, call_workspace(c), c.merged, c.via_ttmc ? c.ttmc_variant : -1);
+    fill_report(o.report, c.orig, c.plan, call_workspace(c), c.merged, c.via_ttmc ? c.ttmc_variant : -1, est);
     if (deinsum_status st = run_mttkrp(c, ws, s)) return st;
     clear_error();
     return DEINSUM_OK;
@@ -546,6 +719,14 @@ deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, 
         return fail(DEINSUM_ERR_SHAPE, "rank must be 1.." + std::to_string(DEINSUM_MAX_RANK));
     if (L < 1 || L > 4096) return fail(DEINSUM_ERR_SHAPE, "chain width L must be 1..4096");
     if (!C || !Y) return fail(DEINSUM_ERR_INVALID_ARG, "null C or Y");
+    if (o.precision == DEINSUM_PREC_AUTO) {  // the MTTKRP's form; the product is summed in FP64
+        const int64_t r1[1] = {R};
+        double est = 0;
+        if (deinsum_status st = resolve_form(spec, dims, r1, X, &o, false, static_cast<hipStream_t>(stream), &est))
+            return st;
+        if (o.precision == DEINSUM_PREC_FP64 && o.out_dtype != DEINSUM_F64)
+            return fail(DEINSUM_ERR_INVALID_ARG, "the FP64 form writes an F64 output");
+    }
     const int n = spec->free_mode;
     const size_t cb = u_elem_bytes(o.precision), yb = dtype_bytes(o.out_dtype);
     const size_t ybytes = static_cast<size_t>(dims[n] * L) * yb;
@@ -597,6 +778,13 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
     if (reps < 1 || reps > 1000) return fail(DEINSUM_ERR_INVALID_ARG, "tune: reps must be 1..1000");
     deinsum_opts o;
     if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (o.precision == DEINSUM_PREC_AUTO) {
+        const int64_t r1[1] = {R};
+        double est = 0;
+        if (!spec) return fail(DEINSUM_ERR_INVALID_ARG, "null spec");
+        if (deinsum_status st = resolve_form(spec, dims, r1, X, &o, false, static_cast<hipStream_t>(stream), &est))
+            return st;
+    }
     o.plan_hint = 0;
     o.split_hint = 0;
     o.workspace = nullptr;
@@ -700,6 +888,12 @@ deinsum_status deinsum_tune_ttmc(const deinsum_spec *spec, const int64_t *dims, 
     if (reps < 1 || reps > 1000) return fail(DEINSUM_ERR_INVALID_ARG, "tune_ttmc: reps must be 1..1000");
     deinsum_opts o;
     if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (o.precision == DEINSUM_PREC_AUTO) {
+        double est = 0;
+        if (!spec) return fail(DEINSUM_ERR_INVALID_ARG, "null spec");
+        if (deinsum_status st = resolve_form(spec, dims, ranks, X, &o, false, static_cast<hipStream_t>(stream), &est))
+            return st;
+    }
     o.workspace = nullptr;
     o.workspace_bytes = 0;
     o.report = nullptr;
@@ -754,6 +948,15 @@ deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const
     if (deinsum_status st = resolve_opts(opts, &o)) return st;
     if (deinsum_status st = check_dims(spec, dims)) return st;
     if (spec->kind != DEINSUM_TTMC) return fail(DEINSUM_ERR_INVALID_ARG, "spec is not a TTMc");
+    if (!ranks) return fail(DEINSUM_ERR_INVALID_ARG, "null ranks");
+    double est = NAN;
+    if (o.precision == DEINSUM_PREC_AUTO || o.report) {
+        if (deinsum_status st = resolve_form(spec, dims, ranks, X, &o, o.report != nullptr,
+                                             static_cast<hipStream_t>(stream), &est))
+            return st;
+        if (o.precision == DEINSUM_PREC_FP64 && o.out_dtype != DEINSUM_F64)
+            return fail(DEINSUM_ERR_INVALID_ARG, "the FP64 form writes an F64 output");
+    }
     void *ws = o.workspace;
     size_t need = 0;
     if (deinsum_status st = ttmc_workspace_size(spec, dims, ranks, o, &need)) return st;
@@ -765,8 +968,111 @@ deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const
     }
     if (deinsum_status st = run_ttmc(spec, dims, ranks, X, U, Y, o, ws, need, static_cast<hipStream_t>(stream)))
         return st;
+    if (o.report) {
+        deinsum_report *r = o.report;
+        std::memset(r, 0, sizeof(*r));
+        r->precision = o.precision;
+        r->est_err = est;
+        r->workspace_bytes = need;
+        double nx = 1, ny = 1, fac = 0;
+        for (int m = 0; m < spec->order; ++m) {
+            nx *= static_cast<double>(dims[m]);
+            if (m == spec->free_mode) {
+                ny *= static_cast<double>(dims[m]);
+            } else {
+                const double rm = static_cast<double>(ranks[spec->operand_of_mode[m]]);
+                ny *= rm;
+                fac += static_cast<double>(dims[m]) * rm;
+            }
+        }
+        r->alg_bytes = nx * static_cast<double>(x_elem_bytes(o.precision)) +
+                       fac * static_cast<double>(u_elem_bytes(o.precision)) + ny * dtype_bytes(o.out_dtype);
+        std::snprintf(r->plan_name, sizeof(r->plan_name), "ttmc %s", form_name(o.precision));
+    }
     clear_error();
     return DEINSUM_OK;
+}
+
+deinsum_status deinsum_estimate_error(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,
+                                      const void *X, const deinsum_opts *opts, int32_t *precision, double *est_err,
+                                      void *stream)
+{
+    if (!precision || !est_err) return fail(DEINSUM_ERR_INVALID_ARG, "estimate_error: null output");
+    deinsum_opts o;
+    if (deinsum_status st = resolve_opts(opts, &o)) return st;
+    if (!spec) return fail(DEINSUM_ERR_INVALID_ARG, "null spec");
+    if (o.precision == DEINSUM_PREC_FX20 && !X)
+        return fail(DEINSUM_ERR_INVALID_ARG, "estimate_error: the FX20 estimate reads X's header");
+    if (o.precision == DEINSUM_PREC_AUTO && o.x_dtype == DEINSUM_FX20 && !X)
+        return fail(DEINSUM_ERR_INVALID_ARG, "estimate_error: the FX20 estimate reads X's header");
+    if (spec->kind == DEINSUM_TTMC && o.precision != DEINSUM_PREC_AUTO && o.precision != DEINSUM_PREC_FP64 &&
+        o.precision != DEINSUM_PREC_FP32 && o.precision != DEINSUM_PREC_BF16)
+        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64, FP32 and BF16 forms");
+    double est = NAN;
+    if (deinsum_status st = resolve_form(spec, dims, ranks, X, &o, true, static_cast<hipStream_t>(stream), &est))
+        return st;
+    *precision = o.precision;
+    *est_err = est;
+    clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_choose_storage(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, double tol,
+                                      double max_abs, double rms, int32_t *x_dtype, int32_t *precision,
+                                      double *est_err)
+{
+    if (!spec || !dims || !ranks || !x_dtype || !precision || !est_err)
+        return fail(DEINSUM_ERR_INVALID_ARG, "choose_storage: null argument");
+    if (!(tol > 0)) return fail(DEINSUM_ERR_INVALID_ARG, "choose_storage: tol must be > 0");
+    if (deinsum_status st = check_dims(spec, dims)) return st;
+    const bool ttmc = spec->kind == DEINSUM_TTMC;
+    // (storage, form), cheapest storage first; within F32 the faster form first.
+    const int order_x[] = {DEINSUM_BF16, DEINSUM_FX20, DEINSUM_F32, DEINSUM_F32, DEINSUM_F64};
+    const int order_p[] = {P_BF16, P_FX20, P_BF16X3, P_FP32, P_FP64};
+    double best = INFINITY;
+    for (int i = 0; i < 5; ++i) {
+        const int p = order_p[i];
+        if (ttmc && (p == P_FX20 || p == P_BF16X3)) continue;
+        double e = 0;
+        if (p == P_FX20) {
+            const double dx = fx20_storage_model(max_abs, rms);
+            if (!(dx >= 0)) continue;  // no statistics of X: FX20 not considered
+            ErrInputs in;
+            in.prec = P_FX20;
+            in.order = spec->order;
+            double nx = 1;
+            for (int m = 0; m < spec->order; ++m) nx *= static_cast<double>(dims[m]);
+            in.L = nx > 0 ? nx / static_cast<double>(dims[spec->free_mode]) : 1;
+            deinsum_spec ms = *spec;
+            ms.kind = DEINSUM_MTTKRP;
+            deinsum_opts o;
+            deinsum_opts_init(&o);
+            o.precision = P_FX20;
+            o.out_dtype = DEINSUM_F32;
+            MttkrpCall c{};
+            if (nx > 0) {
+                if (deinsum_status st = prepare_mttkrp(&ms, dims, ranks[0], o, &c)) return st;
+                in.k32 = c.plan.slice;
+            }
+            in.x_storage = dx;
+            e = nx > 0 ? estimate_error(in) : 0.0;
+        } else if (ttmc) {
+            e = ttmc_estimate(spec, dims, p);
+        } else if (deinsum_status st = mttkrp_estimate(spec, dims, ranks[0], p, nullptr, nullptr, &e)) {
+            return st;
+        }
+        if (e <= tol) {
+            *x_dtype = order_x[i];
+            *precision = p;
+            *est_err = e;
+            clear_error();
+            return DEINSUM_OK;
+        }
+        best = std::min(best, e);
+    }
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "choose_storage: no storage meets tol %.3g (best estimate %.3g)", tol, best);
+    return fail(DEINSUM_ERR_UNSUPPORTED, msg);
 }
 
 deinsum_status deinsum_synth_fill(void *X, int32_t dtype, int64_t count, uint64_t seed, int64_t offset, int32_t dist,

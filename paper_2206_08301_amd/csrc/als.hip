@@ -88,8 +88,10 @@ __device__ void als_solve_block(const AlsJob &j, int64_t blk)
         diag_max = mx;
     }
     __syncthreads();
-    // A pivot below this floor means V is (numerically) singular; the floor acts as a ridge.
+    // A pivot below this floor means V is (numerically) singular; the floor acts as a ridge
+    // and the job's first workgroup reports it through j.flag.
     const double floor_p = diag_max > 0.0 ? 1e-14 * diag_max : 1e-300;
+    bool floored = false;
     // In-place Gauss-Jordan inversion, one pivot per step.
     for (int k = 0; k < R; ++k) {
         if (tid < R) {
@@ -98,7 +100,10 @@ __device__ void als_solve_block(const AlsJob &j, int64_t blk)
         }
         __syncthreads();
         double p = rowk[k];
-        if (!(p > floor_p)) p = floor_p;
+        if (!(p > floor_p)) {
+            p = floor_p;
+            floored = true;
+        }
         const double inv = 1.0 / p;
         for (int e = tid; e < R * R; e += kAlsThreads) {
             const int i = e / R, c = e % R;
@@ -110,6 +115,7 @@ __device__ void als_solve_block(const AlsJob &j, int64_t blk)
         }
         __syncthreads();
     }
+    if (blk == 0 && tid == 0 && j.flag) __atomic_store_n(j.flag, floored ? 1 : 0, __ATOMIC_RELAXED);
     // Rows of the solution: Xs = M V^{-1}, a 4x4 register tile per thread.
     const int rg = tid >> 4, cg = tid & 15;
     double acc[4][4];
@@ -167,6 +173,7 @@ __device__ void als_finish_job(const AlsJob &j)
         double s = 0.0;
         for (int64_t b = 0; b < nb; ++b) s += j.Gp[(b * R + tid) * R + tid];
         d[tid] = s > 0.0 ? 1.0 / sqrt(s) : 1.0;
+        if (j.lambda) j.lambda[tid] = sqrt(s);
     }
     __syncthreads();
     double *Gn = j.G + static_cast<int64_t>(j.mode) * R * R;

@@ -14,6 +14,15 @@ void set_error(const std::string &msg);
 void clear_error();
 deinsum_status fail(deinsum_status st, const std::string &msg);
 
+// The library's grow-only device workspace of the current device (abi.cpp).  Work
+// that uses it must be ordered with every other user (one stream, or synchronised).
+deinsum_status pool_get(size_t bytes, void **out);
+
+// Normwise relative storage error ||X - X_stored|| / ||X|| recorded in the header of
+// an FX20 buffer of `count` elements (fx20.hip).  Copies the header to the host and
+// synchronises `stream`.
+deinsum_status fx20_storage_error(const void *X, int64_t count, void *stream, double *err);
+
 // Einsum parser (parse.cpp).
 deinsum_status parse_spec(const char *text, deinsum_spec *out);
 

@@ -53,6 +53,9 @@ struct Fx20Header {
     int32_t exp2;     // X ~ (256 h + l) * 2^exp2
     int64_t count;
     double max_abs;   // max |X| before encoding
+    // Integer sums, exact and independent of summation order:
+    uint64_t sumsq_q; // sum of (x 2^-(exp2+19))^2, in units of 2^-24 (per-wave sums rounded)
+    uint64_t errsq_q; // sum of ((x - stored x) 2^-exp2)^2, in units of 2^-28 (per-wave sums rounded)
 };
 constexpr uint32_t kFx20Magic = 0x30325846u;  // "FX20"
 

@@ -77,7 +77,12 @@ struct SRequest {
     int32_t tensor = 0, mode = 0;
     double arrival = 0, done = -1;
     int64_t epoch = -1;
+    int32_t status = DEINSUM_REQ_PENDING;  // read by deinsum_server_poll from other threads (atomic access)
+    int32_t flags = 0;
 };
+
+void store_status(SRequest &rq, int32_t st) { __atomic_store_n(&rq.status, st, __ATOMIC_RELEASE); }
+int32_t load_status(const SRequest &rq) { return __atomic_load_n(&rq.status, __ATOMIC_ACQUIRE); }
 
 struct Epoch {
     bool active = false;
@@ -110,14 +115,16 @@ struct deinsum_server {
     deinsum_server_config cfg{};
     std::vector<STensor> tensors;
     std::vector<SRequest> reqs;
-    std::mutex mu;                    // guards reqs growth, `submitted` and `error`
+    std::mutex mu;                    // guards reqs growth, `submitted` and the first error
     std::condition_variable cv;       // signalled on submission and on stop
     std::deque<int64_t> submitted;
     std::thread sched;
     std::atomic<bool> stop{false};
-    std::atomic<bool> failed{false};
-    std::string error;
-    std::atomic<int64_t> completed{0};
+    std::string first_error;          // message of the first failed request
+    int32_t first_status = DEINSUM_OK;
+    std::atomic<int64_t> completed{0};  // requests served successfully
+    std::atomic<int64_t> failed{0};     // requests that ended with an error
+    int32_t *req_flags = nullptr;       // pinned, one word per request: the update's floor flag
     int64_t nsubmitted = 0;
     Clock::time_point t0;
     bool started = false;
@@ -142,11 +149,36 @@ struct deinsum_server {
 
 namespace {
 
-void set_failed(deinsum_server *s, const std::string &msg)
+// A request that cannot be served ends with its own status; the server, the other
+// requests and later requests of the same tensor go on.
+void fail_request(deinsum_server *s, int64_t r, int32_t status, const std::string &msg)
 {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->error = msg;
-    s->failed = true;
+    SRequest &rq = s->reqs[r];
+    rq.done = s->now();
+    STensor &tn = s->tensors[rq.tensor];
+    tn.busy = false;
+    if (!tn.fifo.empty() && tn.fifo.front() == r) tn.fifo.pop_front();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->first_status == DEINSUM_OK) {
+            s->first_status = status;
+            s->first_error = "request " + std::to_string(r) + ": " + msg;
+        }
+    }
+    store_status(rq, status);
+    ++s->failed;
+}
+
+void finish_request(deinsum_server *s, int64_t r, double t)
+{
+    SRequest &rq = s->reqs[r];
+    rq.done = t;
+    if (s->cfg.als_update && __atomic_load_n(&s->req_flags[r], __ATOMIC_RELAXED)) rq.flags |= DEINSUM_REQ_REGULARISED;
+    STensor &tn = s->tensors[rq.tensor];
+    tn.busy = false;
+    if (!tn.fifo.empty() && tn.fifo.front() == r) tn.fifo.pop_front();
+    store_status(rq, DEINSUM_REQ_DONE);
+    ++s->completed;
 }
 
 bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
@@ -168,8 +200,11 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
     if (ep.reqs.empty()) return false;
     deinsum_batch_reset(s->batch[e]);
     int64_t als_total = 0;
+    std::vector<int64_t> added;
+    size_t footprint = 0;
     for (size_t k = 0; k < ep.reqs.size(); ++k) {
-        SRequest &rq = s->reqs[ep.reqs[k]];
+        const int64_t r = ep.reqs[k];
+        SRequest &rq = s->reqs[r];
         STensor &t = s->tensors[rq.tensor];
         const deinsum_spec sp = mttkrp_spec_for(t.order, rq.mode);
         const void *ops[DEINSUM_MAX_ORDER];
@@ -178,20 +213,30 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
         deinsum_opts_init(&o);
         o.precision = t.prec;
         o.out_dtype = DEINSUM_F64;
-        if (deinsum_batch_add_mttkrp(s->batch[e], &sp, t.dims, t.R, t.X, ops, t.M, &o, nullptr) != DEINSUM_OK) {
-            set_failed(s, std::string("serve: batch_add: ") + deinsum_last_error());
-            return false;
+        if (deinsum_status st = deinsum_batch_add_mttkrp(s->batch[e], &sp, t.dims, t.R, t.X, ops, t.M, &o, nullptr)) {
+            fail_request(s, r, st, std::string("batch_add: ") + deinsum_last_error());
+            continue;
         }
-        AlsJob &aj = s->als_pinned[e][k];
+        AlsJob &aj = s->als_pinned[e][added.size()];
         aj = als_job_for(t, rq.mode);
         aj.block_begin = als_total;
+        aj.flag = s->req_flags + r;
         als_total += als_blocks(t.dims[rq.mode]);
         rq.epoch = s->epochs;
+        footprint += t.ws[rq.mode];
+        added.push_back(r);
     }
-    if (deinsum_batch_launch(s->batch[e], s->stream[e]) != DEINSUM_OK) {
-        set_failed(s, std::string("serve: batch_launch: ") + deinsum_last_error());
+    ep.reqs.swap(added);
+    ep.footprint = footprint;
+    if (ep.reqs.empty()) return false;
+    auto fail_epoch = [&](const std::string &msg) {
+        for (int64_t r : ep.reqs) fail_request(s, r, DEINSUM_ERR_DEVICE, msg);
+        ep.reqs.clear();
         return false;
-    }
+    };
+    for (int64_t r : ep.reqs) store_status(s->reqs[r], DEINSUM_REQ_RUNNING);
+    if (deinsum_batch_launch(s->batch[e], s->stream[e]) != DEINSUM_OK)
+        return fail_epoch(std::string("batch_launch: ") + deinsum_last_error());
     if (s->cfg.als_update) {
         // One request: its update job goes as a kernel argument (the same kernels, no
         // descriptor copy); several: one table upload and one batched launch.
@@ -203,15 +248,9 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
                                  hipMemcpyHostToDevice, s->stream[e]);
             st = launch_als_batch(s->als_dev[e], static_cast<int>(ep.reqs.size()), als_total, s->stream[e]);
         }
-        if (st != DEINSUM_OK) {
-            set_failed(s, std::string("serve: ") + deinsum_last_error());
-            return false;
-        }
+        if (st != DEINSUM_OK) return fail_epoch(std::string("factor update: ") + deinsum_last_error());
     }
-    if (hipEventRecord(s->ev[e], s->stream[e]) != hipSuccess) {
-        set_failed(s, "serve: event record failed");
-        return false;
-    }
+    if (hipEventRecord(s->ev[e], s->stream[e]) != hipSuccess) return fail_epoch("event record failed");
     ep.active = true;
     s->footprint_used += ep.footprint;
     ++s->epochs;
@@ -219,18 +258,15 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
     return true;
 }
 
-void complete_epoch(deinsum_server *s, int e)
+// The epoch's event has completed (device_ok) or reported an error (its requests fail).
+void complete_epoch(deinsum_server *s, int e, bool device_ok)
 {
     Epoch &ep = s->epoch[e];
     const double t = s->now();
     for (int64_t r : ep.reqs) {
-        SRequest &rq = s->reqs[r];
-        rq.done = t;
-        STensor &tn = s->tensors[rq.tensor];
-        tn.busy = false;
-        if (!tn.fifo.empty() && tn.fifo.front() == r) tn.fifo.pop_front();
+        if (device_ok) finish_request(s, r, t);
+        else fail_request(s, r, DEINSUM_ERR_DEVICE, "device error while the epoch ran");
     }
-    s->completed += static_cast<int64_t>(ep.reqs.size());
     s->footprint_used -= ep.footprint;
     ep.active = false;
     ep.reqs.clear();
@@ -249,6 +285,7 @@ bool launch_one(deinsum_server *s, int64_t r)
     o.out_dtype = DEINSUM_F64;
     o.workspace = s->ws;
     o.workspace_bytes = s->ws_bytes;
+    store_status(rq, DEINSUM_REQ_RUNNING);
     deinsum_status st = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]);
     if (st == DEINSUM_ERR_NO_MEMORY && s->ws) {  // a plan tuned after start needs more: the library pool
         o.workspace = nullptr;
@@ -256,12 +293,14 @@ bool launch_one(deinsum_server *s, int64_t r)
         st = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]);
     }
     if (st != DEINSUM_OK) {
-        set_failed(s, std::string("serve: mttkrp: ") + deinsum_last_error());
+        fail_request(s, r, st, std::string("mttkrp: ") + deinsum_last_error());
         return false;
     }
     if (s->cfg.als_update) {
-        if (launch_als_one(als_job_for(t, rq.mode), s->stream[0]) != DEINSUM_OK) {
-            set_failed(s, std::string("serve: ") + deinsum_last_error());
+        AlsJob aj = als_job_for(t, rq.mode);
+        aj.flag = s->req_flags + r;
+        if (deinsum_status st2 = launch_als_one(aj, s->stream[0])) {
+            fail_request(s, r, st2, std::string("factor update: ") + deinsum_last_error());
             return false;
         }
     }
@@ -270,10 +309,14 @@ bool launch_one(deinsum_server *s, int64_t r)
         ev = s->event_pool.back();
         s->event_pool.pop_back();
     } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
-        set_failed(s, "serve: event creation failed");
+        fail_request(s, r, DEINSUM_ERR_DEVICE, "event creation failed");
         return false;
     }
-    (void)hipEventRecord(ev, s->stream[0]);
+    if (hipEventRecord(ev, s->stream[0]) != hipSuccess) {
+        s->event_pool.push_back(ev);
+        fail_request(s, r, DEINSUM_ERR_DEVICE, "event record failed");
+        return false;
+    }
     s->inflight.emplace_back(r, ev);
     rq.epoch = s->epochs++;
     return true;
@@ -283,6 +326,7 @@ void scheduler(deinsum_server *s)
 {
     (void)hipSetDevice(s->device);
     std::deque<int64_t> pending;  // arrival order
+    std::vector<int64_t> intake;
     for (;;) {
         bool progress = false;
         {
@@ -290,18 +334,31 @@ void scheduler(deinsum_server *s)
             while (!s->submitted.empty()) {
                 const int64_t r = s->submitted.front();
                 s->submitted.pop_front();
-                s->tensors[s->reqs[r].tensor].fifo.push_back(r);
-                pending.push_back(r);
-                progress = true;
+                intake.push_back(r);
             }
         }
-        if (s->failed) return;
+        for (int64_t r : intake) {
+            progress = true;
+            const SRequest &rq = s->reqs[r];
+            const size_t ws = s->tensors[rq.tensor].ws[rq.mode];
+            if (ws > s->cfg.hbm_budget_bytes) {  // can never be admitted within the budget
+                fail_request(s, r, DEINSUM_ERR_NO_MEMORY,
+                             "MTTKRP workspace of " + std::to_string(ws) + " bytes exceeds the HBM budget");
+                continue;
+            }
+            s->tensors[rq.tensor].fifo.push_back(r);
+            pending.push_back(r);
+        }
+        intake.clear();
         if (s->cfg.batched) {
-            for (int e = 0; e < 2; ++e)
-                if (s->epoch[e].active && hipEventQuery(s->ev[e]) == hipSuccess) {
-                    complete_epoch(s, e);
-                    progress = true;
-                }
+            for (int e = 0; e < 2; ++e) {
+                if (!s->epoch[e].active) continue;
+                const hipError_t q = hipEventQuery(s->ev[e]);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) (void)hipGetLastError();
+                complete_epoch(s, e, q == hipSuccess);
+                progress = true;
+            }
             const int slots = std::max(1, std::min(2, s->cfg.epochs_in_flight));
             for (int e = 0; e < slots && !pending.empty(); ++e)
                 if (!s->epoch[e].active && launch_epoch(s, e, pending)) progress = true;
@@ -309,21 +366,24 @@ void scheduler(deinsum_server *s)
             while (!pending.empty()) {
                 const int64_t r = pending.front();
                 pending.pop_front();
-                if (!launch_one(s, r)) return;
+                (void)launch_one(s, r);  // a failure ends that request only
                 progress = true;
             }
-            while (!s->inflight.empty() && hipEventQuery(s->inflight.front().second) == hipSuccess) {
+            while (!s->inflight.empty()) {
+                const hipError_t q = hipEventQuery(s->inflight.front().second);
+                if (q == hipErrorNotReady) break;
                 const int64_t r = s->inflight.front().first;
-                s->reqs[r].done = s->now();
-                STensor &tn = s->tensors[s->reqs[r].tensor];
-                if (!tn.fifo.empty() && tn.fifo.front() == r) tn.fifo.pop_front();
+                if (q == hipSuccess) {
+                    finish_request(s, r, s->now());
+                } else {
+                    (void)hipGetLastError();
+                    fail_request(s, r, DEINSUM_ERR_DEVICE, "device error while the request ran");
+                }
                 s->event_pool.push_back(s->inflight.front().second);
                 s->inflight.pop_front();
-                ++s->completed;
                 progress = true;
             }
         }
-        if (s->failed) return;
         if (s->stop && pending.empty()) {
             bool idle = s->inflight.empty() && !s->epoch[0].active && !s->epoch[1].active;
             std::lock_guard<std::mutex> lk(s->mu);
@@ -463,6 +523,13 @@ deinsum_status deinsum_server_start(deinsum_server *s)
     if (!s) return fail(DEINSUM_ERR_INVALID_ARG, "server_start: null server");
     if (s->started) return fail(DEINSUM_ERR_BUSY, "server_start: already started");
     s->reqs.reserve(static_cast<size_t>(s->cfg.max_requests));
+    if (hipHostMalloc(reinterpret_cast<void **>(&s->req_flags), sizeof(int32_t) * static_cast<size_t>(s->cfg.max_requests),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        s->req_flags = nullptr;
+        return fail(DEINSUM_ERR_NO_MEMORY, "server_start: request flag table allocation failed");
+    }
+    std::memset(s->req_flags, 0, sizeof(int32_t) * static_cast<size_t>(s->cfg.max_requests));
     if (!s->cfg.batched) {
         size_t mx = 0;
         for (auto &t : s->tensors)
@@ -489,7 +556,6 @@ deinsum_status deinsum_server_submit(deinsum_server *s, int32_t tensor_id, int32
         return fail(DEINSUM_ERR_INVALID_ARG, "server_submit: unknown tensor");
     if (mode < 0 || mode >= s->tensors[tensor_id].order) return fail(DEINSUM_ERR_INVALID_ARG, "server_submit: bad mode");
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server_submit: server failed: " + s->error);
     if (s->reqs.size() == s->reqs.capacity())
         return fail(DEINSUM_ERR_BUSY, "server_submit: request table full");  // reqs must not reallocate while served
     SRequest rq;
@@ -530,13 +596,36 @@ deinsum_status deinsum_server_drain(deinsum_server *s)
         int64_t nsub;
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            if (s->failed) return fail(DEINSUM_ERR_DEVICE, "server failed: " + s->error);
             nsub = s->nsubmitted;
         }
-        if (s->completed >= nsub) break;
+        if (s->completed + s->failed >= nsub) break;
         std::this_thread::sleep_for(std::chrono::microseconds(50));
     }
+    if (s->failed > 0) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        return fail(static_cast<deinsum_status>(s->first_status),
+                    std::to_string(s->failed.load()) + " request(s) failed; first: " + s->first_error);
+    }
     clear_error();
+    return DEINSUM_OK;
+}
+
+deinsum_status deinsum_server_poll(const deinsum_server *s, int64_t request_id, int32_t *status, int32_t *flags,
+                                   double *done_s)
+{
+    if (!s || !s->started) return fail(DEINSUM_ERR_INVALID_ARG, "server_poll: server not started");
+    auto *ms = const_cast<deinsum_server *>(s);
+    int64_t n;
+    {
+        std::lock_guard<std::mutex> lk(ms->mu);
+        n = static_cast<int64_t>(s->reqs.size());
+    }
+    if (request_id < 0 || request_id >= n) return fail(DEINSUM_ERR_INVALID_ARG, "server_poll: unknown request");
+    const SRequest &rq = s->reqs[request_id];
+    const int32_t st = load_status(rq);  // acquire: done and flags below were written before it
+    if (status) *status = st;
+    if (flags) *flags = st == DEINSUM_REQ_DONE ? rq.flags : 0;
+    if (done_s) *done_s = (st == DEINSUM_REQ_DONE || st < 0) ? rq.done : -1.0;
     return DEINSUM_OK;
 }
 
@@ -581,6 +670,7 @@ deinsum_status deinsum_server_destroy(deinsum_server *s)
     for (auto &t : s->tensors)
         if (t.M) (void)hipFree(t.M);
     if (s->ws) (void)hipFree(s->ws);
+    if (s->req_flags) (void)hipHostFree(s->req_flags);
     delete s;
     return DEINSUM_OK;
 }

@@ -186,3 +186,81 @@ def test_server_rejects_bad_input(dn):
         srv.submit(t + 1, 0)
     srv.drain()
     srv.close()
+
+
+@pytest.mark.parametrize("batched", [True, False])
+def test_request_over_budget_fails_alone(dn, oracle_mod, batched):
+    """A request whose MTTKRP workspace alone exceeds the HBM budget ends with
+    NO_MEMORY; the other tensor's requests, interleaved with it, are served and match
+    the oracle, and the server keeps accepting work."""
+    small = host_tensor(710, (24, 20, 28), 8, "fp64")
+    big = host_tensor(711, (200, 220, 240), 64, "fp64")
+    ws_small = max(dn.workspace_size(s, small[0].shape, [8]) for s in ("ijk,ja,ka->ia", "ijk,ia,ka->ja", "ijk,ia,ja->ka"))
+    ws_big = dn.workspace_size("ijk,ja,ka->ia", big[0].shape, [64])
+    budget = (ws_small + ws_big) // 2
+    assert ws_small <= budget < ws_big
+    srv = dn.Server(batched=batched, max_requests=64, hbm_budget_bytes=budget)
+    devs = []
+    for X, U in (small, big):
+        Xd, Ud = device_copy(X, U, "fp64")
+        srv.add_tensor(Xd, Ud, precision="fp64")
+        devs.append(Ud)
+    srv.start()
+    ids = []
+    for n in range(3):
+        ids.append((0, n, srv.submit(0, n)))
+        ids.append((1, 0, srv.submit(1, 0)))  # mode 0 of the big tensor needs more than the budget
+    st = srv.drain(check=False)
+    assert st == -5, dn.last_error()
+    for t, n, rid in ids:
+        p = srv.poll(rid)
+        if t == 0:
+            assert p["status"] == "done" and p["done"] >= 0, p
+        else:
+            assert p["status"] == "NO_MEMORY" and p["code"] == -5, p
+    assert srv.stats()["completed"] == 3
+    rid = srv.submit(0, 0)  # the server still serves
+    srv.drain(check=False)
+    assert srv.poll(rid)["status"] == "done"
+    srv.close()
+    torch.cuda.synchronize()
+    ref = oracle_sweeps(oracle_mod, small[0], small[1], [0, 1, 2, 0])
+    for m in range(3):
+        assert nrel(devs[0][m].cpu().numpy(), ref[m]) <= 1e-10
+
+
+def test_regularised_update_is_flagged(dn):
+    """R = 32 with two modes of extent 3: V = G^0 * G^1 (Hadamard) for the mode-2 update
+    has rank at most 9 < 32, so the Gauss-Jordan pivots fall below the floor and the
+    request is flagged; a well-conditioned tensor's requests are not."""
+    sing = host_tensor(720, (3, 3, 90), 32, "fp64")
+    good = host_tensor(721, (60, 50, 70), 8, "fp64")
+    srv = dn.Server(batched=True, max_requests=16)
+    for X, U in (sing, good):
+        Xd, Ud = device_copy(X, U, "fp64")
+        srv.add_tensor(Xd, Ud, precision="fp64")
+    srv.start()
+    r_sing = srv.submit(0, 2)
+    r_good = [srv.submit(1, n) for n in range(3)]
+    srv.drain()
+    assert srv.poll(r_sing)["flags"] == {"regularised"}
+    for r in r_good:
+        p = srv.poll(r)
+        assert p["status"] == "done" and p["flags"] == set(), p
+    srv.close()
+
+
+def test_poll_states_and_errors(dn):
+    X, U = host_tensor(730, (30, 20, 25), 8, "fp64")
+    srv = dn.Server(batched=True, max_requests=8)
+    Xd, Ud = device_copy(X, U, "fp64")
+    srv.add_tensor(Xd, Ud, precision="fp64")
+    srv.start()
+    rid = srv.submit(0, 1)
+    assert srv.poll(rid)["status"] in ("pending", "running", "done")
+    srv.drain()
+    p = srv.poll(rid)
+    assert p["status"] == "done" and p["code"] == 0 and p["done"] > 0
+    with pytest.raises(dn.DeinsumError):
+        srv.poll(rid + 100)
+    srv.close()
