@@ -17,7 +17,11 @@ This module only marshals numpy arrays to that library, except for
   * ``als_update`` -- one CP-ALS factor update built on ``mttkrp`` (numpy).
     The paper names MTTKRP as the main kernel of the CP decomposition (Sec. I)
     but does not state the update; this is the textbook alternating
-    least-squares step (Kolda & Bader, SIAM Review 51(3), 2009, Sec. 3.4).
+    least-squares step (Kolda & Bader, SIAM Review 51(3), 2009, Sec. 3.4);
+  * ``cp_als`` and ``tucker_hooi`` -- the textbook CP-ALS sweep loop and the
+    higher-order orthogonal iteration (Kolda & Bader, Sec. 3.4 and 4.2) on top
+    of ``mttkrp`` / ``ttmc`` with numpy's dense solve and SVD, fits from the
+    explicitly formed reconstructions.
 """
 from __future__ import annotations
 
@@ -176,3 +180,105 @@ def als_update(X, U, n):
     norms = np.sqrt(np.sum(A * A, axis=0))
     norms[norms == 0] = 1.0
     return A / norms
+
+
+# --------------------------------------------------------------------------- decompositions
+# The paper motivates MTTKRP and TTMc by the CP and Tucker decompositions that
+# consume them (Sec. I).  It does not state the outer algorithms; these are the
+# textbook ones (Kolda & Bader, SIAM Review 51(3), 2009): CP-ALS (Sec. 3.4) and
+# the higher-order orthogonal iteration, HOOI (Sec. 4.2), written plainly on
+# top of ``mttkrp`` and ``ttmc`` with numpy's dense solvers.
+
+def _letters(N):
+    return "abcdefgh"[:N]
+
+
+def kruskal_full(lam, U):
+    """The dense tensor sum_r lam_r U[0][:, r] o U[1][:, r] o ... (outer products)."""
+    N = len(U)
+    t = _letters(N)
+    spec = "z," + ",".join(f"{t[m]}z" for m in range(N)) + "->" + t
+    return np.einsum(spec, _f64(lam), *[_f64(u) for u in U])
+
+
+def tucker_full(G, U):
+    """The dense tensor G x_0 U[0] x_1 U[1] ... (each U[m] is I_m x R_m)."""
+    Y = _f64(G)
+    for m, u in enumerate(U):
+        Y = ttm(Y, _f64(u).T, m)
+    return Y
+
+
+def cp_als(X, U0, sweeps, tol=0.0):
+    """CP-ALS from the starting factors ``U0`` (one I_m x R matrix per mode).
+
+    A sweep updates the modes in increasing order; the mode-n update solves the
+    normal equations A V = M, M = mttkrp(X, U, n), V = Hadamard product of the
+    Grams U[m]^T U[m] (m != n), then stores U[n] = A with unit 2-norm columns and
+    lam = the column norms of A.  After each sweep the fit
+    1 - ||X - [[lam; U]]||_F / ||X||_F is computed from the explicitly formed
+    reconstruction.  Stops after ``sweeps`` sweeps, or earlier when the fit
+    changes by less than ``tol``.  Returns (U, lam, fits).
+    """
+    X = _f64(X)
+    N = X.ndim
+    U = [_f64(u).copy() for u in U0]
+    R = U[0].shape[1]
+    lam = np.ones(R)
+    fits = []
+    xnorm = np.linalg.norm(X.ravel())
+    for _ in range(sweeps):
+        for n in range(N):
+            M = mttkrp(X, [None if m == n else U[m] for m in range(N)], n)
+            V = np.ones((R, R))
+            for m in range(N):
+                if m != n:
+                    V = V * (U[m].T @ U[m])
+            A = np.linalg.solve(V, M.T).T
+            lam = np.sqrt(np.sum(A * A, axis=0))
+            U[n] = A / np.where(lam > 0, lam, 1.0)
+        fits.append(1.0 - np.linalg.norm((X - kruskal_full(lam, U)).ravel()) / xnorm)
+        if len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
+            break
+    return U, lam, fits
+
+
+def sign_fix(Q):
+    """Columns scaled by +-1 so that each column's entry of largest magnitude (the
+    first one on ties) is positive: the convention that makes singular vectors unique."""
+    Q = _f64(Q).copy()
+    for r in range(Q.shape[1]):
+        k = int(np.argmax(np.abs(Q[:, r])))
+        if Q[k, r] < 0:
+            Q[:, r] = -Q[:, r]
+    return Q
+
+
+def tucker_hooi(X, U0, sweeps, tol=0.0):
+    """HOOI from the starting factors ``U0`` (I_m x R_m, orthonormal columns).
+
+    A sweep updates the modes in increasing order: Y = ttmc(X, U, n) (every mode
+    but n), then U[n] = the R_n leading left singular vectors of the mode-n
+    unfolding of Y (numpy SVD, columns by decreasing singular value, sign_fix).
+    After each sweep the core G = Y x_n U[n]^T of the last mode and the fit
+    1 - ||X - G x_0 U[0] ... ||_F / ||X||_F (explicit reconstruction) are formed.
+    Stops after ``sweeps`` sweeps or when the fit changes by less than ``tol``.
+    Returns (U, G, fits).
+    """
+    X = _f64(X)
+    N = X.ndim
+    U = [_f64(u).copy() for u in U0]
+    fits = []
+    xnorm = np.linalg.norm(X.ravel())
+    G = None
+    for _ in range(sweeps):
+        for n in range(N):
+            Y = ttmc(X, U, n)
+            Yn = np.moveaxis(Y, n, 0).reshape(X.shape[n], -1)
+            left, _, _ = np.linalg.svd(Yn, full_matrices=False)
+            U[n] = sign_fix(left[:, :U[n].shape[1]])
+        G = ttm(Y, U[N - 1], N - 1)
+        fits.append(1.0 - np.linalg.norm((X - tucker_full(G, U)).ravel()) / xnorm)
+        if len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
+            break
+    return U, G, fits

@@ -398,3 +398,106 @@ def test_als_update_matches_lstsq(oracle_mod, dims, n):
     got = oracle_mod.als_update(X, [None if m == n else U[m] for m in range(len(dims))], n)
     assert nrel(got, _unit_columns(A)) <= 1e-10
     assert np.allclose(np.sqrt(np.sum(got * got, axis=0)), 1.0, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------------ CP-ALS and HOOI (Sec. I consumers)
+def _orth(rng, n, r):
+    q, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    return q
+
+
+def test_cp_als_rank1_exact_in_one_sweep(oracle_mod):
+    """X = a o b o c: the first mode-0 update is a scaled a (M = a (b^T B)*(c^T C)), and
+    the next two make the reconstruction exact, so one sweep gives fit 1."""
+    rng = np.random.default_rng(11)
+    a, b, c = rng.standard_normal(7), rng.standard_normal(6), rng.standard_normal(5)
+    X = np.einsum("i,j,k->ijk", a, b, c)
+    U0 = [rng.standard_normal((d, 1)) for d in X.shape]
+    U, lam, fits = oracle_mod.cp_als(X, U0, 1)
+    assert fits[0] == pytest.approx(1.0, abs=1e-12)
+    for u, v in zip(U, (a, b, c)):
+        assert abs(abs(u[:, 0] @ v) / np.linalg.norm(v) - 1.0) < 1e-12
+    assert lam[0] == pytest.approx(np.linalg.norm(a) * np.linalg.norm(b) * np.linalg.norm(c), rel=1e-12)
+
+
+def test_cp_als_recovers_planted_kruskal(oracle_mod):
+    rng = np.random.default_rng(12)
+    dims, R = (14, 12, 10), 3
+    A = [rng.standard_normal((d, R)) for d in dims]
+    lam = np.array([3.0, 2.0, 1.5])
+    X = oracle_mod.kruskal_full(lam, A)
+    U0 = [a + 0.2 * rng.standard_normal(a.shape) for a in A]
+    U, lam_hat, fits = oracle_mod.cp_als(X, U0, 300, tol=1e-15)
+    assert fits[-1] > 1.0 - 1e-8
+    assert np.linalg.norm(oracle_mod.kruskal_full(lam_hat, U) - X) <= 1e-7 * np.linalg.norm(X)
+
+
+def test_cp_als_first_update_is_least_squares(oracle_mod):
+    """The mode-0 update minimises ||X_(0) - A (C kr B)^T||: compare with lstsq on the
+    explicit Khatri-Rao product (columns normalised the same way)."""
+    rng = np.random.default_rng(13)
+    X = rng.standard_normal((6, 5, 4))
+    U0 = [rng.standard_normal((d, 3)) for d in X.shape]
+    U, _, _ = oracle_mod.cp_als(X, U0, 1)
+    # After a full sweep U[0] is the first update; recompute it from U0 directly.
+    K = np.einsum("jr,kr->jkr", U0[1], U0[2]).reshape(-1, 3)
+    A = np.linalg.lstsq(K, X.reshape(6, -1).T, rcond=None)[0].T
+    A /= np.linalg.norm(A, axis=0)
+    assert np.allclose(U[0], A, atol=1e-12)
+
+
+def test_cp_als_fit_does_not_decrease(oracle_mod):
+    rng = np.random.default_rng(14)
+    X = rng.standard_normal((9, 8, 7))
+    U0 = [rng.standard_normal((d, 4)) for d in X.shape]
+    _, _, fits = oracle_mod.cp_als(X, U0, 15)
+    assert all(f2 >= f1 - 1e-12 for f1, f2 in zip(fits, fits[1:]))
+
+
+def test_hooi_matrix_is_truncated_svd(oracle_mod):
+    """Order 2: HOOI is subspace iteration on X X^T, converging to the truncated SVD;
+    the fit is then Eckart-Young's 1 - sqrt(sum_{i>r} s_i^2) / ||X||."""
+    rng = np.random.default_rng(15)
+    sv = np.array([10.0, 7.0, 5.0, 1.0, 0.7, 0.4, 0.2, 0.1, 0.05])
+    X = _orth(rng, 12, 9) @ np.diag(sv) @ _orth(rng, 9, 9).T
+    U0 = [_orth(rng, 12, 3), _orth(rng, 9, 3)]
+    U, G, fits = oracle_mod.tucker_hooi(X, U0, 40)
+    left, s, right = np.linalg.svd(X)
+    assert fits[-1] == pytest.approx(1 - np.sqrt(np.sum(s[3:] ** 2)) / np.linalg.norm(X), abs=1e-12)
+    assert np.allclose(U[0] @ U[0].T, left[:, :3] @ left[:, :3].T, atol=1e-10)
+    assert np.allclose(np.abs(np.diag(G)), s[:3], atol=1e-10)
+
+
+def test_hooi_recovers_planted_tucker(oracle_mod):
+    """X = G x_m V_m with orthonormal V_m: exact multilinear rank, so one sweep from a
+    random orthonormal start gives the subspaces of V_m and fit 1."""
+    rng = np.random.default_rng(16)
+    dims, ranks = (10, 9, 8, 7), (3, 2, 4, 2)
+    V = [_orth(rng, d, r) for d, r in zip(dims, ranks)]
+    G0 = rng.standard_normal(ranks)
+    X = oracle_mod.tucker_full(G0, V)
+    U0 = [_orth(rng, d, r) for d, r in zip(dims, ranks)]
+    U, G, fits = oracle_mod.tucker_hooi(X, U0, 1)
+    assert fits[0] == pytest.approx(1.0, abs=1e-12)
+    for u, v in zip(U, V):
+        assert np.allclose(u @ u.T, v @ v.T, atol=1e-12)
+        assert np.allclose(u.T @ u, np.eye(u.shape[1]), atol=1e-12)
+    assert np.linalg.norm(G) == pytest.approx(np.linalg.norm(X), rel=1e-12)
+
+
+def test_hooi_fit_does_not_decrease_and_core_norm(oracle_mod):
+    """Orthonormal factors: ||X - [[G; U]]||^2 = ||X||^2 - ||G||^2 at every sweep, and
+    the fit of HOOI does not decrease."""
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((8, 7, 6))
+    U0 = [_orth(rng, d, 3) for d in X.shape]
+    U, G, fits = oracle_mod.tucker_hooi(X, U0, 6)
+    assert all(f2 >= f1 - 1e-12 for f1, f2 in zip(fits, fits[1:]))
+    xn, gn = np.linalg.norm(X), np.linalg.norm(G)
+    assert fits[-1] == pytest.approx(1 - np.sqrt(xn ** 2 - gn ** 2) / xn, abs=1e-12)
+
+
+def test_sign_fix_convention(oracle_mod):
+    Q = np.array([[0.1, -0.9], [-0.8, 0.2], [0.3, 0.9]])
+    F = oracle_mod.sign_fix(Q)
+    assert np.array_equal(F, np.array([[-0.1, 0.9], [0.8, -0.2], [-0.3, -0.9]]))
