@@ -517,6 +517,73 @@ deinsum_status deinsum_server_stats(const deinsum_server *s, int64_t *completed,
 deinsum_status deinsum_server_destroy(deinsum_server *s);
 
 /*
+ * Decompositions built on the two kernels: the paper motivates MTTKRP and TTMc
+ * by the CP and Tucker decompositions that spend their time in them (Sec. I).
+ * Both run on the device around deinsum_mttkrp / deinsum_ttmc on `stream` and
+ * return when done (they read one convergence scalar per sweep, HOOI also one
+ * per subspace iteration, so they synchronise `stream`).  Deterministic.
+ *
+ * deinsum_cp_als: CP-ALS (Kolda & Bader, SIAM Review 2009, Sec. 3.4).  A sweep
+ *   updates the modes in increasing order: M = the mode-n MTTKRP, then
+ *   U^n = M V^{-1}, V the Hadamard product of the Grams U^m^T U^m (m != n),
+ *   columns scaled to unit norm, the norms kept in lambda (the update of the
+ *   request server; a pivot below 1e-14 max diag V is floored and flagged).
+ *   After each sweep, fit = 1 - ||X - [[lambda; U]]||_F / ||X||_F from
+ *   ||X||^2 - 2 <X, [[lambda; U]]> + ||[[lambda; U]]||^2 (the inner product
+ *   from the last mode's MTTKRP and factor, the model norm from lambda and the
+ *   Grams), so fits within ~1e-8 of 1 are not resolved.  Stops after
+ *   max_sweeps or when the fit changes by less than tol.
+ *   order 2..8, R 1..64.  X, U: device, F64 (precision FP64) or F32 (FP32,
+ *   BF16X3: the MTTKRP form); U holds `order` factors by mode (dims[m] x R),
+ *   read as the starting point and overwritten with the result; lambda: device,
+ *   R doubles, out.
+ * deinsum_tucker_hooi: higher-order orthogonal iteration (Kolda & Bader, Sec.
+ *   4.2).  A sweep updates the modes in increasing order: Y = the TTMc of mode
+ *   n (every other mode contracted with its factor), then U^n = the ranks[n]
+ *   leading left singular vectors of the mode-n unfolding of Y: subspace
+ *   iteration Q <- orth(Y_(n) orth(Y_(n)^T Q)) from the current U^n, CholeskyQR
+ *   twice for each orth, until ||Q_new - Q Q^T Q_new||_F < iter_tol or
+ *   max_iters; then Rayleigh-Ritz (cyclic Jacobi on the ranks[n]^2 matrix
+ *   (Y^T Q)^T (Y^T Q)), columns by decreasing singular value, each signed so
+ *   that its entry of largest magnitude is positive.  After each sweep the core
+ *   G = Y x_{N-1} U^{N-1}^T (row-major ranks[0] x .. x ranks[N-1], FP64) and
+ *   fit = 1 - sqrt(||X||^2 - ||G||^2) / ||X||.  Stops as CP-ALS.  ranks[m] in
+ *   1..min(64, dims[m]) and at most the product of the other ranks.  X, U:
+ *   device, F64 (FP64) or F32 (FP32); U: `order` factors dims[m] x ranks[m]
+ *   with orthonormal columns, read as the start and overwritten; core: device,
+ *   prod(ranks) doubles, out.
+ * Errors as for deinsum_mttkrp / deinsum_ttmc; the drivers allocate their small
+ * state (FP64 intermediates) with hipMalloc and free it before returning.
+ */
+typedef struct deinsum_decomp_opts {
+    int32_t precision;    /* MTTKRP / TTMc form (see above)                          */
+    int32_t max_sweeps;   /* >= 1 (default 25)                                       */
+    double tol;           /* stop when |fit - previous fit| < tol (default 1e-10)     */
+    int32_t max_iters;    /* HOOI: subspace iterations per mode update (default 200) */
+    double iter_tol;      /* HOOI: subspace change to stop at (default 1e-11)        */
+    double *fit_trace;    /* optional host array of max_sweeps doubles: fit per sweep */
+} deinsum_decomp_opts;
+
+#define DEINSUM_DECOMP_REGULARISED 1    /* a CP update floored a pivot of V          */
+#define DEINSUM_DECOMP_MAX_ITERS 2      /* a HOOI subspace iteration hit max_iters   */
+#define DEINSUM_DECOMP_RANK_DEFICIENT 4 /* a HOOI orthonormalisation met rank loss   */
+
+typedef struct deinsum_decomp_result {
+    int32_t sweeps;       /* sweeps run                                             */
+    int32_t flags;        /* DEINSUM_DECOMP_* bits                                  */
+    double fit;           /* fit after the last sweep                               */
+    int64_t iters;        /* HOOI: subspace iterations, all modes and sweeps        */
+} deinsum_decomp_result;
+
+void deinsum_decomp_opts_init(deinsum_decomp_opts *opts);
+deinsum_status deinsum_cp_als(int32_t order, const int64_t *dims, int64_t R, const void *X, void *const *U,
+                              double *lambda, const deinsum_decomp_opts *opts, deinsum_decomp_result *result,
+                              void *stream);
+deinsum_status deinsum_tucker_hooi(int32_t order, const int64_t *dims, const int64_t *ranks, const void *X,
+                                   void *const *U, double *core, const deinsum_decomp_opts *opts,
+                                   deinsum_decomp_result *result, void *stream);
+
+/*
  * Autotuner.  deinsum_tune_mttkrp runs the MTTKRP on the caller's buffers
  * (M is overwritten) once with every compiled tile shape for the problem's
  * precision and free mode (column width 16*nt, rows per wave, slice of the

@@ -209,7 +209,7 @@ def tucker_full(G, U):
     return Y
 
 
-def cp_als(X, U0, sweeps, tol=0.0):
+def cp_als(X, U0, sweeps, tol=0.0, with_fit=True):
     """CP-ALS from the starting factors ``U0`` (one I_m x R matrix per mode).
 
     A sweep updates the modes in increasing order; the mode-n update solves the
@@ -217,8 +217,9 @@ def cp_als(X, U0, sweeps, tol=0.0):
     Grams U[m]^T U[m] (m != n), then stores U[n] = A with unit 2-norm columns and
     lam = the column norms of A.  After each sweep the fit
     1 - ||X - [[lam; U]]||_F / ||X||_F is computed from the explicitly formed
-    reconstruction.  Stops after ``sweeps`` sweeps, or earlier when the fit
-    changes by less than ``tol``.  Returns (U, lam, fits).
+    reconstruction (skipped, and ``tol`` ignored, with ``with_fit=False``).
+    Stops after ``sweeps`` sweeps, or earlier when the fit changes by less than
+    ``tol``.  Returns (U, lam, fits).
     """
     X = _f64(X)
     N = X.ndim
@@ -237,6 +238,8 @@ def cp_als(X, U0, sweeps, tol=0.0):
             A = np.linalg.solve(V, M.T).T
             lam = np.sqrt(np.sum(A * A, axis=0))
             U[n] = A / np.where(lam > 0, lam, 1.0)
+        if not with_fit:
+            continue
         fits.append(1.0 - np.linalg.norm((X - kruskal_full(lam, U)).ravel()) / xnorm)
         if len(fits) > 1 and abs(fits[-1] - fits[-2]) < tol:
             break

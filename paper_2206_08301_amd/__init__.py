@@ -451,6 +451,73 @@ def prepare(X: torch.Tensor, spec, ranks, tol, stream=None):
     return convert(X, dst, stream), storage
 
 
+def _decomp_opts(precision, max_sweeps, tol, max_iters, iter_tol, trace):
+    o = _lib.DecompOpts()
+    _lib.load().deinsum_decomp_opts_init(ctypes.byref(o))
+    o.precision = PRECISIONS[precision]
+    o.max_sweeps = int(max_sweeps)
+    o.tol = float(tol)
+    if max_iters is not None:
+        o.max_iters = int(max_iters)
+    if iter_tol is not None:
+        o.iter_tol = float(iter_tol)
+    o.fit_trace = ctypes.cast(trace, ctypes.POINTER(ctypes.c_double))
+    return o
+
+
+def cp_als(X, U, precision="fp64", max_sweeps=25, tol=1e-10, stream=None):
+    """CP-ALS on the device (deinsum_cp_als).  ``U`` (one dims[m] x R factor per mode) is
+    the starting point and is overwritten with the result.  Returns (lambda, info) with
+    info = {"sweeps", "fit", "fits" (per sweep), "regularised"}."""
+    _check_tensor(X, _X_DTYPE[precision], "X")
+    if len(U) != X.dim():
+        raise ValueError("one factor per mode is required")
+    R = U[0].shape[1]
+    for m, u in enumerate(U):
+        _check_tensor(u, _U_DTYPE[precision], f"U[{m}]")
+        if u.dim() != 2 or u.shape[0] != X.shape[m] or u.shape[1] != R:
+            raise ValueError(f"factor {m} must be {X.shape[m]} x {R}")
+    lam = torch.empty(R, dtype=torch.float64, device=X.device)
+    trace = (ctypes.c_double * int(max_sweeps))()
+    o = _decomp_opts(precision, max_sweeps, tol, None, None, trace)
+    res = _lib.DecompResult()
+    ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+    with torch.cuda.device(X.device):
+        _lib.check(_lib.load().deinsum_cp_als(X.dim(), _i64(X.shape), R, ctypes.c_void_p(X.data_ptr()), ptrs,
+                                              ctypes.c_void_p(lam.data_ptr()), ctypes.byref(o), ctypes.byref(res),
+                                              _stream(stream)))
+    return lam, {"sweeps": res.sweeps, "fit": res.fit, "fits": list(trace[:res.sweeps]),
+                 "regularised": bool(res.flags & 1)}
+
+
+def tucker_hooi(X, U, precision="fp64", max_sweeps=25, tol=1e-10, max_iters=None, iter_tol=None, stream=None):
+    """Tucker decomposition by HOOI on the device (deinsum_tucker_hooi).  ``U`` (one
+    dims[m] x R_m factor with orthonormal columns per mode) is the start and is
+    overwritten.  Returns (core, info) with info = {"sweeps", "fit", "fits", "iters",
+    "max_iters_hit", "rank_deficient"}."""
+    _check_tensor(X, _X_DTYPE[precision], "X")
+    if len(U) != X.dim():
+        raise ValueError("one factor per mode is required")
+    ranks = []
+    for m, u in enumerate(U):
+        _check_tensor(u, _U_DTYPE[precision], f"U[{m}]")
+        if u.dim() != 2 or u.shape[0] != X.shape[m]:
+            raise ValueError(f"factor {m} must be {X.shape[m]} x R_{m}")
+        ranks.append(u.shape[1])
+    core = torch.empty(ranks, dtype=torch.float64, device=X.device)
+    trace = (ctypes.c_double * int(max_sweeps))()
+    o = _decomp_opts(precision, max_sweeps, tol, max_iters, iter_tol, trace)
+    res = _lib.DecompResult()
+    ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+    with torch.cuda.device(X.device):
+        _lib.check(_lib.load().deinsum_tucker_hooi(X.dim(), _i64(X.shape), _i64(ranks),
+                                                   ctypes.c_void_p(X.data_ptr()), ptrs,
+                                                   ctypes.c_void_p(core.data_ptr()), ctypes.byref(o),
+                                                   ctypes.byref(res), _stream(stream)))
+    return core, {"sweeps": res.sweeps, "fit": res.fit, "fits": list(trace[:res.sweeps]), "iters": res.iters,
+                  "max_iters_hit": bool(res.flags & 2), "rank_deficient": bool(res.flags & 4)}
+
+
 def synth_fill(t: torch.Tensor, seed: int, dist: str = "uniform", offset: int = 0, stream=None):
     """Fill ``t`` with the counter-based SplitMix64 input stream (see include/deinsum.h)."""
     if t.device.type != "cuda" or not t.is_contiguous():

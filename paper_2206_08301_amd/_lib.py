@@ -59,6 +59,26 @@ class Report(ctypes.Structure):
     ]
 
 
+class DecompOpts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("max_iters", ctypes.c_int32),
+        ("iter_tol", ctypes.c_double),
+        ("fit_trace", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class DecompResult(ctypes.Structure):
+    _fields_ = [
+        ("sweeps", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("fit", ctypes.c_double),
+        ("iters", ctypes.c_int64),
+    ]
+
+
 class ServerConfig(ctypes.Structure):
     _fields_ = [
         ("batched", ctypes.c_int32),
@@ -98,7 +118,7 @@ EXPORTS = (
     "deinsum_tune_load", "deinsum_tune_save", "deinsum_tune_clear", "deinsum_tune_entries",
     "deinsum_fx20_size", "deinsum_fx20_encode", "deinsum_tune_ttmc", "deinsum_mttkrp_mm",
     "deinsum_mttkrp_noalloc", "deinsum_estimate_error", "deinsum_choose_storage", "deinsum_tensor_stats",
-    "deinsum_server_poll",
+    "deinsum_server_poll", "deinsum_decomp_opts_init", "deinsum_cp_als", "deinsum_tucker_hooi",
 )
 
 _lib = None
@@ -178,6 +198,14 @@ def load():
     lib.deinsum_server_drain.restype = ctypes.c_int
     lib.deinsum_server_results.argtypes = [vp, ctypes.c_int64, f64p, f64p, i64p]
     lib.deinsum_server_results.restype = ctypes.c_int
+    lib.deinsum_decomp_opts_init.argtypes = [ctypes.POINTER(DecompOpts)]
+    lib.deinsum_decomp_opts_init.restype = None
+    lib.deinsum_cp_als.argtypes = [ctypes.c_int32, i64p, ctypes.c_int64, vp, ctypes.POINTER(vp), vp,
+                                   ctypes.POINTER(DecompOpts), ctypes.POINTER(DecompResult), vp]
+    lib.deinsum_cp_als.restype = ctypes.c_int
+    lib.deinsum_tucker_hooi.argtypes = [ctypes.c_int32, i64p, i64p, vp, ctypes.POINTER(vp), vp,
+                                        ctypes.POINTER(DecompOpts), ctypes.POINTER(DecompResult), vp]
+    lib.deinsum_tucker_hooi.restype = ctypes.c_int
     lib.deinsum_server_poll.argtypes = [vp, ctypes.c_int64, i32p, i32p, f64p]
     lib.deinsum_server_poll.restype = ctypes.c_int
     lib.deinsum_server_stats.argtypes = [vp, i64p, i64p, i64p]

@@ -23,8 +23,8 @@ struct AlsJob {
     double *G;                     // Gram cache, order x R x R; G[m] = U^m^T U^m, G[mode] rewritten
     void *U[DEINSUM_MAX_ORDER];    // factors by mode; U[mode] is overwritten
     int64_t block_begin;           // first solve workgroup of this job in a batched launch
-    int32_t *flag;                 // optional: set to 1 when V needed the pivot floor, else 0
-                                   // (device-visible host memory or device memory)
+    int32_t *flag;                 // optional: set to 1 when V needed the pivot floor (never
+                                   // cleared; device-visible host memory or device memory)
     double *lambda;                // optional: the R column norms of the unnormalised update
 };
 

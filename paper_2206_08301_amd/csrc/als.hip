@@ -115,7 +115,7 @@ __device__ void als_solve_block(const AlsJob &j, int64_t blk)
         }
         __syncthreads();
     }
-    if (blk == 0 && tid == 0 && j.flag) __atomic_store_n(j.flag, floored ? 1 : 0, __ATOMIC_RELAXED);
+    if (blk == 0 && tid == 0 && j.flag && floored) __atomic_store_n(j.flag, 1, __ATOMIC_RELAXED);
     // Rows of the solution: Xs = M V^{-1}, a 4x4 register tile per thread.
     const int rg = tid >> 4, cg = tid & 15;
     double acc[4][4];
