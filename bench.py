@@ -44,6 +44,14 @@ def parse_args():
     ap.add_argument("--copy-probe", action="store_true",
                     help="profiling: run one plain 1 GiB device copy first (calibrates HBM byte counters)")
     ap.add_argument("--only", default="", help="profiling: run just one part (fp64|fx20|fp32|bf16|bf16x3|ttmc|more|serving)")
+    ap.add_argument("--summarize-trace", default="", metavar="CSV",
+                    help="print a kernel-time table from a rocprofv3 kernel_trace.csv and exit (no GPU)")
+    ap.add_argument("--summarize-pmc", default="", metavar="CSV",
+                    help="print a per-kernel counter table from a rocprofv3 counter_collection.csv and exit")
+    ap.add_argument("--last", type=int, default=0, help="--summarize-*: steady state = the last N launches per kernel")
+    ap.add_argument("--bytes", type=float, default=0.0,
+                    help="--summarize-trace: algorithmic bytes per launch of the kernel named by --kernel")
+    ap.add_argument("--kernel", default="", help="--summarize-*: substring naming the dominant kernel")
     return ap.parse_args()
 
 
@@ -73,8 +81,19 @@ def measured_traffic(plan_name):
     return int(mb.group(1)) if h.hexdigest() == mh.group(1) else None
 
 
-def event_median(torch, stream, fn, reps=10):
-    """Median duration (ms) of `reps` back-to-back calls, HIP events on the launch stream."""
+def boot_ci(samples, n=2000, seed=2206083010):
+    """95 % bootstrap confidence interval of the median (percentile method)."""
+    import numpy as np
+    a = np.asarray(samples, dtype=np.float64)
+    if a.size < 2:
+        return [float(a[0]), float(a[0])] if a.size else [None, None]
+    rng = np.random.default_rng(seed)
+    meds = np.median(a[rng.integers(0, a.size, (n, a.size))], axis=1)
+    return [round(float(np.percentile(meds, 2.5)), 4), round(float(np.percentile(meds, 97.5)), 4)]
+
+
+def event_samples(torch, stream, fn, reps=10):
+    """Durations (ms) of `reps` back-to-back calls, HIP events on the launch stream."""
     fn()
     torch.cuda.synchronize()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
@@ -83,48 +102,85 @@ def event_median(torch, stream, fn, reps=10):
         fn()
         evs[k + 1].record(stream)
     torch.cuda.synchronize()
-    return statistics.median(evs[k].elapsed_time(evs[k + 1]) for k in range(reps))
+    return [evs[k].elapsed_time(evs[k + 1]) for k in range(reps)]
+
+
+def timed(torch, stream, fn, reps=10):
+    """{"ms": median, "ci95_ms": bootstrap CI of the median} of `reps` event-timed calls."""
+    t = event_samples(torch, stream, fn, reps)
+    return statistics.median(t), boot_ci(t)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def rel_rows(got_rows, ref_rows):
+    """Largest normwise relative error over the sampled rows / slabs."""
+    import numpy as np
+    errs = []
+    for g, r in zip(got_rows, ref_rows):
+        errs.append(float(np.linalg.norm(np.ravel(g) - np.ravel(r)) / np.linalg.norm(np.ravel(r))))
+    return max(errs)
 
 
 def more_workloads(dn, synth, torch, stream, tune):
     """Order-5 MTTKRP (80^5, R=24, modes 0 and 2: FP64, FP32, FX20), order-4 TTMc (192^4,
     ranks 16, mode 0: FP64, FP32, BF16), and the paper's order-5 forms at 60^5, R=24
-    (MTTKRP mode 4: FP64, FP32, FX20; TTMc mode 0: FP64, FP32, BF16).  Reduced forms
-    report their error against the FP64 result of the same call (which the GPU tests
-    pin to the oracle)."""
+    (MTTKRP mode 4: FP64, FP32, FX20; TTMc mode 0: FP64, FP32, BF16).  Every form reports
+    its error against the oracle on sampled output rows / slabs, and its median time with
+    a 95 % bootstrap CI."""
+    import numpy as np
+
+    import oracle
     dev = torch.device("cuda:0")
     out = {}
+
+    def entry(t_ci, byts, flops=None):
+        t, ci = t_ci
+        e = {"ms": round(t, 4), "ci95_ms": ci, "GB/s": round(byts / (t / 1e3) / 1e9, 1),
+             "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        if flops:
+            e["GFLOP/s"] = round(flops / (t / 1e3) / 1e9, 1)
+        return e
+
     D5, R5 = (80,) * 5, 24
+    seed5 = synth.config_seed(3, 0)
     X = torch.empty(D5, dtype=torch.float64, device=dev)
-    dn.synth_fill(X, synth.config_seed(3, 0))
-    U = [torch.from_numpy(synth.normal_factor(synth.config_seed(3, 1 + m), 80, R5)).to(dev) for m in range(5)]
+    dn.synth_fill(X, seed5)
+    Uh = [synth.normal_factor(synth.config_seed(3, 1 + m), 80, R5) for m in range(5)]
+    U = [torch.from_numpy(u).to(dev) for u in Uh]
     X32 = torch.empty(D5, dtype=torch.float32, device=dev)
     dn.convert(X, X32)
     Xf = dn.to_fx20(X)
     nx = 80 ** 5
     res = {}
+    rows5 = {0: (0, 53, 79), 2: (1, 40, 79)}
     for n in (0, 2):
         spec = "abcde," + ",".join(f"{l}z" for i, l in enumerate("abcde") if i != n) + "->" + "abcde"[n] + "z"
         ops = [U[m] for m in range(5) if m != n]
         ops32 = [u.float() for u in ops]
-        M64 = torch.empty((80, R5), dtype=torch.float64, device=dev)
-        M32 = torch.empty((80, R5), dtype=torch.float64, device=dev)
+        ref = oracle.mttkrp(synth.x_rows(seed5, D5, n, rows5[n]), [None if m == n else Uh[m] for m in range(5)], n)
+        M = torch.empty((80, R5), dtype=torch.float64, device=dev)
         row = {}
         for form, Xp, opsp in (("fp64", X, ops), ("fp32", X32, ops32), ("fx20", Xf, ops32)):
-            M = M64 if form == "fp64" else M32
             if tune:
                 dn.tune_mttkrp(spec, Xp, opsp, precision=form, out=M, reps=2)
-            t = event_median(torch, stream, lambda: dn.mttkrp(spec, Xp, opsp, precision=form, out=M))
+            tc = timed(torch, stream, lambda: dn.mttkrp(spec, Xp, opsp, precision=form, out=M))
             xb = {"fp64": 8, "fp32": 4, "fx20": 3}[form]
             byts = nx * xb + 4 * 80 * R5 * (8 if form == "fp64" else 4) + 80 * R5 * 8
             flops = 2 * nx * R5 + 2 * (nx // 80) * R5 * 3
-            e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
-                 "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                 "GFLOP/s": round(flops / (t / 1e3) / 1e9, 1)}
+            e = entry(tc, byts, flops)
+            torch.cuda.synchronize()
+            e["rel_err_vs_oracle_sampled_rows"] = rel_rows(M.cpu().numpy()[list(rows5[n])], ref)
             if form != "fp64":
-                torch.cuda.synchronize()
-                e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
-                e["rel_err_vs_fp64"] = float((M - M64).norm() / M64.norm())
+                e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / tc[0], 3)
             row[form] = e
         res[str(n)] = row
         print(f"[bench] order-5 mode {n}: {row}", file=sys.stderr, flush=True)
@@ -133,44 +189,48 @@ def more_workloads(dn, synth, torch, stream, tune):
     torch.cuda.empty_cache()
 
     D4, R4 = (192,) * 4, 16
+    seed4 = synth.config_seed(4, 0)
     X = torch.empty(D4, dtype=torch.float64, device=dev)
-    dn.synth_fill(X, synth.config_seed(4, 0))
-    B = [torch.from_numpy(synth.orthonormal_factor(synth.config_seed(4, 1 + m), 192, R4)).to(dev) for m in (1, 2, 3)]
+    dn.synth_fill(X, seed4)
+    Bh = [synth.orthonormal_factor(synth.config_seed(4, 1 + m), 192, R4) for m in (1, 2, 3)]
+    B = [torch.from_numpy(b).to(dev) for b in Bh]
     X32 = torch.empty(D4, dtype=torch.float32, device=dev)
     dn.convert(X, X32)
     X16 = torch.empty(D4, dtype=torch.bfloat16, device=dev)
     dn.convert(X, X16)
-    Y64 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
-    Y32 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
-    Y16 = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
+    Y = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
+    slabs4 = (0, 77, 191)
+    ref4 = [oracle.ttmc(synth.x_slab(seed4, D4, 0, i), [None] + Bh, 0)[0] for i in slabs4]
     row = {}
     nx = 192 ** 4
     B32 = [b.float() for b in B]
-    for form, Xp, Bp, Y in (("fp64", X, B, Y64), ("fp32", X32, B32, Y32), ("bf16", X16, B32, Y16)):
+    for form, Xp, Bp in (("fp64", X, B), ("fp32", X32, B32), ("bf16", X16, B32)):
         if tune:
             dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y, tune_reps=2)
-        t = event_median(torch, stream, lambda: dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y))
+        tc = timed(torch, stream, lambda: dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y))
         xb = {"fp64": 8, "fp32": 4, "bf16": 2}[form]
         byts = nx * xb + 3 * 192 * R4 * (8 if form == "fp64" else 4) + 192 * R4 ** 3 * 8
-        e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
-             "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        e = entry(tc, byts)
+        torch.cuda.synchronize()
+        Yh = Y.cpu().numpy()
+        e["rel_err_vs_oracle_sampled_slabs"] = rel_rows([Yh[i] for i in slabs4], ref4)
         if form != "fp64":
-            torch.cuda.synchronize()
-            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
-            e["rel_err_vs_fp64"] = float((Y - Y64).norm() / Y64.norm())
+            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / tc[0], 3)
         row[form] = e
     print(f"[bench] ttmc order-4: {row}", file=sys.stderr, flush=True)
     out["ttmc_order4"] = {"workload": "TTMc order 4 mode 0, X 192^4 FP64 (10.9 GB), ranks 16, orthonormal factors",
                           "forms": row}
-    del X, X32, X16, Y64, Y32, Y16
+    del X, X32, X16, Y
     torch.cuda.empty_cache()
 
     # The paper's order-5 forms at I = 60, R = 24: MTTKRP in the last mode, TTMc in mode 0.
     D6, R6 = (60,) * 5, 24
     nx = 60 ** 5
+    seed6 = synth.config_seed(3, 60)
     X = torch.empty(D6, dtype=torch.float64, device=dev)
-    dn.synth_fill(X, synth.config_seed(3, 60))
-    U = [torch.from_numpy(synth.normal_factor(synth.config_seed(3, 61 + m), 60, R6)).to(dev) for m in range(5)]
+    dn.synth_fill(X, seed6)
+    Uh = [synth.normal_factor(synth.config_seed(3, 61 + m), 60, R6) for m in range(5)]
+    U = [torch.from_numpy(u).to(dev) for u in Uh]
     U32 = [u.float() for u in U]
     X32 = torch.empty(D6, dtype=torch.float32, device=dev)
     dn.convert(X, X32)
@@ -178,49 +238,48 @@ def more_workloads(dn, synth, torch, stream, tune):
     dn.convert(X, X16)
     Xf = dn.to_fx20(X)
     spec = "abcde,az,bz,cz,dz->ez"
-    M64 = torch.empty((60, R6), dtype=torch.float64, device=dev)
-    M32 = torch.empty((60, R6), dtype=torch.float64, device=dev)
+    rows6 = (0, 31, 59)
+    ref6 = oracle.mttkrp(synth.x_rows(seed6, D6, 4, rows6), Uh[:4] + [None], 4)
+    M = torch.empty((60, R6), dtype=torch.float64, device=dev)
     row = {}
     for form, Xp, opsp in (("fp64", X, U[:4]), ("fp32", X32, U32[:4]), ("fx20", Xf, U32[:4])):
-        M = M64 if form == "fp64" else M32
         if tune:
             dn.tune_mttkrp(spec, Xp, opsp, precision=form, out=M, reps=3)
-        t = event_median(torch, stream, lambda: dn.mttkrp(spec, Xp, opsp, precision=form, out=M))
+        tc = timed(torch, stream, lambda: dn.mttkrp(spec, Xp, opsp, precision=form, out=M))
         xb = {"fp64": 8, "fp32": 4, "fx20": 3}[form]
         byts = nx * xb + 4 * 60 * R6 * (8 if form == "fp64" else 4) + 60 * R6 * 8
-        e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
-             "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        e = entry(tc, byts)
+        torch.cuda.synchronize()
+        e["rel_err_vs_oracle_sampled_rows"] = rel_rows(M.cpu().numpy()[list(rows6)], ref6)
         if form != "fp64":
-            torch.cuda.synchronize()
-            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
-            e["rel_err_vs_fp64"] = float((M - M64).norm() / M64.norm())
+            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / tc[0], 3)
         row[form] = e
     print(f"[bench] order-5 60^5 mttkrp mode 4: {row}", file=sys.stderr, flush=True)
     out["mttkrp_order5_last_mode"] = {"workload": "MTTKRP order 5, X 60^5 FP64 (6.2 GB), R=24, mode 4 (last)",
                                       "forms": row}
     del Xf
     tspec = "abcde,bw,cx,dy,ez->awxyz"
-    Y64 = torch.empty((60, R6, R6, R6, R6), dtype=torch.float64, device=dev)
-    Yr = torch.empty_like(Y64)
+    Y = torch.empty((60, R6, R6, R6, R6), dtype=torch.float64, device=dev)
+    slabs6 = (0, 29, 59)
+    ref6t = [oracle.ttmc(synth.x_slab(seed6, D6, 0, i), [None] + Uh[1:], 0)[0] for i in slabs6]
     row = {}
     for form, Xp, Bp in (("fp64", X, U[1:]), ("fp32", X32, U32[1:]), ("bf16", X16, U32[1:])):
-        Y = Y64 if form == "fp64" else Yr
         if tune:
             dn.ttmc(tspec, Xp, Bp, precision=form, out=Y, tune_reps=3)
-        t = event_median(torch, stream, lambda: dn.ttmc(tspec, Xp, Bp, precision=form, out=Y))
+        tc = timed(torch, stream, lambda: dn.ttmc(tspec, Xp, Bp, precision=form, out=Y))
         xb = {"fp64": 8, "fp32": 4, "bf16": 2}[form]
         byts = nx * xb + 4 * 60 * R6 * (8 if form == "fp64" else 4) + 60 * R6 ** 4 * 8
-        e = {"ms": round(t, 4), "GB/s": round(byts / (t / 1e3) / 1e9, 1),
-             "frac_hbm": round(byts / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        e = entry(tc, byts)
+        torch.cuda.synchronize()
+        Yh = Y.cpu().numpy()
+        e["rel_err_vs_oracle_sampled_slabs"] = rel_rows([Yh[i] for i in slabs6], ref6t)
         if form != "fp64":
-            torch.cuda.synchronize()
-            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / t, 3)
-            e["rel_err_vs_fp64"] = float((Y - Y64).norm() / Y64.norm())
+            e["speedup_vs_fp64"] = round(row["fp64"]["ms"] / tc[0], 3)
         row[form] = e
     print(f"[bench] order-5 60^5 ttmc mode 0: {row}", file=sys.stderr, flush=True)
     out["ttmc_order5"] = {"workload": "TTMc order 5 mode 0, X 60^5 FP64 (6.2 GB), ranks 24, N(0,1) factors",
                           "forms": row}
-    del X, X32, X16, Y64, Yr
+    del X, X32, X16, Y
     torch.cuda.empty_cache()
     return out
 
@@ -238,8 +297,101 @@ def alg_counts(dims, R, n, xbytes):
     return byts, flops
 
 
+def _csv_rows(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _col(row, *names):
+    for n in names:
+        if n in row:
+            return row[n]
+    raise KeyError(f"none of {names} in {sorted(row)}")
+
+
+def _short(name):
+    """Kernel name without the return type, namespaces and argument list."""
+    name = re.sub(r"^void ", "", name)
+    name = name.replace("deinsum::(anonymous namespace)::", "").replace("deinsum::", "")
+    return re.sub(r"\((?![^()]*\)\s*$).*$|\([^()]*\)\s*$", "", name).strip()
+
+
+def summarize_trace(path, last, dominant, alg_bytes):
+    """Kernel-time table from a rocprofv3 kernel_trace.csv: per kernel, launches, mean, and
+    the median over the last `last` launches (the steady state of a run whose tuning and
+    warm-up launches come first); for the kernel matching `dominant`, bytes / that median."""
+    rows = _csv_rows(path)
+    per = {}
+    for r in rows:
+        name = _short(_col(r, "Kernel_Name", "KernelName", "Name"))
+        d = (int(_col(r, "End_Timestamp", "EndNs")) - int(_col(r, "Start_Timestamp", "BeginNs"))) / 1e3
+        per.setdefault(name, []).append(d)
+    tot = sum(sum(v) for v in per.values())
+    print(f"{'kernel':<56} {'calls':>6} {'mean us':>9} {'median us':>10} {'steady med':>10} {'min us':>9} {'% time':>7}")
+    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        ss = v[-last:] if last else v
+        print(f"{name[:56]:<56} {len(v):>6} {statistics.mean(v):>9.1f} {statistics.median(v):>10.1f} "
+              f"{statistics.median(ss):>10.1f} {min(v):>9.1f} {100 * sum(v) / tot:>7.2f}")
+    if dominant:
+        hits = [n for n in per if dominant in n]
+        if len(hits) == 1:
+            v = per[hits[0]]
+            ss = v[-last:] if last else v
+            med = statistics.median(ss)
+            print(f"\ndominant kernel: {hits[0]}")
+            print(f"steady-state launches: {len(ss)} (the last {len(ss)} of {len(v)}); median {med:.1f} us")
+            if alg_bytes:
+                gbs = alg_bytes / (med * 1e-6) / 1e9
+                print(f"algorithmic bytes per launch {alg_bytes:.0f} / median = {gbs:.1f} GB/s "
+                      f"= {gbs / HBM_PEAK_GBS:.4f} of {HBM_PEAK_GBS:.0f} GB/s")
+        else:
+            print(f"\ndominant kernel: {len(hits)} names match {dominant!r}: {hits}")
+
+
+def summarize_pmc(path, dominant):
+    """Per-kernel counter table from a rocprofv3 counter_collection.csv: each counter summed
+    per dispatch, then averaged over the dispatches of a kernel.  The runtime's copy kernel
+    (bench.py --copy-probe: 1 GiB read and written) calibrates FETCH_SIZE / WRITE_SIZE."""
+    rows = _csv_rows(path)
+    disp = {}
+    for r in rows:
+        key = (_col(r, "Dispatch_Id", "Dispatch_ID", "dispatch"), _short(_col(r, "Kernel_Name", "KernelName", "Name")))
+        cname = _col(r, "Counter_Name", "CounterName")
+        disp.setdefault(key, {}).setdefault(cname, 0.0)
+        disp[key][cname] += float(_col(r, "Counter_Value", "CounterValue"))
+    per = {}
+    for (_, name), cs in disp.items():
+        for c, v in cs.items():
+            per.setdefault(name, {}).setdefault(c, []).append(v)
+    counters = sorted({c for cs in per.values() for c in cs})
+    print(f"{'kernel':<70} {'n':>4} " + " ".join(f"{c:>14}" for c in counters))
+    for name, cs in sorted(per.items(), key=lambda kv: kv[0]):
+        n = max(len(v) for v in cs.values())
+        print(f"{name[:70]:<70} {n:>4} " + " ".join(f"{statistics.mean(cs[c]) if c in cs else 0.0:>14.1f}"
+                                                    for c in counters))
+    copy = [n for n in per if "copyBuffer" in n]
+    if copy and dominant:
+        gib_kib = float(1 << 20)
+        cs = per[copy[0]]
+        scale = {c: gib_kib / sum(cs[c]) for c in ("FETCH_SIZE", "WRITE_SIZE") if c in cs and sum(cs[c]) > 0}
+        hits = [n for n in per if dominant in n]
+        for h in hits:
+            for c, sc in scale.items():
+                if c in per[h]:
+                    kib = statistics.mean(per[h][c])
+                    print(f"{h[:60]}: {c} {kib:.1f} KiB per dispatch x {sc:.4f} (copy calibration) = "
+                          f"{kib * sc * 1024:.0f} bytes")
+
+
 def main():
     args = parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.last, args.kernel, args.bytes)
+        return
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc, args.kernel)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; sharding across GPUs is not implemented",
                           "n_gpus_requested": args.gpus}))
@@ -284,6 +436,8 @@ def main():
         steps = 0
     ms_step = float("nan")
     per_mode_ms = {0: [], 1: [], 2: []}
+    kernel_ms = {0: [], 1: [], 2: []}   # each call's main kernel alone (library HIP events)
+    step_ms = []
     tune = not args.no_tune
     if steps:
         for n in range(3):
@@ -293,11 +447,20 @@ def main():
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        # The timed region: K steps, bracketed by device synchronisation.  The library
+        # records HIP events around each call's main kernel on the launch stream
+        # (deinsum_kernel_timing), which gives the dominant kernel's own duration.
+        dn.kernel_timing(True, 3 * steps + 16)
         t0 = time.perf_counter()
         for _ in range(steps):
             step()
         torch.cuda.synchronize()
         ms_step = (time.perf_counter() - t0) * 1e3 / steps
+        dn.kernel_timing(False)
+        kt = dn.kernel_times()
+        if len(kt) == 3 * steps:  # one main kernel per call, calls in mode order
+            for i, (_, ms) in enumerate(kt):
+                kernel_ms[i % 3].append(ms)
         # per-call durations with HIP events on the launch stream
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
         for s in range(steps):
@@ -307,6 +470,7 @@ def main():
                 ev[s][n + 1].record(stream)
         torch.cuda.synchronize()
         for s in range(steps):
+            step_ms.append(ev[s][0].elapsed_time(ev[s][3]))
             for n in range(3):
                 per_mode_ms[n].append(ev[s][n].elapsed_time(ev[s][n + 1]))
 
@@ -331,21 +495,38 @@ def main():
     if steps:
         med = {n: statistics.median(per_mode_ms[n]) for n in range(3)}
         gbs = {n: bytes_mode[n] / (med[n] / 1e3) / 1e9 for n in range(3)}
-        # dominant kernel: the longest call of the step, mode 0 (through the fused TTMc pass
-        # unless the tuner picked the K-contiguous kernel); its duration includes the small
-        # kernels of the call (factor padding, partial reduction, diagonal)
+        result["step_ms_event"] = {"median": round(statistics.median(step_ms), 4), "ci95": boot_ci(step_ms)}
+        # Dominant kernel: the main kernel of the step's longest call, mode 0 (the fused
+        # TTMc pass unless the tuner picked the K-contiguous kernel); its duration is the
+        # median over the timed steps of the library's HIP events around that kernel.
         plan0 = reports[0].plan_name.decode()
-        dom_gbs = bytes_mode[0] / (med[0] / 1e3) / 1e9
-        kname = ("ttmc_fused_kernel (MTTKRP mode 0 through the fused TTMc pass" if plan0.startswith("mttkrp_via_ttmc")
-                 else "mttkrp_stream_kernel (K-contiguous MTTKRP, mode 0")
+        kname = ("ttmc_fused_kernel (MTTKRP mode 0 through the fused TTMc pass)" if plan0.startswith("mttkrp_via_ttmc")
+                 else "mttkrp_stream_kernel (K-contiguous MTTKRP, mode 0)")
+        if kernel_ms[0]:
+            k0 = statistics.median(kernel_ms[0])
+            how = ("median over the timed steps of the kernel's own duration, HIP events recorded by the "
+                   "library on the launch stream around that kernel")
+        else:
+            k0 = med[0]
+            how = "median call duration (HIP events around the whole call)"
+        dom_gbs = bytes_mode[0] / (k0 / 1e3) / 1e9
         result["roofline"] = {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                               "traffic": measured_traffic(plan0),
-                              "kernel": kname + "; call duration from HIP events on the launch stream)"}
-        result["modes"] = {str(n): {"ms": round(med[n], 4), "GB/s": round(gbs[n], 1),
-                                     "frac_hbm": round(gbs[n] / HBM_PEAK_GBS, 4),
-                                     "GFLOP/s": round(alg_counts(DIMS, R, n, 8)[1] / (med[n] / 1e3) / 1e9, 1),
-                                     "plan": reports[n].plan_name.decode()} for n in range(3)}
+                              "kernel": kname, "kernel_ms": round(k0, 4),
+                              "kernel_ms_ci95": boot_ci(kernel_ms[0]) if kernel_ms[0] else None,
+                              "alg_bytes_per_launch": bytes_mode[0], "duration": how}
+        result["modes"] = {}
+        for n in range(3):
+            e = {"ms": round(med[n], 4), "ci95_ms": boot_ci(per_mode_ms[n]), "GB/s": round(gbs[n], 1),
+                 "frac_hbm": round(gbs[n] / HBM_PEAK_GBS, 4),
+                 "GFLOP/s": round(alg_counts(DIMS, R, n, 8)[1] / (med[n] / 1e3) / 1e9, 1),
+                 "plan": reports[n].plan_name.decode()}
+            if kernel_ms[n]:
+                km = statistics.median(kernel_ms[n])
+                e["kernel_ms"] = round(km, 4)
+                e["kernel_frac_hbm"] = round(bytes_mode[n] / (km / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+            result["modes"][str(n)] = e
 
     # ---- parity spot check of the timed outputs (sampled rows against the oracle)
     import oracle
@@ -373,13 +554,20 @@ def main():
         Xf = None
         forms_all = ("fx20", "fp32", "bf16x3", "bf16")
         todo = list(forms_all) if not args.only else ([args.only] if args.only in forms_all else [])
+        # One-off cost of storing X in each form's storage (paid once per tensor, then
+        # amortised over modes and sweeps): median of 3 event-timed conversions.
+        storage_ms = {}
+        if todo:
+            storage_ms["f32"] = timed(torch, stream, lambda: dn.convert(X, X32), 3)
         for prec in todo:
             if prec == "bf16" and Xb is None:
                 Xb = torch.empty(DIMS, dtype=torch.bfloat16, device=dev)
-                dn.convert(X, Xb)
+                storage_ms["bf16"] = timed(torch, stream, lambda: dn.convert(X, Xb), 3)
             if prec == "fx20" and Xf is None:
+                storage_ms["fx20"] = timed(torch, stream, lambda: dn.to_fx20(X), 3)
                 Xf = dn.to_fx20(X)
             Xp = Xb if prec == "bf16" else (Xf if prec == "fx20" else X32)
+            skey = {"bf16": "bf16", "fx20": "fx20"}.get(prec, "f32")
             modes = [0, 1, 2]
             o32 = {n: torch.empty((DIMS[n], R), dtype=torch.float32, device=dev) for n in modes}
             if tune:
@@ -388,31 +576,34 @@ def main():
             preps = {n: dn.Report() for n in modes}
             for n in modes:
                 dn.mttkrp(SPECS[n], Xp, opsf[n], precision=prec, out=o32[n], report=preps[n])
-            for _ in range(2):
-                for n in modes:
-                    dn.mttkrp(SPECS[n], Xp, opsf[n], precision=prec, out=o32[n])
             torch.cuda.synchronize()
             res = {}
             for n in modes:
-                evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
-                evs[0].record(stream)
-                for k in range(10):
-                    dn.mttkrp(SPECS[n], Xp, opsf[n], precision=prec, out=o32[n])
-                    evs[k + 1].record(stream)
-                torch.cuda.synchronize()
-                t = statistics.median(evs[k].elapsed_time(evs[k + 1]) for k in range(10))
+                t, ci = timed(torch, stream, lambda: dn.mttkrp(SPECS[n], Xp, opsf[n], precision=prec, out=o32[n]))
                 xb = {"bf16": 2, "fx20": 3}.get(prec, 4)
                 b, f = alg_counts(DIMS, R, n, xb)
-                res[str(n)] = {"ms": round(t, 4), "GB/s": round(b / (t / 1e3) / 1e9, 1),
+                res[str(n)] = {"ms": round(t, 4), "ci95_ms": ci, "GB/s": round(b / (t / 1e3) / 1e9, 1),
                                "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                               "GFLOP/s": round(f / (t / 1e3) / 1e9, 1), "plan": preps[n].plan_name.decode()}
+                               "GFLOP/s": round(f / (t / 1e3) / 1e9, 1), "plan": preps[n].plan_name.decode(),
+                               "est_err": preps[n].est_err}
                 if steps:
                     res[str(n)]["speedup_vs_fp64"] = round(med[n] / t, 3)
             err = sampled_error(o32)
+            st_ms = storage_ms[skey][0]
             forms[prec] = {"x_storage": {"bf16": "bf16", "fx20": "fx20 (20-bit fixed point: FP16 + int8 planes, 3 bytes)"}.get(prec, "f32"),
+                           "storage_conversion_ms": round(st_ms, 4),
+                           "storage_conversion_ci95_ms": storage_ms[skey][1],
                            "modes": res,
                            "max_rel_err_sampled_vs_fp64_oracle": err}
-            print(f"[bench] {prec}: {res} err {err:.2e}", file=sys.stderr, flush=True)
+            if steps:
+                # speedup of one 3-mode step with the conversion paid once in it, and the
+                # number of steps after which the form has paid for its conversion
+                t_form = sum(res[str(n)]["ms"] for n in modes)
+                t64 = sum(med[n] for n in modes)
+                forms[prec]["step_speedup_incl_conversion"] = round(t64 / (t_form + st_ms), 3)
+                forms[prec]["steps_to_amortise_conversion"] = (round(st_ms / (t64 - t_form), 2)
+                                                               if t64 > t_form else None)
+            print(f"[bench] {prec}: {res} err {err:.2e} conversion {st_ms:.3f} ms", file=sys.stderr, flush=True)
         if forms:
             result["mixed_forms"] = forms
         del X32, Xb, Xf
@@ -424,27 +615,19 @@ def main():
             Y = torch.empty((1024, Rt, Rt), dtype=torch.float64, device=dev)
             if tune:
                 dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y, tune_reps=7)
-            for _ in range(2):
-                dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y)
-            evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
-            evs[0].record(stream)
-            for k in range(10):
-                dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y)
-                evs[k + 1].record(stream)
-            torch.cuda.synchronize()
-            t = statistics.median(evs[k].elapsed_time(evs[k + 1]) for k in range(10))
+            t, ci = timed(torch, stream, lambda: dn.ttmc("ijk,jb,kc->ibc", X, Bt, out=Y))
             nx = 1024 ** 3
             b = nx * 8 + 2 * 1024 * Rt * 8 + 1024 * Rt * Rt * 8
             f = 2 * nx * Rt + 2 * 1024 * 1024 * Rt * Rt
             Bh = [None] + [b_.cpu().numpy() for b_ in Bt]
-            errs = []
-            for i in (5, 999):
-                ref = oracle.ttmc(synth.x_slab(seed, DIMS, 0, i), Bh, 0)[0]
-                errs.append(float(np.linalg.norm(Y[i].cpu().numpy() - ref) / np.linalg.norm(ref)))
+            tslabs = (5, 512, 999)
+            tref = [oracle.ttmc(synth.x_slab(seed, DIMS, 0, i), Bh, 0)[0] for i in tslabs]
+            torch.cuda.synchronize()
             result["ttmc"] = {"workload": "TTMc order 3 mode 0, X 1024^3 FP64, B and C 1024x32 orthonormal",
-                              "ms": round(t, 4), "GB/s": round(b / (t / 1e3) / 1e9, 1),
+                              "ms": round(t, 4), "ci95_ms": ci, "GB/s": round(b / (t / 1e3) / 1e9, 1),
                               "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                              "GFLOP/s": round(f / (t / 1e3) / 1e9, 1), "max_rel_err_sampled": max(errs)}
+                              "GFLOP/s": round(f / (t / 1e3) / 1e9, 1),
+                              "max_rel_err_sampled": rel_rows([Y[i].cpu().numpy() for i in tslabs], tref)}
             # reduced-precision forms of the same TTMc: X stored FP32 / BF16, FP32 factors
             tforms = {}
             B32 = [b_.float() for b_ in Bt]
@@ -454,14 +637,15 @@ def main():
                 Yt = torch.empty_like(Y)
                 if tune:
                     dn.ttmc("ijk,jb,kc->ibc", Xt, B32, precision=form, out=Yt, tune_reps=7)
-                tt = event_median(torch, stream, lambda: dn.ttmc("ijk,jb,kc->ibc", Xt, B32, precision=form, out=Yt))
+                tt, tci = timed(torch, stream, lambda: dn.ttmc("ijk,jb,kc->ibc", Xt, B32, precision=form, out=Yt))
                 xb = 4 if form == "fp32" else 2
                 bt = nx * xb + 2 * 1024 * Rt * 4 + 1024 * Rt * Rt * 8
                 torch.cuda.synchronize()
-                tforms[form] = {"ms": round(tt, 4), "GB/s": round(bt / (tt / 1e3) / 1e9, 1),
+                tforms[form] = {"ms": round(tt, 4), "ci95_ms": tci, "GB/s": round(bt / (tt / 1e3) / 1e9, 1),
                                 "frac_hbm": round(bt / (tt / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                                 "speedup_vs_fp64": round(t / tt, 3),
-                                "rel_err_vs_fp64": float((Yt - Y).norm() / Y.norm())}
+                                "rel_err_vs_oracle_sampled_slabs": rel_rows([Yt[i].cpu().numpy() for i in tslabs],
+                                                                            tref)}
                 del Xt, Yt
                 torch.cuda.empty_cache()
             result["ttmc"]["forms"] = tforms
@@ -484,29 +668,50 @@ def main():
             log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
 
     # ---- CPU oracle on a bounded sample of the same workload: all three modes over
-    # 64-row slabs of a 1024^3 X until about BENCH_CPU_SECONDS of oracle time.
+    # 64-row slabs of the benchmark's own X (the same counter-based values the GPU read,
+    # drawn in host RAM; generation not timed) until about BENCH_CPU_SECONDS of oracle time.
     if not args.no_cpu:
         budget = float(os.environ.get("BENCH_CPU_SECONDS", "12"))
-        rng = np.random.default_rng(2206083010)
         t, rows, f = 0.0, 0, 0
+        slab = DIMS[1] * DIMS[2]
         while rows < DIMS[0] and t < budget:
-            # Same shape and distribution as the GPU's X; drawn with numpy's PCG64 because the
-            # counter generator runs at a few million values per second in numpy.
-            Xs = rng.uniform(-1.0, 1.0, (64, DIMS[1], DIMS[2]))
+            Xs = synth.x_range(seed, rows * slab, 64 * slab).reshape(64, DIMS[1], DIMS[2])
             for n in range(3):
-                Un = [None if m == n else U[m][:64] if m == 0 else U[m] for m in range(3)]
+                Un = [None if m == n else U[m][rows:rows + 64] if m == 0 else U[m] for m in range(3)]
                 t0 = time.perf_counter()
                 oracle.mttkrp(Xs, Un, n)
                 t += time.perf_counter() - t0
                 f += alg_counts((64, DIMS[1], DIMS[2]), R, n, 8)[1]
             rows += 64
             del Xs
+        # The 64^3 R=16 mode-0 workload on one thread (median of 3 runs, own process so
+        # that OpenMP starts with one thread).
+        single = None
+        try:
+            import subprocess
+            code = ("import time, statistics, sys; sys.path.insert(0, %r); import oracle; "
+                    "from paper_2206_08301_amd import synth; "
+                    "X = synth.x_tensor(synth.config_seed(1, 0), (64, 64, 64)); "
+                    "U = [None] + [synth.normal_factor(synth.config_seed(1, 1 + m), 64, 16) for m in (1, 2)]; "
+                    "ts = []\n"
+                    "for _ in range(3):\n"
+                    "    t0 = time.perf_counter(); oracle.mttkrp(X, U, 0); ts.append(time.perf_counter() - t0)\n"
+                    "print(oracle.num_threads(), statistics.median(ts))") % ROOT
+            env = dict(os.environ, OMP_NUM_THREADS="1")
+            r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=120)
+            th, sec = r.stdout.split()[-2:]
+            flops1 = alg_counts((64, 64, 64), 16, 0, 8)[1]
+            single = {"workload": "MTTKRP order 3, X 64^3 FP64, R=16, mode 0", "threads": int(th),
+                      "ms": round(float(sec) * 1e3, 3), "GFLOP/s": round(flops1 / float(sec) / 1e9, 3)}
+        except Exception as exc:  # reported, not fatal: the baseline above stands on its own
+            single = {"error": str(exc)[:200]}
         result["cpu_baseline"] = {"value": round(f / t / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-                                  "kind": "oracle",
+                                  "kind": "oracle", "cpu_model": cpu_model(),
                                   "sample": f"MTTKRP modes 0, 1 and 2 of the 1024^3 R=24 FP64 step restricted to "
-                                            f"{rows} of the 1024 mode-0 slices (64 at a time, X uniform [-1,1) in "
-                                            f"host RAM, generation excluded), {t:.1f} s of oracle time; flops "
-                                            f"counted as for the GPU"}
+                                            f"{rows} of the 1024 mode-0 slices (64 at a time; X the benchmark's "
+                                            f"own counter-based values, drawn in host RAM, generation excluded), "
+                                            f"{t:.1f} s of oracle time; flops counted as for the GPU",
+                                  "single_thread_small": single}
     print(json.dumps(result), flush=True)
 
 

@@ -625,6 +625,19 @@ deinsum_status deinsum_tune_clear(void);
 /* Number of cached plans. */
 deinsum_status deinsum_tune_entries(int64_t *entries);
 
+/*
+ * Kernel timing, for measurement.  With enable = 1 (capacity 1..2^20 launches) the
+ * main kernel of every later MTTKRP / TTMc call -- the streaming MTTKRP kernel
+ * (kind 1) or the fused TTMc pass (kind 2), whichever the plan launches -- is
+ * bracketed by two HIP events on the call's stream, so its own duration is known
+ * apart from the call's small set-up and reduction kernels; launches past the
+ * capacity are not recorded.  enable = 0 stops recording.  deinsum_kernel_times
+ * waits for the recorded events, copies up to max_n (kind, milliseconds) pairs in
+ * launch order into the host arrays, sets *n and forgets the records.
+ */
+deinsum_status deinsum_kernel_timing(int32_t enable, int64_t capacity);
+deinsum_status deinsum_kernel_times(int64_t max_n, int32_t *kind, double *ms, int64_t *n);
+
 /* Release the library's device workspace pools and plan caches. */
 deinsum_status deinsum_shutdown(void);
 

@@ -540,6 +540,23 @@ def convert(src: torch.Tensor, dst: torch.Tensor, stream=None):
     return dst
 
 
+KERNEL_KINDS = {1: "mttkrp_stream_kernel", 2: "ttmc_fused_kernel"}
+
+
+def kernel_timing(enable: bool, capacity: int = 4096):
+    """Start (or stop) HIP-event timing of each call's main kernel (deinsum_kernel_timing)."""
+    _lib.check(_lib.load().deinsum_kernel_timing(int(bool(enable)), int(capacity)))
+
+
+def kernel_times(max_n: int = 1 << 16):
+    """[(kernel kind name, ms)] of the recorded launches, in launch order (synchronising)."""
+    kinds = (ctypes.c_int32 * max_n)()
+    ms = (ctypes.c_double * max_n)()
+    n = ctypes.c_int64(0)
+    _lib.check(_lib.load().deinsum_kernel_times(int(max_n), kinds, ms, ctypes.byref(n)))
+    return [(KERNEL_KINDS.get(kinds[i], str(kinds[i])), ms[i]) for i in range(n.value)]
+
+
 def shutdown():
     _lib.check(_lib.load().deinsum_shutdown())
 

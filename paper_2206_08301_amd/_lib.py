@@ -119,6 +119,7 @@ EXPORTS = (
     "deinsum_fx20_size", "deinsum_fx20_encode", "deinsum_tune_ttmc", "deinsum_mttkrp_mm",
     "deinsum_mttkrp_noalloc", "deinsum_estimate_error", "deinsum_choose_storage", "deinsum_tensor_stats",
     "deinsum_server_poll", "deinsum_decomp_opts_init", "deinsum_cp_als", "deinsum_tucker_hooi",
+    "deinsum_kernel_timing", "deinsum_kernel_times",
 )
 
 _lib = None
@@ -198,6 +199,10 @@ def load():
     lib.deinsum_server_drain.restype = ctypes.c_int
     lib.deinsum_server_results.argtypes = [vp, ctypes.c_int64, f64p, f64p, i64p]
     lib.deinsum_server_results.restype = ctypes.c_int
+    lib.deinsum_kernel_timing.argtypes = [ctypes.c_int32, ctypes.c_int64]
+    lib.deinsum_kernel_timing.restype = ctypes.c_int
+    lib.deinsum_kernel_times.argtypes = [ctypes.c_int64, i32p, f64p, i64p]
+    lib.deinsum_kernel_times.restype = ctypes.c_int
     lib.deinsum_decomp_opts_init.argtypes = [ctypes.POINTER(DecompOpts)]
     lib.deinsum_decomp_opts_init.restype = None
     lib.deinsum_cp_als.argtypes = [ctypes.c_int32, i64p, ctypes.c_int64, vp, ctypes.POINTER(vp), vp,

@@ -497,7 +497,10 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
         a.W = W;
         a.ldw = cols_pad;
         if (deinsum_status st = launch_outer_weights(a.od, a.O, pb.R, ncols, cols_pad, pb.prec, W, s)) return st;
-        if (deinsum_status st = launch_mttkrp_stream(*p.kernel, a, p.groups, p.waves, s)) return st;
+        const int kt = ktimer_begin(s, KK_MTTKRP_STREAM);
+        const deinsum_status lst = launch_mttkrp_stream(*p.kernel, a, p.groups, p.waves, s);
+        ktimer_end(kt, s);
+        if (lst) return lst;
         if (deinsum_status st = launch_reduce_partials(a.P, p.parts, p.n_tiles, p.tile_rows, cols_pad, pb.dims[n],
                                                        ncols, static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
                                                        c.out_dtype, pb.R, hx, nx, s))

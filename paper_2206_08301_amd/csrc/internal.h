@@ -23,6 +23,13 @@ deinsum_status pool_get(size_t bytes, void **out);
 // synchronises `stream`.
 deinsum_status fx20_storage_error(const void *X, int64_t count, void *stream, double *err);
 
+// Live kernel timing (ktimer.cpp, deinsum_kernel_timing): ktimer_begin records the
+// start event of the next main-kernel launch on `stream` (a hipStream_t) and
+// returns its slot (-1 when timing is off or full); ktimer_end records the stop.
+enum KernelKind { KK_MTTKRP_STREAM = 1, KK_TTMC_FUSED = 2 };
+int ktimer_begin(void *stream, int kind);
+void ktimer_end(int slot, void *stream);
+
 // Einsum parser (parse.cpp).
 deinsum_status parse_spec(const char *text, deinsum_spec *out);
 

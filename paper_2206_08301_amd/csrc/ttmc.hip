@@ -382,11 +382,16 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                                 lds[w * TA * TC + (ta * 16 + c) * TC + tc * 16 + tile_row<P>(lane, v)] =
                                     static_cast<double>(z[tc][ta][v]);
                     __syncthreads();
-                    for (int i = threadIdx.x; i < zn; i += 64 * a.nwaves) {
-                        const int j = (i / a.rc) * TC + i % a.rc;
-                        double acc = lds[j];
-                        for (int ww = 1; ww < a.nwaves; ++ww) acc += lds[ww * TA * TC + j];
-                        out[i] = acc;
+                    // Thread t sums column t % TC of rows t / TC, + 4 nwaves / NTC, ...: no
+                    // runtime divisions (TC is a compile-time power of two).
+                    for (int ra = static_cast<int>(threadIdx.x) / TC; ra < a.ra; ra += 64 * a.nwaves / TC) {
+                        const int col = static_cast<int>(threadIdx.x) % TC;
+                        if (col < a.rc) {
+                            const int j = ra * TC + col;
+                            double acc = lds[j];
+                            for (int ww = 1; ww < a.nwaves; ++ww) acc += lds[ww * TA * TC + j];
+                            out[ra * a.rc + col] = acc;
+                        }
                     }
                 } else {
                     for (int ww = 0; ww < a.nwaves; ++ww) {
@@ -404,7 +409,10 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                         }
                         __syncthreads();
                     }
-                    for (int i = threadIdx.x; i < zn; i += 64 * a.nwaves) out[i] = lds[(i / a.rc) * TC + i % a.rc];
+                    for (int ra = static_cast<int>(threadIdx.x) / TC; ra < a.ra; ra += 64 * a.nwaves / TC) {
+                        const int col = static_cast<int>(threadIdx.x) % TC;
+                        if (col < a.rc) out[ra * a.rc + col] = lds[ra * TC + col];
+                    }
                 }
                 __syncthreads();
             } else {
@@ -500,8 +508,11 @@ __global__ void __launch_bounds__(256) reduce_strided_kernel(const ReduceArgs a)
 }
 
 // One mode product on an FP64 intermediate with a strided destination.  A thread
-// computes kTtmRB consecutive ranks of one output fibre, reading each input value once.
-constexpr int kTtmRB = 8;
+// computes RB consecutive ranks of one output fibre, reading each input value once;
+// RB is the rank rounded up to 8, 16, 24 or 32 (8 beyond that), so for ranks up to 32
+// every input fibre is read by one thread only.
+constexpr int kTtmRB = 8;  // granularity of RB
+int ttm_rb(int64_t r) { return r <= 32 ? static_cast<int>((r + 7) / 8 * 8) : 8; }
 struct SmallTtmArgs {
     const double *T;
     int nd;
@@ -513,20 +524,21 @@ struct SmallTtmArgs {
     const void *U;
     int64_t ldu;
     int uprec;
-    int64_t total;                    // threads: product of odim with dim m counted in blocks of kTtmRB
+    int64_t total;                    // threads: product of odim with dim m counted in blocks of RB
     void *out;
     int out_dtype;
     int lds;                          // 1: U staged in LDS (dynamic shared memory)
 };
 
-// Largest factor (rows x ranks rounded up to kTtmRB, FP64) staged in LDS per workgroup.
+// Largest factor (rows x ranks rounded up to RB, FP64) staged in LDS per workgroup.
 constexpr size_t kTtmLdsBytes = 48 * 1024;
 
+template <int RB, bool LDS>
 __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
 {
-    extern __shared__ double su[];  // U as FP64, row stride ldl = ranks rounded up to kTtmRB (0 = not staged)
-    const int64_t ldl = (a.odim[a.m] + kTtmRB - 1) / kTtmRB * kTtmRB;
-    if (a.lds) {
+    extern __shared__ double su[];  // LDS: U as FP64, row stride ldl = ranks rounded up to RB
+    const int64_t ldl = (a.odim[a.m] + RB - 1) / RB * RB;
+    if constexpr (LDS) {
         for (int64_t i = threadIdx.x; i < a.Im * ldl; i += blockDim.x) {
             const int64_t row = i / ldl, r = i % ldl;
             su[i] = r < a.odim[a.m] ? ldu_p(a.U, row * a.ldu + r, a.uprec) : 0.0;
@@ -537,68 +549,64 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
     if (e >= a.total) return;
     int64_t rem = e, ioff = 0, ooff = 0, r0 = 0;
     for (int d = a.nd - 1; d >= 0; --d) {
-        const int64_t ext = (d == a.m) ? (a.odim[d] + kTtmRB - 1) / kTtmRB : a.odim[d];
+        const int64_t ext = (d == a.m) ? (a.odim[d] + RB - 1) / RB : a.odim[d];
         const int64_t i = rem % ext;
         rem /= ext;
         if (d == a.m) {
-            r0 = i * kTtmRB;
+            r0 = i * RB;
         } else {
             ooff += i * a.ostr[d];
             ioff += i * a.tstr[d];
         }
     }
-    const int nr = static_cast<int>(tmin(kTtmRB, a.odim[a.m] - r0));
-    double acc[kTtmRB];
+    const int nr = static_cast<int>(tmin(RB, a.odim[a.m] - r0));
+    double acc[RB];
 #pragma unroll
-    for (int q = 0; q < kTtmRB; ++q) acc[q] = 0.0;
-    // Unconditional loads (ranks past the last are clamped and their sums dropped), so
-    // the loads of an unrolled step are all in flight together.
-    int64_t col[kTtmRB];
-#pragma unroll
-    for (int q = 0; q < kTtmRB; ++q) col[q] = r0 + (q < nr ? q : 0);
-    auto body = [&](const auto *U) {
-        const int64_t sm = a.tstr[a.m];
-        int64_t i = 0;
-        for (; i + 8 <= a.Im; i += 8) {
-            double t[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) t[k] = a.T[ioff + (i + k) * sm];
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-#pragma unroll
-                for (int q = 0; q < kTtmRB; ++q) acc[q] += t[k] * static_cast<double>(U[(i + k) * a.ldu + col[q]]);
-        }
-        for (; i < a.Im; ++i) {
-            const double t = a.T[ioff + i * sm];
-#pragma unroll
-            for (int q = 0; q < kTtmRB; ++q) acc[q] += t * static_cast<double>(U[i * a.ldu + col[q]]);
-        }
-    };
-    if (a.lds) {
+    for (int q = 0; q < RB; ++q) acc[q] = 0.0;
+    const int64_t sm = a.tstr[a.m];
+    if constexpr (LDS) {
         // every rank of the block is staged (zero past the last): no clamping needed
-        const int64_t sm = a.tstr[a.m];
         int64_t i = 0;
         for (; i + 8 <= a.Im; i += 8) {
-            double t[8];
+            double t[8];  // eight loads in flight per thread
 #pragma unroll
             for (int k = 0; k < 8; ++k) t[k] = a.T[ioff + (i + k) * sm];
 #pragma unroll
             for (int k = 0; k < 8; ++k)
 #pragma unroll
-                for (int q = 0; q < kTtmRB; ++q) acc[q] += t[k] * su[(i + k) * ldl + r0 + q];
+                for (int q = 0; q < RB; ++q) acc[q] += t[k] * su[(i + k) * ldl + r0 + q];
         }
         for (; i < a.Im; ++i) {
             const double t = a.T[ioff + i * sm];
 #pragma unroll
-            for (int q = 0; q < kTtmRB; ++q) acc[q] += t * su[i * ldl + r0 + q];
+            for (int q = 0; q < RB; ++q) acc[q] += t * su[i * ldl + r0 + q];
         }
-    } else if (a.uprec == P_FP64) {
-        body(static_cast<const double *>(a.U));
     } else {
-        body(static_cast<const float *>(a.U));
+        // Factor read from global memory; ranks past the last are clamped (their sums dropped),
+        // so the loads of an unrolled step are unconditional.
+        auto body = [&](const auto *U) {
+            int64_t i = 0;
+            for (; i + 8 <= a.Im; i += 8) {
+                double t[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) t[k] = a.T[ioff + (i + k) * sm];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+#pragma unroll
+                    for (int q = 0; q < RB; ++q)
+                        acc[q] += t[k] * static_cast<double>(U[(i + k) * a.ldu + r0 + (q < nr ? q : 0)]);
+            }
+            for (; i < a.Im; ++i) {
+                const double t = a.T[ioff + i * sm];
+#pragma unroll
+                for (int q = 0; q < RB; ++q) acc[q] += t * static_cast<double>(U[i * a.ldu + r0 + (q < nr ? q : 0)]);
+            }
+        };
+        if (a.uprec == P_FP64) body(static_cast<const double *>(a.U));
+        else body(static_cast<const float *>(a.U));
     }
 #pragma unroll
-    for (int q = 0; q < kTtmRB; ++q) {
+    for (int q = 0; q < RB; ++q) {
         if (q >= nr) break;
         const int64_t o = ooff + (r0 + q) * a.ostr[a.m];
         if (a.out_dtype == DEINSUM_F64) static_cast<double *>(a.out)[o] = acc[q];
@@ -922,7 +930,9 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     a.xcd_remap = 1;
     a.n_groups = p.groups;
     a.P = P;
+    const int kt = ktimer_begin(s, KK_TTMC_FUSED);
     p.kernel->fn(a, p.groups, s);
+    ktimer_end(kt, s);
     if (deinsum_status st = check_launch("ttmc_fused")) return st;
 
     // ---- logical dims of the intermediate: slab modes, then (a, c) or (n, a)
@@ -1006,12 +1016,15 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
             st *= sext[d];
         }
         cur[pos].extent = p.Rm[m];
+        // Whole rank range per thread when its factor fits in LDS; else blocks of 8.
+        int rb = ttm_rb(p.Rm[m]);
+        if (static_cast<size_t>(p.I[m] * cdivl(p.Rm[m], rb) * rb) * 8 > kTtmLdsBytes) rb = kTtmRB;
         int64_t nout = 1;
         t.total = 1;
         for (int d = 0; d < t.nd; ++d) {
             t.odim[d] = cur[d].extent;
             nout *= cur[d].extent;
-            t.total *= (d == pos) ? cdivl(cur[d].extent, kTtmRB) : cur[d].extent;
+            t.total *= (d == pos) ? cdivl(cur[d].extent, rb) : cur[d].extent;
             sext[d] = cur[d].extent;
         }
         if (!last && static_cast<size_t>(nout) * 8 > p.t_bytes)
@@ -1031,9 +1044,14 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         t.uprec = o.precision == P_FP64 ? P_FP64 : P_FP32;  // factor storage
         t.out = dst;
         t.out_dtype = last ? o.out_dtype : DEINSUM_F64;
-        const size_t ubytes = static_cast<size_t>(t.Im * cdivl(p.Rm[m], kTtmRB) * kTtmRB) * 8;
+        const size_t ubytes = static_cast<size_t>(t.Im * cdivl(p.Rm[m], rb) * rb) * 8;
         t.lds = ubytes <= kTtmLdsBytes;
-        small_ttm_kernel<<<static_cast<unsigned>(cdivl(t.total, 256)), 256, t.lds ? ubytes : 0, s>>>(t);
+        const unsigned tg = static_cast<unsigned>(cdivl(t.total, 256));
+        if (!t.lds) small_ttm_kernel<8, false><<<tg, 256, 0, s>>>(t);
+        else if (rb == 8) small_ttm_kernel<8, true><<<tg, 256, ubytes, s>>>(t);
+        else if (rb == 16) small_ttm_kernel<16, true><<<tg, 256, ubytes, s>>>(t);
+        else if (rb == 24) small_ttm_kernel<24, true><<<tg, 256, ubytes, s>>>(t);
+        else small_ttm_kernel<32, true><<<tg, 256, ubytes, s>>>(t);
         if (deinsum_status st2 = check_launch("ttmc_small_ttm")) return st2;
         src = static_cast<const double *>(dst);
     }
