@@ -198,17 +198,18 @@ def more_workloads(dn, synth, torch, stream, tune):
     dn.convert(X, X32)
     X16 = torch.empty(D4, dtype=torch.bfloat16, device=dev)
     dn.convert(X, X16)
+    Xf = dn.to_fx20(X)
     Y = torch.empty((192, R4, R4, R4), dtype=torch.float64, device=dev)
     slabs4 = (0, 77, 191)
     ref4 = [oracle.ttmc(synth.x_slab(seed4, D4, 0, i), [None] + Bh, 0)[0] for i in slabs4]
     row = {}
     nx = 192 ** 4
     B32 = [b.float() for b in B]
-    for form, Xp, Bp in (("fp64", X, B), ("fp32", X32, B32), ("bf16", X16, B32)):
+    for form, Xp, Bp in (("fp64", X, B), ("fp32", X32, B32), ("bf16", X16, B32), ("fx20", Xf, B32)):
         if tune:
             dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y, tune_reps=2)
         tc = timed(torch, stream, lambda: dn.ttmc("abcd,bx,cy,dz->axyz", Xp, Bp, precision=form, out=Y))
-        xb = {"fp64": 8, "fp32": 4, "bf16": 2}[form]
+        xb = {"fp64": 8, "fp32": 4, "bf16": 2, "fx20": 3}[form]
         byts = nx * xb + 3 * 192 * R4 * (8 if form == "fp64" else 4) + 192 * R4 ** 3 * 8
         e = entry(tc, byts)
         torch.cuda.synchronize()
@@ -220,7 +221,7 @@ def more_workloads(dn, synth, torch, stream, tune):
     print(f"[bench] ttmc order-4: {row}", file=sys.stderr, flush=True)
     out["ttmc_order4"] = {"workload": "TTMc order 4 mode 0, X 192^4 FP64 (10.9 GB), ranks 16, orthonormal factors",
                           "forms": row}
-    del X, X32, X16, Y
+    del X, X32, X16, Xf, Y
     torch.cuda.empty_cache()
 
     # The paper's order-5 forms at I = 60, R = 24: MTTKRP in the last mode, TTMc in mode 0.
@@ -257,17 +258,16 @@ def more_workloads(dn, synth, torch, stream, tune):
     print(f"[bench] order-5 60^5 mttkrp mode 4: {row}", file=sys.stderr, flush=True)
     out["mttkrp_order5_last_mode"] = {"workload": "MTTKRP order 5, X 60^5 FP64 (6.2 GB), R=24, mode 4 (last)",
                                       "forms": row}
-    del Xf
     tspec = "abcde,bw,cx,dy,ez->awxyz"
     Y = torch.empty((60, R6, R6, R6, R6), dtype=torch.float64, device=dev)
     slabs6 = (0, 29, 59)
     ref6t = [oracle.ttmc(synth.x_slab(seed6, D6, 0, i), [None] + Uh[1:], 0)[0] for i in slabs6]
     row = {}
-    for form, Xp, Bp in (("fp64", X, U[1:]), ("fp32", X32, U32[1:]), ("bf16", X16, U32[1:])):
+    for form, Xp, Bp in (("fp64", X, U[1:]), ("fp32", X32, U32[1:]), ("bf16", X16, U32[1:]), ("fx20", Xf, U32[1:])):
         if tune:
             dn.ttmc(tspec, Xp, Bp, precision=form, out=Y, tune_reps=3)
         tc = timed(torch, stream, lambda: dn.ttmc(tspec, Xp, Bp, precision=form, out=Y))
-        xb = {"fp64": 8, "fp32": 4, "bf16": 2}[form]
+        xb = {"fp64": 8, "fp32": 4, "bf16": 2, "fx20": 3}[form]
         byts = nx * xb + 4 * 60 * R6 * (8 if form == "fp64" else 4) + 60 * R6 ** 4 * 8
         e = entry(tc, byts)
         torch.cuda.synchronize()
@@ -279,7 +279,7 @@ def more_workloads(dn, synth, torch, stream, tune):
     print(f"[bench] order-5 60^5 ttmc mode 0: {row}", file=sys.stderr, flush=True)
     out["ttmc_order5"] = {"workload": "TTMc order 5 mode 0, X 60^5 FP64 (6.2 GB), ranks 24, N(0,1) factors",
                           "forms": row}
-    del X, X32, X16, Y
+    del X, X32, X16, Xf, Y
     torch.cuda.empty_cache()
     return out
 
@@ -631,14 +631,17 @@ def main():
             # reduced-precision forms of the same TTMc: X stored FP32 / BF16, FP32 factors
             tforms = {}
             B32 = [b_.float() for b_ in Bt]
-            for form, tdt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
-                Xt = torch.empty(DIMS, dtype=tdt, device=dev)
-                dn.convert(X, Xt)
+            for form, tdt in (("fp32", torch.float32), ("bf16", torch.bfloat16), ("fx20", None)):
+                if form == "fx20":
+                    Xt = dn.to_fx20(X)
+                else:
+                    Xt = torch.empty(DIMS, dtype=tdt, device=dev)
+                    dn.convert(X, Xt)
                 Yt = torch.empty_like(Y)
                 if tune:
                     dn.ttmc("ijk,jb,kc->ibc", Xt, B32, precision=form, out=Yt, tune_reps=7)
                 tt, tci = timed(torch, stream, lambda: dn.ttmc("ijk,jb,kc->ibc", Xt, B32, precision=form, out=Yt))
-                xb = 4 if form == "fp32" else 2
+                xb = {"fp32": 4, "bf16": 2, "fx20": 3}[form]
                 bt = nx * xb + 2 * 1024 * Rt * 4 + 1024 * Rt * Rt * 8
                 torch.cuda.synchronize()
                 tforms[form] = {"ms": round(tt, 4), "ci95_ms": tci, "GB/s": round(bt / (tt / 1e3) / 1e9, 1),
@@ -684,13 +687,15 @@ def main():
                 f += alg_counts((64, DIMS[1], DIMS[2]), R, n, 8)[1]
             rows += 64
             del Xs
-        # The 64^3 R=16 mode-0 workload on one thread (median of 3 runs, own process so
-        # that OpenMP starts with one thread).
+        # The 64^3 R=16 mode-0 workload on one thread (median of 3 runs, in a process of
+        # its own that loads no other OpenMP runtime, so that OpenMP starts with one thread).
         single = None
         try:
             import subprocess
-            code = ("import time, statistics, sys; sys.path.insert(0, %r); import oracle; "
-                    "from paper_2206_08301_amd import synth; "
+            code = ("import time, statistics, sys, importlib.util; sys.path.insert(0, %r); import oracle; "
+                    "sp = importlib.util.spec_from_file_location('synth', oracle.__file__.rsplit('/', 2)[0] + "
+                    "'/paper_2206_08301_amd/synth.py'); synth = importlib.util.module_from_spec(sp); "
+                    "sp.loader.exec_module(synth); "
                     "X = synth.x_tensor(synth.config_seed(1, 0), (64, 64, 64)); "
                     "U = [None] + [synth.normal_factor(synth.config_seed(1, 1 + m), 64, 16) for m in (1, 2)]; "
                     "ts = []\n"

@@ -97,7 +97,7 @@ typedef enum deinsum_dtype { DEINSUM_F64 = 0, DEINSUM_F32 = 1, DEINSUM_BF16 = 2,
  *            DEINSUM_ERR_UNSUPPORTED before anything is enqueued (pick the
  *            storage with deinsum_choose_storage).  The report names the form
  *            that ran and its estimate.  MTTKRP, MTTKRP-GEMM chain and TTMc
- *            (TTMc forms: FP64, FP32, BF16).
+ *            (TTMc forms: FP64, FP32, BF16, FX20).
  */
 typedef enum deinsum_precision {
     DEINSUM_PREC_FP64 = 0,
@@ -257,8 +257,12 @@ deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, 
  * each product contracting the factor's first index (I_m x R_m):
  *   Y[r_0..i_n..r_{N-1}] = sum_{i_m, m != n} X[i] * prod_{m != n} U^{m}[i_m, r_m]
  * ranks : host array of N-1 ranks in operand order, each 1..64.
- * Forms: FP64 (X, U f64), FP32 (X, U f32) and BF16 (X bf16, U f32; BF16 matrix
- * cores for the first contraction, FP32 for the second, FP64 sums beyond).
+ * Forms: FP64 (X, U f64), FP32 (X, U f32), BF16 (X bf16, U f32; BF16 matrix
+ * cores for the first contraction, FP32 for the second, FP64 sums beyond) and
+ * FX20 (X the FX20 buffer, U f32: the first contraction on the FP16 matrix cores
+ * as h*uh + h*ul + l*uh with the factor scaled per column by a power of two and
+ * split into FP16 hi + lo, FP32 sums over the whole contracted extent, then
+ * scaled back; the rest as FP32).
  * Other arguments as for deinsum_mttkrp.
  */
 deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,

@@ -300,8 +300,6 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
     sp = _spec(spec)
     if sp.kind != TTMC:
         raise ValueError("spec is not a TTMc")
-    if precision == "fx20" or isinstance(X, FX20):
-        raise TypeError("TTMc has no FX20 form")
     _x_check(X, precision)
     udt = _u_dtype_for(precision, U)
     if X.dim() != sp.order or len(U) != sp.n_factors:
@@ -325,14 +323,15 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
     ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
     o = _opts(precision, out_dtype, workspace, 0 if variant is None else int(variant) + 1, 0, report, tol=tol,
               x_dtype=_storage_code(X), u_dtype=_DT_CODE[udt])
+    xptr = X.buf.data_ptr() if isinstance(X, FX20) else X.data_ptr()
     if tune_reps:
         rep = Report()
         with torch.cuda.device(X.device):
             _lib.check(_lib.load().deinsum_tune_ttmc(ctypes.byref(sp), _i64(X.shape), _i64(ranks),
-                                                     ctypes.c_void_p(X.data_ptr()), ptrs, ctypes.c_void_p(out.data_ptr()),
+                                                     ctypes.c_void_p(xptr), ptrs, ctypes.c_void_p(out.data_ptr()),
                                                      ctypes.byref(o), int(tune_reps), ctypes.byref(rep), _stream(stream)))
     with torch.cuda.device(X.device):
-        _lib.check(_lib.load().deinsum_ttmc(ctypes.byref(sp), _i64(X.shape), _i64(ranks), ctypes.c_void_p(X.data_ptr()),
+        _lib.check(_lib.load().deinsum_ttmc(ctypes.byref(sp), _i64(X.shape), _i64(ranks), ctypes.c_void_p(xptr),
                                             ptrs, ctypes.c_void_p(out.data_ptr()), ctypes.byref(o), _stream(stream)))
     return out
 

@@ -163,7 +163,6 @@ int form_candidates(int kind, int x_dtype, int u_dtype, int out[2])
         return 2;
     case DEINSUM_BF16: out[0] = P_BF16; return 1;
     case DEINSUM_FX20:
-        if (kind == DEINSUM_TTMC) return 0;
         out[0] = P_FX20;
         return 1;
     default: return 0;
@@ -347,7 +346,8 @@ deinsum_status mttkrp_estimate(const deinsum_spec *spec, const int64_t *dims, in
 }
 
 // The same for TTMc: the fused pass sums over modes a and c in FP32 in the reduced forms.
-double ttmc_estimate(const deinsum_spec *spec, const int64_t *dims, int prec)
+// x_storage: FX20's storage error from the header (< 0: not known).
+double ttmc_estimate(const deinsum_spec *spec, const int64_t *dims, int prec, double x_storage = -1)
 {
     const int N = spec->order, n = spec->free_mode;
     ErrInputs in;
@@ -363,6 +363,7 @@ double ttmc_estimate(const deinsum_spec *spec, const int64_t *dims, int prec)
         const int c = N - 1, a = (n == N - 1 || N - 2 != n) ? N - 2 : N - 3;
         in.k32 = static_cast<double>(dims[a]) + (n == N - 1 ? 0.0 : static_cast<double>(dims[c]));
     }
+    in.x_storage = x_storage;
     return estimate_error(in);
 }
 
@@ -380,7 +381,13 @@ deinsum_status resolve_form(const deinsum_spec *spec, const int64_t *dims, const
     const bool ttmc = spec->kind == DEINSUM_TTMC;
     auto estimate = [&](int prec, const void *x, double *e) -> deinsum_status {
         if (ttmc) {
-            *e = ttmc_estimate(spec, dims, prec);
+            double xs = -1;
+            if (prec == P_FX20 && x) {
+                double nx = 1;
+                for (int m = 0; m < spec->order; ++m) nx *= static_cast<double>(dims[m]);
+                if (deinsum_status st = fx20_storage_error(x, static_cast<int64_t>(nx), s, &xs)) return st;
+            }
+            *e = ttmc_estimate(spec, dims, prec, xs);
             return DEINSUM_OK;
         }
         return mttkrp_estimate(spec, dims, ranks[0], prec, x, s, e);
@@ -1008,9 +1015,8 @@ deinsum_status deinsum_estimate_error(const deinsum_spec *spec, const int64_t *d
         return fail(DEINSUM_ERR_INVALID_ARG, "estimate_error: the FX20 estimate reads X's header");
     if (o.precision == DEINSUM_PREC_AUTO && o.x_dtype == DEINSUM_FX20 && !X)
         return fail(DEINSUM_ERR_INVALID_ARG, "estimate_error: the FX20 estimate reads X's header");
-    if (spec->kind == DEINSUM_TTMC && o.precision != DEINSUM_PREC_AUTO && o.precision != DEINSUM_PREC_FP64 &&
-        o.precision != DEINSUM_PREC_FP32 && o.precision != DEINSUM_PREC_BF16)
-        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64, FP32 and BF16 forms");
+    if (spec->kind == DEINSUM_TTMC && o.precision == DEINSUM_PREC_BF16X3)
+        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64, FP32, BF16 and FX20 forms");
     double est = NAN;
     if (deinsum_status st = resolve_form(spec, dims, ranks, X, &o, true, static_cast<hipStream_t>(stream), &est))
         return st;
@@ -1035,11 +1041,23 @@ deinsum_status deinsum_choose_storage(const deinsum_spec *spec, const int64_t *d
     double best = INFINITY;
     for (int i = 0; i < 5; ++i) {
         const int p = order_p[i];
-        if (ttmc && (p == P_FX20 || p == P_BF16X3)) continue;
+        if (ttmc && p == P_BF16X3) continue;
         double e = 0;
         if (p == P_FX20) {
             const double dx = fx20_storage_model(max_abs, rms);
             if (!(dx >= 0)) continue;  // no statistics of X: FX20 not considered
+            if (ttmc) {
+                e = ttmc_estimate(spec, dims, P_FX20, dx);
+                if (e <= tol) {
+                    *x_dtype = order_x[i];
+                    *precision = p;
+                    *est_err = e;
+                    clear_error();
+                    return DEINSUM_OK;
+                }
+                best = std::min(best, e);
+                continue;
+            }
             ErrInputs in;
             in.prec = P_FX20;
             in.order = spec->order;

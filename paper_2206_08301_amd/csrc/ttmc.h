@@ -21,12 +21,22 @@ struct TkArgs {
     int64_t Ia, Ic, stride_a;
     OuterDesc od;            // slab modes (X strides only)
     int64_t n_slabs, slabs_per_group;
+    int64_t slab_stride;     // element distance of consecutive slabs when constant, else 0
     int n_ctiles, nwaves, n_cgroups;
     int ra, rc;
     int vec_ok;
     int xcd_remap;           // 1: the workgroups of one XCD take one contiguous range of units
     int64_t n_groups;        // grid size
     double *P;               // stage2: [cgroup][slab][ra][rc]; else [slab][n_ctiles*16*MT][16*NTA]
+    // FX20 form only: X is the FP16 plane of the buffer, X2 its int8 plane, fx_hdr its
+    // header (exponent e); Ua holds the packed FP16 hi parts of U^a scaled per column by
+    // 2^-k, Ua2 the lo parts; ua_scale[col] = 2^k and ua_off[col] = 1152 * (sum of the hi
+    // parts of the column) undo the scaling and the int8 operand's offset.
+    const void *X2;
+    const void *Ua2;
+    const double *ua_scale;
+    const double *ua_off;
+    const void *fx_hdr;
 };
 
 deinsum_status ttmc_workspace_size(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks,

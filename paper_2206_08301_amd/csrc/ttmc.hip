@@ -52,6 +52,12 @@ template <> struct TkTypes<P_BF16> {
     using XT = uint16_t; using UT = u16x8; using CT = float; using DT = f32x4;
     static constexpr int KR = 32, LR = 8;
 };
+// FX20: the FP16 plane as the BF16 form's X (2-byte values, 32 rows per K step), the
+// int8 plane beside it; stage 1 on the FP16 matrix cores, stage 2 as the FP32 form.
+template <> struct TkTypes<P_FX20> {
+    using XT = uint16_t; using UT = u16x8; using CT = float; using DT = f32x4;
+    static constexpr int KR = 32, LR = 8;
+};
 
 __device__ __forceinline__ int64_t tmin(int64_t a, int64_t b) { return a < b ? a : b; }
 
@@ -82,41 +88,23 @@ __device__ __forceinline__ void load_vec_n(T *dst, const T *__restrict__ src)
     }
 }
 
-// Slab odometer over the X offset, unrolled over the maximum number of slab
-// modes so the indices stay in registers.
-struct SlabWalk {
-    int64_t idx[kMaxOuter];
-    int64_t off;
-    __device__ __forceinline__ void init(const OuterDesc &od, int64_t o)
-    {
-        off = 0;
+// Element offset in X of slab s (the slab modes in row-major order).  With a constant
+// slab stride (the slab modes are the leading modes of X) it is s * stride; otherwise
+// the index is decomposed, once per slab, which keeps no odometer state in scalar
+// registers across the K loop.
+__device__ __forceinline__ int64_t slab_offset(const OuterDesc &od, int64_t stride, int64_t s)
+{
+    if (stride) return s * stride;
+    int64_t off = 0;
 #pragma unroll
-        for (int m = kMaxOuter - 1; m >= 0; --m) {
-            idx[m] = 0;
-            if (m < od.n_outer) {
-                idx[m] = o % od.dim[m];
-                o /= od.dim[m];
-                off += idx[m] * od.xstride[m];
-            }
+    for (int m = kMaxOuter - 1; m >= 0; --m)
+        if (m < od.n_outer) {
+            const int64_t d = od.dim[m];
+            off += (s % d) * od.xstride[m];
+            s /= d;
         }
-    }
-    __device__ __forceinline__ void next(const OuterDesc &od)
-    {
-        bool carry = true;
-#pragma unroll
-        for (int m = kMaxOuter - 1; m >= 0; --m) {
-            if (m < od.n_outer && carry) {
-                off += od.xstride[m];
-                if (++idx[m] < od.dim[m]) {
-                    carry = false;
-                } else {
-                    off -= idx[m] * od.xstride[m];
-                    idx[m] = 0;
-                }
-            }
-        }
-    }
-};
+    return off;
+}
 
 // Fused two-mode pass.  Per slab, the K loop over i_a runs in ring steps of
 // LDS of the fused kernel.  Stage-2 factor rows of the workgroup are held in LDS
@@ -197,14 +185,24 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
         __syncthreads();
     }
 
+    // FX20: the tensor's scale exponent e (the column scales and offsets are read per slab).
+    int fx_e = 0;
+    if constexpr (P == P_FX20) fx_e = static_cast<const Fx20Header *>(a.fx_hdr)->exp2;
+
     auto run = [&](auto full_tag) {
         constexpr bool FULL = decltype(full_tag)::value;
-        // The lane's LR rows of X per K step, MT indices each (BF16: two per 32-bit word).
-        static_assert(P != P_BF16 || MT % 2 == 0, "BF16 tiles hold whole words");
-        constexpr int XWN = (P == P_BF16) ? MT / 2 : MT;
-        using XWT = std::conditional_t<P == P_BF16, uint32_t, XT>;
+        // The lane's LR rows of X per K step, MT indices each (BF16 and FX20's FP16 plane:
+        // two per 32-bit word; FX20's int8 plane: the MT = 4 bytes of a row in one word).
+        constexpr bool H16 = (P == P_BF16 || P == P_FX20);
+        constexpr bool FX = (P == P_FX20);
+        static_assert(!H16 || MT % 2 == 0, "16-bit tiles hold whole words");
+        static_assert(!FX || MT == 4 || MT == 2, "FX20 tiles take the int8 values of a row in one word");
+        constexpr int XWN = H16 ? MT / 2 : MT;
+        using XWT = std::conditional_t<H16, uint32_t, XT>;
         XWT xb[NBUF][UB][LR][XWN];
         UT ub[NBUF][UB][NTA];
+        uint32_t xl[FX ? NBUF : 1][FX ? UB : 1][FX ? LR : 1];
+        UT ub2[FX ? NBUF : 1][FX ? UB : 1][FX ? NTA : 1];
         // Ring step st of the slab at xsrc into ring slot `slot`.  FULL and unguarded:
         // a fixed sequence of unmasked vector loads, so the compiler waits for exactly
         // the oldest step; otherwise rows past I_a (and dead steps) read as zero.
@@ -212,20 +210,40 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
 #pragma unroll
             for (int u = 0; u < UB; ++u) {
                 const int64_t kb = st * UB + u;  // K step
-                if constexpr (P == P_BF16) {
+                if constexpr (H16) {
                     // B operand: eight rows of one column, packed per lane by the pad kernel.
                     const bool bv = live && kb < nkb;
 #pragma unroll
-                    for (int nt = 0; nt < NTA; ++nt)
-                        ub[slot][u][nt] = bv ? *reinterpret_cast<const u16x8 *>(Ua + ((kb * NTA + nt) * 64 + lane) * 8)
-                                             : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                    for (int nt = 0; nt < NTA; ++nt) {
+                        const int64_t pk = ((kb * NTA + nt) * 64 + lane) * 8;
+                        ub[slot][u][nt] = bv ? *reinterpret_cast<const u16x8 *>(Ua + pk) : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                        if constexpr (FX)
+                            ub2[slot][u][nt] = bv ? *reinterpret_cast<const u16x8 *>(static_cast<const XT *>(a.Ua2) + pk)
+                                                  : u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                    }
                 }
 #pragma unroll
                 for (int q = 0; q < LR; ++q) {
                     // lane group g holds K slots LR*g .. LR*g + LR-1 of the step (KR = 4 * LR rows)
                     const int64_t r = kb * KR + LR * g + q;
                     const bool rv = live && (!guard || r < a.Ia);
-                    if constexpr (P != P_BF16) {
+                    if constexpr (FX) {
+                        // int8 plane: the lane's MT = 4 bytes of the row (zero out of range).
+                        const uint8_t *lsrc = static_cast<const uint8_t *>(a.X2) + (xsrc - X) + r * a.stride_a;
+                        uint32_t wv = 0;
+                        if (rv) {
+                            if (FULL || (a.vec_ok && ibase + MT <= a.Ic)) {
+                                if constexpr (MT == 4) wv = ld_stream<XNT>(reinterpret_cast<const uint32_t *>(lsrc));
+                                else wv = ld_stream<XNT>(reinterpret_cast<const uint16_t *>(lsrc));
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < MT; ++i)
+                                    if (ibase + i < a.Ic) wv |= static_cast<uint32_t>(lsrc[i]) << (8 * i);
+                            }
+                        }
+                        xl[slot][u][q] = wv;
+                    }
+                    if constexpr (!H16) {
 #pragma unroll
                         for (int nt = 0; nt < NTA; ++nt) ub[slot][u][nt] = rv ? Ua[r * TA + nt * 16 + c] : UT{};
                     }
@@ -261,7 +279,7 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                             if (!done) {
 #pragma unroll
                                 for (int k = 0; k < VW; ++k) {
-                                    if constexpr (P == P_BF16)
+                                    if constexpr (H16)
                                         xb[slot][u][q][j * VW + k] =
                                             static_cast<uint32_t>(elem(j * V + 2 * k)) |
                                             (static_cast<uint32_t>(elem(j * V + 2 * k + 1)) << 16);
@@ -280,8 +298,8 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
             for (int u = 0; u < UB; ++u)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
-                    if constexpr (P == P_BF16) {
-                        // A operand: index mt of the lane's eight rows, two BF16 values per word
+                    if constexpr (H16) {
+                        // A operand: index mt of the lane's eight rows, two 16-bit values per word
                         uint32_t w4[4];
                         constexpr uint32_t kLo = 0x05040100u, kHi = 0x07060302u;  // low / high halves
 #pragma unroll
@@ -290,8 +308,29 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                                                           (mt & 1) ? kHi : kLo);
                         u16x8 av;
                         __builtin_memcpy(&av, w4, 16);
+                        if constexpr (FX) {
+                            // int8 operand: byte mt of each row as the FP16 value (1152 + l) / 256,
+                            // bit pattern 0x4400 | (b ^ 0x80); sum_k (256 h + l) u' =
+                            // 256 (h.uh + h.ul + ((1152 + l)/256).uh) - 1152 sum uh.
+                            const uint32_t sel = static_cast<uint32_t>(mt) | (0x0Cu << 8) |
+                                                 (static_cast<uint32_t>(mt + 4) << 16) | (0x0Cu << 24);
+                            uint32_t o4[4];
 #pragma unroll
-                        for (int nt = 0; nt < NTA; ++nt) d[mt][nt] = mfma_bf16(av, ub[slot][u][nt], d[mt][nt]);
+                            for (int k = 0; k < 4; ++k)
+                                o4[k] = __builtin_amdgcn_perm(xl[slot][u][2 * k + 1] ^ 0x80808080u,
+                                                              xl[slot][u][2 * k] ^ 0x80808080u, sel) | 0x44004400u;
+                            u16x8 al;
+                            __builtin_memcpy(&al, o4, 16);
+#pragma unroll
+                            for (int nt = 0; nt < NTA; ++nt) {
+                                d[mt][nt] = mfma_f16(av, ub[slot][u][nt], d[mt][nt]);
+                                d[mt][nt] = mfma_f16(av, ub2[slot][u][nt], d[mt][nt]);
+                                d[mt][nt] = mfma_f16(al, ub[slot][u][nt], d[mt][nt]);
+                            }
+                        } else {
+#pragma unroll
+                            for (int nt = 0; nt < NTA; ++nt) d[mt][nt] = mfma_bf16(av, ub[slot][u][nt], d[mt][nt]);
+                        }
                     } else {
 #pragma unroll
                         for (int nt = 0; nt < NTA; ++nt) {
@@ -304,9 +343,7 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                 }
         };
 
-        SlabWalk walk;
-        walk.init(a.od, s0);
-        const XT *xs = X + walk.off + ibase;
+        const XT *xs = X + slab_offset(a.od, a.slab_stride, s0) + ibase;
         // The ring runs on across slab boundaries: the first NBUF-1 steps of a slab are
         // issued during the last ring turn of the previous one, so the loads stay in
         // flight through stage 2 and the workgroup reduction.
@@ -314,9 +351,7 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
         for (int u = 0; u < NBUF - 1; ++u) issue(u, xs, u, u >= nfull, s0 < s1);
         for (int64_t slab = s0; slab < s1; ++slab) {
             const bool has_next = slab + 1 < s1;
-            SlabWalk wn = walk;
-            if (has_next) wn.next(a.od);
-            const XT *xn = X + wn.off + ibase;
+            const XT *xn = has_next ? X + slab_offset(a.od, a.slab_stride, slab + 1) + ibase : xs;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -339,6 +374,18 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                 }
             }
 
+            if constexpr (FX) {
+                // D = 2^(e + k_col) (256 D' - 1152 sum uh): back to the values of X and U^a.
+#pragma unroll
+                for (int ta = 0; ta < NTA; ++ta) {
+                    const double sc = ldexp(a.ua_scale[ta * 16 + c], fx_e), off = a.ua_off[ta * 16 + c];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            d[mt][ta][v] = static_cast<float>((256.0 * static_cast<double>(d[mt][ta][v]) - off) * sc);
+                }
+            }
             if constexpr (STAGE2) {
                 // Z[r_c, r_a] = sum_{i_c} U^c[i_c, r_c] D[i_c, r_a]: K-step v pairs slot g
                 // with the D row that lanes of group g hold in register v.
@@ -429,7 +476,6 @@ __global__ void __launch_bounds__(256, 2) ttmc_fused_kernel(const TkArgs a)
                                     static_cast<double>(d[mt][ta][v]);
                 }
             }
-            walk = wn;
             xs = xn;
         }
     };
@@ -452,6 +498,67 @@ __global__ void __launch_bounds__(256) pad_factor_kernel(const T *src, int64_t r
 // BF16 stage-1 factor: for K step kb (rows 32 kb ..), column tile nt and lane
 // (g, c), the eight BF16 values of rows 32 kb + 8 g .. + 7 in column 16 nt + c,
 // contiguous (one 16-byte load per lane); zero past the factor's rows and columns.
+// FX20 stage-1 factor, one workgroup per column: k with max |u| < 2^k, scale = 2^k,
+// and off = 1152 * the sum of the FP16 hi parts of the column scaled by 2^-k (removes
+// the int8 operand's offset).  Rows are strided over the threads and both results are
+// combined by a fixed-order tree, so they do not depend on timing.  Columns past r are
+// zero (k = 0).
+__global__ void __launch_bounds__(256) fx20_factor_cols_kernel(const float *src, int64_t rows, int r, int *kexp,
+                                                               double *scale, double *off)
+{
+    __shared__ float smx[256];
+    __shared__ double ssum[256];
+    const int col = static_cast<int>(blockIdx.x);
+    const int t = static_cast<int>(threadIdx.x);
+    float mx = 0.0f;
+    if (col < r)
+        for (int64_t i = t; i < rows; i += 256) mx = fmaxf(mx, fabsf(src[i * r + col]));
+    smx[t] = mx;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) smx[t] = fmaxf(smx[t], smx[t + h]);
+        __syncthreads();
+    }
+    int k = 0;
+    if (smx[0] > 0.0f) (void)frexpf(smx[0], &k);
+    double sh = 0.0;
+    if (col < r)
+        for (int64_t i = t; i < rows; i += 256)
+            sh += static_cast<double>(static_cast<float>(static_cast<_Float16>(ldexpf(src[i * r + col], -k))));
+    ssum[t] = sh;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) ssum[t] += ssum[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        kexp[col] = k;
+        scale[col] = ldexp(1.0, k);
+        off[col] = 1152.0 * ssum[0];
+    }
+}
+
+// FP16 hi and lo parts of U^a scaled per column by 2^-k, packed per K step and lane
+// as the BF16 form packs its factor (eight rows of one column per lane).
+__global__ void __launch_bounds__(256) pack_factor_fx20_kernel(const float *src, int64_t rows, int r, int nta,
+                                                               int64_t nkb, const int *kexp, uint16_t *hi,
+                                                               uint16_t *lo)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= nkb * nta * 512) return;
+    const int q = static_cast<int>(e % 8);
+    const int lane = static_cast<int>((e / 8) % 64);
+    const int nt = static_cast<int>((e / 512) % nta);
+    const int64_t kb = e / (512 * static_cast<int64_t>(nta));
+    const int64_t row = kb * 32 + 8 * (lane >> 4) + q;
+    const int col = nt * 16 + (lane & 15);
+    const float v = (row < rows && col < r) ? ldexpf(src[row * r + col], -kexp[col]) : 0.0f;
+    const _Float16 h = static_cast<_Float16>(v);
+    const _Float16 l = static_cast<_Float16>(v - static_cast<float>(h));
+    hi[e] = __builtin_bit_cast(uint16_t, h);
+    lo[e] = __builtin_bit_cast(uint16_t, l);
+}
+
 __global__ void __launch_bounds__(256) pack_factor_bf16_kernel(const float *src, int64_t rows, int r, int nta,
                                                               int64_t nkb, uint16_t *dst)
 {
@@ -467,9 +574,16 @@ __global__ void __launch_bounds__(256) pack_factor_bf16_kernel(const float *src,
 }
 
 // Bytes of the padded stage-1 factor copy of a rows x (16 nta) tile set.
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Stage-1 factor copy.  FX20: hi pack, lo pack, then per column 2^k (double),
+// 1152 * sum of hi (double) and k (int), each 256-byte aligned.
 size_t stage1_factor_bytes(int prec, int64_t rows, int nta)
 {
-    if (prec == P_BF16) return static_cast<size_t>((rows + 31) / 32) * nta * 512 * sizeof(uint16_t);
+    const size_t pack = static_cast<size_t>((rows + 31) / 32) * nta * 512 * sizeof(uint16_t);
+    if (prec == P_BF16) return pack;
+    if (prec == P_FX20)
+        return 2 * align256(pack) + 2 * align256(static_cast<size_t>(16 * nta) * 8) + align256(16 * nta * 4);
     return static_cast<size_t>(rows) * 16 * nta * (prec == P_FP64 ? 8 : 4);
 }
 
@@ -656,9 +770,15 @@ const TkEntry kTkTable[] = {
     TK(P_BF16, 4, 4, 2, 1, 2),
     TK(P_BF16, 1, 1, 4, 1, 3), TK(P_BF16, 1, 1, 8, 1, 2), TKN(P_BF16, 2, 2, 4, 1, 3), TK(P_BF16, 2, 2, 4, 1, 2),
     TKN(P_BF16, 2, 2, 4, 1, 2),
+    TK(P_FX20, 1, 1, 4, 1, 2), TK(P_FX20, 1, 2, 4, 1, 2), TK(P_FX20, 1, 4, 4, 1, 2), TK(P_FX20, 2, 1, 4, 1, 2),
+    TK(P_FX20, 2, 2, 4, 1, 2), TK(P_FX20, 2, 4, 4, 1, 2), TK(P_FX20, 4, 1, 4, 1, 2), TK(P_FX20, 4, 2, 4, 1, 2),
+    TK(P_FX20, 4, 4, 4, 1, 2),
+    TKN(P_FX20, 1, 1, 4, 1, 2), TK(P_FX20, 1, 1, 4, 1, 3), TKN(P_FX20, 2, 2, 4, 1, 2), TK(P_FX20, 2, 2, 4, 1, 3),
+    TKN(P_FX20, 2, 2, 4, 1, 3), TK(P_FX20, 2, 2, 4, 1, 4), TK(P_FX20, 2, 2, 4, 2, 2),
     TK1(P_FP64, 1, 4, 2, 4), TK1(P_FP64, 2, 2, 2, 4), TK1(P_FP64, 4, 1, 2, 4),
     TK1(P_FP32, 1, 4, 2, 4), TK1(P_FP32, 2, 4, 2, 4), TK1(P_FP32, 4, 2, 2, 4),
     TK1(P_BF16, 1, 4, 1, 3), TK1(P_BF16, 2, 4, 1, 2), TK1(P_BF16, 4, 4, 1, 2),
+    TK1(P_FX20, 1, 4, 1, 2), TK1(P_FX20, 2, 4, 1, 2), TK1(P_FX20, 4, 4, 1, 2),
 };
 #undef TK
 #undef TKN
@@ -726,8 +846,8 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
             return fail(DEINSUM_ERR_SHAPE, "TTMc ranks must be 1.." + std::to_string(kMaxTtmcRank));
         p.Rm[m] = r;
     }
-    if (prec != P_FP64 && prec != P_FP32 && prec != P_BF16)
-        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64, FP32 and BF16 forms");
+    if (prec != P_FP64 && prec != P_FP32 && prec != P_BF16 && prec != P_FX20)
+        return fail(DEINSUM_ERR_UNSUPPORTED, "TTMc supports the FP64, FP32, BF16 and FX20 forms");
     const int N = p.N, n = p.n;
     if (N == 2 && n == 0) {  // a single product over the contiguous mode: the MTTKRP kernel computes it
         p.via_mttkrp = true;
@@ -831,7 +951,8 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
     if (o.plan_hint < 0) return fail(DEINSUM_ERR_INVALID_ARG, "TTMc plan_hint must be >= 0");
     if (deinsum_status st = make_plan(spec, dims, ranks, o.precision, o.plan_hint, &p)) return st;
     const int N = p.N, n = p.n;
-    const size_t xb = o.precision == P_FP64 ? 8 : (o.precision == P_FP32 ? 4 : 2);
+    const bool fx20 = o.precision == P_FX20;
+    const size_t xb = o.precision == P_FP64 ? 8 : (o.precision == P_FP32 ? 4 : 2);  // FX20: the FP16 plane
     const size_t ub = o.precision == P_FP64 ? 8 : 4;  // factors: FP64, else FP32
     const size_t ob = o.out_dtype == DEINSUM_F64 ? 8 : 4;
     const void *Um[DEINSUM_MAX_ORDER] = {nullptr};
@@ -849,7 +970,10 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
             const uintptr_t pa = reinterpret_cast<uintptr_t>(a0), pb = reinterpret_cast<uintptr_t>(b0);
             return pa < pb + nb && pb < pa + na;
         };
-        if (ov(Y, ny * ob, X, nx * xb)) return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps X");
+        if (ov(Y, ny * ob, X, fx20 ? static_cast<size_t>(fx20_bytes(nx)) : nx * xb))
+            return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps X");
+        if (fx20 && reinterpret_cast<uintptr_t>(X) % 256 != 0)
+            return fail(DEINSUM_ERR_INVALID_ARG, "an FX20 X buffer must be 256-byte aligned");
         for (int m = 0; m < N; ++m)
             if (m != n && ov(Y, ny * ob, Um[m], p.I[m] * p.Rm[m] * ub))
                 return fail(DEINSUM_ERR_INVALID_ARG, "output overlaps a factor");
@@ -898,6 +1022,18 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
             pack_factor_bf16_kernel<<<static_cast<unsigned>(cdivl(n, 256)), 256, 0, s>>>(
                 static_cast<const float *>(Um[p.a]), p.I[p.a], static_cast<int>(p.Rm[p.a]), p.nta, nkb,
                 reinterpret_cast<uint16_t *>(Ua_pad));
+        } else if (fx20) {
+            const int64_t nkb = cdivl(p.I[p.a], 32), n = nkb * p.nta * 512;
+            const size_t pk = align256(static_cast<size_t>(n) * sizeof(uint16_t)), ta = 16 * p.nta;
+            char *lo = Ua_pad + pk;
+            double *scale = reinterpret_cast<double *>(lo + pk);
+            double *off = reinterpret_cast<double *>(lo + pk + align256(ta * 8));
+            int *kexp = reinterpret_cast<int *>(lo + pk + 2 * align256(ta * 8));
+            fx20_factor_cols_kernel<<<static_cast<unsigned>(ta), 256, 0, s>>>(
+                static_cast<const float *>(Um[p.a]), p.I[p.a], static_cast<int>(p.Rm[p.a]), kexp, scale, off);
+            pack_factor_fx20_kernel<<<static_cast<unsigned>(cdivl(n, 256)), 256, 0, s>>>(
+                static_cast<const float *>(Um[p.a]), p.I[p.a], static_cast<int>(p.Rm[p.a]), p.nta, nkb, kexp,
+                reinterpret_cast<uint16_t *>(Ua_pad), reinterpret_cast<uint16_t *>(lo));
         } else {
             pad(p.a, 16 * p.nta, Ua_pad);
         }
@@ -907,8 +1043,17 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
 
     // ---- fused pass
     TkArgs a{};
-    a.X = X;
+    a.X = fx20 ? static_cast<const void *>(static_cast<const char *>(X) + kFx20Header) : X;
     a.Ua = Ua_pad;
+    if (fx20) {
+        const int64_t nkb = cdivl(p.I[p.a], 32);
+        const size_t pk = align256(static_cast<size_t>(nkb * p.nta * 512) * sizeof(uint16_t)), ta = 16 * p.nta;
+        a.X2 = static_cast<const char *>(X) + fx20_lo_offset(nx);
+        a.fx_hdr = X;
+        a.Ua2 = Ua_pad + pk;
+        a.ua_scale = reinterpret_cast<const double *>(Ua_pad + 2 * pk);
+        a.ua_off = reinterpret_cast<const double *>(Ua_pad + 2 * pk + align256(ta * 8));
+    }
     a.Uc = p.stage2 ? Uc_pad : nullptr;
     a.Ia = p.I[p.a];
     a.Ic = p.I[p.c];
@@ -920,13 +1065,20 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         a.od.U[k] = nullptr;
     }
     a.n_slabs = p.n_slabs;
+    // Slab modes 0 .. N-3 ahead of (a, c) = (N-2, N-1): slabs are equally spaced.
+    {
+        bool lead = p.a == N - 2 && p.c == N - 1;
+        for (size_t k = 0; k < p.slab_modes.size(); ++k) lead &= p.slab_modes[k] == static_cast<int>(k);
+        a.slab_stride = lead ? p.I[p.a] * p.I[p.c] : 0;
+    }
     a.slabs_per_group = p.spg;
     a.n_ctiles = p.n_ctiles;
     a.nwaves = p.nwaves;
     a.n_cgroups = p.n_cgroups;
     a.ra = static_cast<int>(p.Rm[p.a]);
     a.rc = p.stage2 ? static_cast<int>(p.Rm[p.c]) : 0;
-    a.vec_ok = ((p.I[p.c] * xb) % 8 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
+    a.vec_ok = fx20 ? (p.I[p.c] % 4 == 0)  // planes are 256-byte aligned; rows of whole 4-element groups
+                    : ((p.I[p.c] * xb) % 8 == 0) && (reinterpret_cast<uintptr_t>(X) % 16 == 0);
     a.xcd_remap = 1;
     a.n_groups = p.groups;
     a.P = P;

@@ -107,7 +107,7 @@ def test_auto_argument_errors(dn):
 def test_ttmc_forms(dn):
     spec, ranks = "ijk,jb,kc->ibc", [32, 32]
     assert dn.estimate_error(spec, D3, ranks, "auto", tol=1e-5, x_dtype=dn.F32, u_dtype=dn.F32)[0] == "fp32"
-    with pytest.raises(dn.DeinsumError):  # no FX20 TTMc form
+    with pytest.raises(dn.DeinsumError):  # the FX20 estimate needs the buffer's header
         dn.estimate_error(spec, D3, ranks, "auto", tol=1e-5, x_dtype=dn.FX20_STORAGE, u_dtype=dn.F32)
     _, e32 = dn.estimate_error(spec, D3, ranks, "fp32")
     assert e32 == pytest.approx(documented_rule("fp32", 3, 1024.0 ** 2, 2048), rel=1e-12)

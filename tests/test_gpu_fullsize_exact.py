@@ -70,14 +70,15 @@ def test_ttmc_full_size_integer_exact(dn, synth, oracle_mod, dims, rank):
     spec = ttmc_spec(N, 0)
     X32 = torch.empty(dims, dtype=torch.float32, device="cuda")
     dn.convert(X, X32)
-    for prec, Xp, dt in (("fp64", X, torch.float64), ("fp32", X32, torch.float32)):
+    Xf = dn.to_fx20(X)
+    for prec, Xp, dt in (("fp64", X, torch.float64), ("fp32", X32, torch.float32), ("fx20", Xf, torch.float32)):
         flush(f"TTMc integer {prec} dims={dims}")
         Y = dn.ttmc(spec, Xp, [to_dev(u, dt) for u in U[1:]], precision=prec, out_dtype=torch.float64)
         torch.cuda.synchronize()
         for i in (0, dims[0] // 2 + 1):
             ref = oracle_mod.ttmc(synth.x_slab(seed, dims, 0, i, dist="int3"), U, 0)[0]
             assert np.array_equal(Y[i].cpu().numpy(), ref), (prec, i)
-    del X, X32
+    del X, X32, Xf
     torch.cuda.empty_cache()
 
 

@@ -168,3 +168,62 @@ def test_ttmc_bf16_every_kernel_variant(dn, synth, oracle_mod, dims, ranks):
         assert err <= 1e-5, v
         seen += 1
     assert seen >= 1
+
+
+@pytest.mark.parametrize("dims,ranks", CASES)
+def test_ttmc_fx20_all_modes(dn, oracle_mod, dims, ranks):
+    """FX20 form (X in the 3-byte FX20 storage, FP32 factors): against the oracle on the
+    FP64 inputs, within the call's own error estimate and within 1e-5."""
+    rng = np.random.default_rng(sum(dims) + 20)
+    X = rng.uniform(-1, 1, dims)
+    Xf = dn.to_fx20(to_dev(X))
+    for n in range(len(dims)):
+        flush(f"ttmc fx20 dims={dims} n={n}")
+        U = [None if m == n else rng.standard_normal((d, ranks[m])) for m, d in enumerate(dims)]
+        ref = oracle_mod.ttmc(X, U, n)
+        rep = dn.Report()
+        got = dn.einsum(ttmc_spec(len(dims), n), Xf, *[to_dev(u, torch.float32) for u in U if u is not None],
+                        precision="fx20", out_dtype=torch.float64, report=rep)
+        torch.cuda.synchronize()
+        err = nrel(got.cpu().numpy(), ref)
+        assert err <= min(1e-5, rep.est_err), (dims, n, err, rep.est_err)
+
+
+def test_ttmc_fx20_integer_exact(dn, synth, oracle_mod):
+    """Integer X in {-2..2} and integer factors: the FX20 codes, the FP16 splits and every
+    FP32 partial sum are exact, so the result equals the oracle bit for bit."""
+    dims = (40, 64, 96)
+    X = synth.x_tensor(98, dims, "int5")
+    Xf = dn.to_fx20(to_dev(X))
+    rng = np.random.default_rng(4)
+    for n in range(3):
+        U = [None if m == n else rng.integers(-2, 3, (d, 16)).astype(np.float64) for m, d in enumerate(dims)]
+        ref = oracle_mod.ttmc(X, U, n)
+        got = dn.einsum(ttmc_spec(3, n), Xf, *[to_dev(u, torch.float32) for u in U if u is not None],
+                        precision="fx20", out_dtype=torch.float64)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), ref), n
+
+
+@pytest.mark.parametrize("dims,ranks", [((40, 70, 132), (8, 32, 24)), ((24, 60, 50, 70), (3, 40, 20, 64)),
+                                        ((6, 33, 70), (4, 16, 16))])
+def test_ttmc_fx20_every_kernel_variant(dn, oracle_mod, dims, ranks):
+    rng = np.random.default_rng(sum(dims) + 5)
+    X = rng.uniform(-1, 1, dims)
+    Xf = dn.to_fx20(to_dev(X))
+    U = [None] + [rng.standard_normal((d, ranks[m])) for m, d in enumerate(dims) if m > 0]
+    ref = oracle_mod.ttmc(X, U, 0)
+    Ud = [to_dev(u, torch.float32) for u in U[1:]]
+    seen = 0
+    for v in range(8):
+        try:
+            got = dn.ttmc(ttmc_spec(len(dims), 0), Xf, Ud, precision="fx20", out_dtype=torch.float64, variant=v)
+        except dn.DeinsumError as e:
+            assert e.status == -1  # no such variant
+            break
+        torch.cuda.synchronize()
+        err = nrel(got.cpu().numpy(), ref)
+        flush(f"ttmc fx20 variant {v} dims={dims}: {err:.2e}")
+        assert err <= 1e-5, v
+        seen += 1
+    assert seen >= 1
