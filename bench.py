@@ -667,7 +667,7 @@ def main():
         X = None
         torch.cuda.empty_cache()
         result["serving"] = serve_workload.measure(
-            dn, repeats=int(os.environ.get("BENCH_SERVE_REPEATS", "3")),
+            dn, repeats=int(os.environ.get("BENCH_SERVE_REPEATS", "5")),
             log=lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True))
 
     # ---- CPU oracle on a bounded sample of the same workload: all three modes over

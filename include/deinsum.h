@@ -32,6 +32,13 @@
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream)
  *     and the call returns without synchronising.  A device fault surfaces
  *     as DEINSUM_ERR_DEVICE from a later call or from the caller's sync.
+ *   - Workspace: with opts->workspace NULL a call takes the library pool's
+ *     buffer for its device and stream (grow-only; growing it synchronises
+ *     that stream).  Calls on one stream reuse it in stream order; calls on
+ *     different streams use different buffers, so they may run concurrently.
+ *     Up to 16 streams per device hold a buffer at once; a 17th stream takes
+ *     the least recently used one after a device synchronise.  A caller
+ *     buffer in opts->workspace is the caller's to order across streams.
  *   - Results are deterministic: for a given problem, plan and device the
  *     output is bitwise identical run to run (fixed reduction order, no
  *     floating-point atomics).
@@ -140,7 +147,8 @@ typedef struct deinsum_report {
 typedef struct deinsum_opts {
     int32_t precision;        /* deinsum_precision (default FP64)                    */
     int32_t out_dtype;        /* DEINSUM_F64 or DEINSUM_F32 (F64 required for FP64)  */
-    void *workspace;          /* optional caller device buffer; NULL = library pool  */
+    void *workspace;          /* optional caller device buffer; NULL = the library
+                                 pool's buffer for this device and stream           */
     size_t workspace_bytes;   /* its size                                            */
     int32_t plan_hint;        /* MTTKRP: 0 = autotuned plan if cached, else the
                                  heuristic; 1 / 2 = heuristic, and the free mode
@@ -433,7 +441,8 @@ deinsum_status deinsum_batch_destroy(deinsum_batch *b);
  * request (head of its tensor's queue, tensor idle) in arrival order while the
  * epoch has slots and the sum of the admitted requests' MTTKRP workspaces stays
  * within hbm_budget_bytes, and runs the epoch as one batch launch
- * (deinsum_batch_*) plus one batched update kernel on the slot's stream.  With
+ * (deinsum_batch_*) plus one batched update kernel on the slot's stream (an
+ * epoch of one request: see single_direct).  With
  * batched=0 every request is launched on arrival (deinsum_mttkrp + one update
  * kernel) on a single stream: the per-request baseline.
  *
@@ -455,9 +464,16 @@ typedef struct deinsum_server_config {
     int32_t als_update;         /* 1: run the factor update after each MTTKRP         */
     int64_t max_requests;       /* capacity of the request table                     */
     size_t hbm_budget_bytes;    /* admission limit on summed MTTKRP workspace         */
+    int32_t single_direct;      /* batched: 1 = an epoch of one request runs it with
+                                   the per-request launches (no descriptor upload or
+                                   batch graph); its result then matches the batched
+                                   one within the form's tolerance, not bitwise.
+                                   0 = every epoch is a batch launch: each result is
+                                   bitwise the same alone and in any mix            */
 } deinsum_server_config;
 
-/* Defaults: batched, 256 jobs per epoch, 2 in flight, update on, 1<<20 requests, 4 GiB. */
+/* Defaults: batched, 256 jobs per epoch, 2 in flight, update on, 1<<20 requests, 4 GiB,
+ * single_direct 1. */
 void deinsum_server_config_init(deinsum_server_config *cfg);
 
 deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_server **out);

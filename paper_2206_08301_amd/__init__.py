@@ -195,7 +195,10 @@ def mttkrp(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=Non
     """Mode-n MTTKRP.  ``U`` lists the factor operands in the spec's operand order.
     ``precision="auto"`` with ``tol`` lets the library pick the cheapest form that reads
     X's storage (its dtype, or an FX20 buffer) within the tolerance; ``report`` then
-    names the form (``report.precision``) and its estimated error (``report.est_err``)."""
+    names the form (``report.precision``) and its estimated error (``report.est_err``).
+    ``workspace=None`` takes the library pool's buffer for the device and ``stream``
+    (calls on different streams never share one); a caller workspace is the caller's
+    to order across streams."""
     sp = _spec(spec)
     if sp.kind != MTTKRP:
         raise ValueError("spec is not an MTTKRP")
@@ -296,7 +299,10 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
          variant=None, tune_reps=0, tol=None):
     """Mode-n TTMc.  ``U`` lists the factor operands in the spec's operand order.
     ``variant`` picks a compiled fused kernel for the ranks (None = the autotuned one if
-    cached, else the default); ``tune_reps`` > 0 autotunes first (``out`` is overwritten)."""
+    cached, else the default); ``tune_reps`` > 0 autotunes first (``out`` is overwritten).
+    ``workspace=None`` takes the library pool's buffer for the device and ``stream``
+    (calls on different streams never share one); a caller workspace is the caller's
+    to order across streams."""
     sp = _spec(spec)
     if sp.kind != TTMC:
         raise ValueError("spec is not a TTMc")
@@ -339,7 +345,10 @@ def ttmc(spec, X, U, precision="fp64", out=None, out_dtype=None, workspace=None,
 def mttkrp_mm(spec, X, U, C, precision="fp64", out=None, out_dtype=None, workspace=None, report=None, stream=None,
               tol=None):
     """MTTKRP followed by a matrix product, e.g. "ijk,ja,ka,al->il" (the paper's running
-    example): ``U`` lists the MTTKRP factor operands, ``C`` is the R x L matrix."""
+    example): ``U`` lists the MTTKRP factor operands, ``C`` is the R x L matrix.
+    ``workspace=None`` takes the library pool's buffer for the device and ``stream``
+    (calls on different streams never share one); a caller workspace is the caller's
+    to order across streams."""
     sp = _spec(spec)
     if sp.kind != MTTKRP_MM:
         raise ValueError("spec is not an MTTKRP-GEMM chain")
@@ -629,11 +638,14 @@ class Server:
     Each request (tensor, mode) runs the mode's MTTKRP and the factor update
     in the library; the factors registered with ``add_tensor`` are updated in
     place.  ``batched=True`` runs continuous batching, ``False`` one launch
-    per request.
+    per request.  ``single_direct=True`` runs an epoch of one request with the
+    per-request launches (lower latency; its result matches the batched one within
+    the form's tolerance); ``False`` keeps every result bitwise the same alone and
+    in any mix.
     """
 
     def __init__(self, batched=True, max_jobs_per_epoch=256, epochs_in_flight=2, als_update=True,
-                 max_requests=1 << 20, hbm_budget_bytes=4 << 30):
+                 max_requests=1 << 20, hbm_budget_bytes=4 << 30, single_direct=True):
         cfg = _lib.ServerConfig()
         _lib.load().deinsum_server_config_init(ctypes.byref(cfg))
         cfg.batched = int(bool(batched))
@@ -642,6 +654,7 @@ class Server:
         cfg.als_update = int(bool(als_update))
         cfg.max_requests = int(max_requests)
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.single_direct = int(bool(single_direct))
         self._h = ctypes.c_void_p()
         _lib.check(_lib.load().deinsum_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._keep = []

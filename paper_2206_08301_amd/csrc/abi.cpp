@@ -32,41 +32,94 @@ deinsum_status check_launch(const char *what)
 }
 
 // ------------------------------------------------------------------ workspace pool
-// One grow-only device buffer per device.  Calls that use the pool must be
-// ordered (one stream, or synchronised streams); concurrent calls pass their
-// own workspace.
+// Grow-only device buffers, one per (device, stream): calls with no workspace of
+// their own on one stream reuse that stream's buffer in stream order, and calls on
+// different streams never share one.  Up to kPoolStreams streams per device keep a
+// buffer; a further stream takes the least recently used one after a device
+// synchronise (nothing may still be using it).
 struct Pool {
+    void *stream = nullptr;
     void *ptr = nullptr;
     size_t bytes = 0;
+    uint64_t last_use = 0;
 };
+constexpr int kPoolStreams = 16;
 std::mutex g_pool_mu;
-Pool g_pool[64];
+Pool g_pool[64][kPoolStreams];
+uint64_t g_pool_clock = 0;
 
-deinsum_status pool_get(size_t bytes, void **out)
+deinsum_status pool_get(size_t bytes, void *stream, void **out)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
         return fail(DEINSUM_ERR_DEVICE, "workspace: no current HIP device");
     std::lock_guard<std::mutex> lk(g_pool_mu);
-    Pool &p = g_pool[dev];
-    if (p.bytes < bytes) {
-        if (p.ptr) {
-            // Earlier work may still use the old buffer.
+    Pool *p = nullptr, *lru = nullptr;
+    for (Pool &q : g_pool[dev]) {
+        if (q.ptr && q.stream == stream) {
+            p = &q;
+            break;
+        }
+        if (!lru || (!q.ptr && lru->ptr) || (q.ptr && lru->ptr && q.last_use < lru->last_use)) lru = &q;
+    }
+    if (!p) {
+        p = lru;
+        if (p->ptr) {  // evict: its stream's work may still be running
             if (hipDeviceSynchronize() != hipSuccess)
                 return fail(DEINSUM_ERR_DEVICE, "workspace: device synchronise failed");
-            (void)hipFree(p.ptr);
-            p.ptr = nullptr;
-            p.bytes = 0;
+            (void)hipFree(p->ptr);
+            *p = Pool{};
+        }
+        p->stream = stream;
+    }
+    p->last_use = ++g_pool_clock;
+    if (p->bytes < bytes) {
+        if (p->ptr) {
+            // Earlier work on this stream may still use the old buffer.
+            if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+                return fail(DEINSUM_ERR_DEVICE, "workspace: stream synchronise failed");
+            (void)hipFree(p->ptr);
+            p->ptr = nullptr;
+            p->bytes = 0;
         }
         size_t want = std::max<size_t>(bytes, size_t(1) << 20);
-        if (hipMalloc(&p.ptr, want) != hipSuccess) {
+        if (hipMalloc(&p->ptr, want) != hipSuccess) {
             (void)hipGetLastError();
-            p.ptr = nullptr;
+            *p = Pool{};
             return fail(DEINSUM_ERR_NO_MEMORY, "workspace: hipMalloc of " + std::to_string(want) + " bytes failed");
         }
-        p.bytes = want;
+        p->bytes = want;
     }
-    *out = p.ptr;
+    *out = p->ptr;
+    return DEINSUM_OK;
+}
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+    return na && nb && pa < pb + nb && pb < pa + na;
+}
+
+deinsum_status check_dims(const deinsum_spec *spec, const int64_t *dims)
+{
+    if (!spec || !dims) return fail(DEINSUM_ERR_INVALID_ARG, "null spec or dims");
+    if (spec->order < 2 || spec->order > DEINSUM_MAX_ORDER || spec->free_mode < 0 ||
+        spec->free_mode >= spec->order || spec->n_factors != spec->order - 1)
+        return fail(DEINSUM_ERR_INVALID_ARG, "spec is not a parsed deinsum_spec");
+    // Every mode but the free one is contracted with exactly one factor operand.
+    unsigned seen = 0;
+    for (int k = 0; k < spec->n_factors; ++k) {
+        const int m = spec->factor_mode[k];
+        if (m < 0 || m >= spec->order || m == spec->free_mode || (seen >> m & 1u) || spec->operand_of_mode[m] != k)
+            return fail(DEINSUM_ERR_INVALID_ARG, "spec is not a parsed deinsum_spec (factor modes)");
+        seen |= 1u << m;
+    }
+    for (int m = 0; m < spec->order; ++m)
+        if (dims[m] < 0) return fail(DEINSUM_ERR_SHAPE, "dims must be >= 0");
+    // Element count must fit comfortably in 62 bits.
+    long double total = 1;
+    for (int m = 0; m < spec->order; ++m) total *= static_cast<long double>(dims[m]);
+    if (total > 4.0e18L) return fail(DEINSUM_ERR_SHAPE, "tensor too large");
     return DEINSUM_OK;
 }
 
@@ -112,12 +165,6 @@ size_t x_elem_bytes(int prec)
 }
 size_t u_elem_bytes(int prec) { return prec == DEINSUM_PREC_FP64 ? 8 : 4; }
 size_t dtype_bytes(int dt) { return dt == DEINSUM_F64 ? 8 : (dt == DEINSUM_F32 ? 4 : 2); }
-
-bool overlaps(const void *a, size_t na, const void *b, size_t nb)
-{
-    const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
-    return na && nb && pa < pb + nb && pb < pa + na;
-}
 
 deinsum_status resolve_opts(const deinsum_opts *in, deinsum_opts *o)
 {
@@ -175,21 +222,6 @@ const char *form_name(int p)
     return (p >= 0 && p <= 5) ? names[p] : "?";
 }
 
-
-deinsum_status check_dims(const deinsum_spec *spec, const int64_t *dims)
-{
-    if (!spec || !dims) return fail(DEINSUM_ERR_INVALID_ARG, "null spec or dims");
-    if (spec->order < 2 || spec->order > DEINSUM_MAX_ORDER || spec->free_mode < 0 ||
-        spec->free_mode >= spec->order || spec->n_factors != spec->order - 1)
-        return fail(DEINSUM_ERR_INVALID_ARG, "spec is not a parsed deinsum_spec");
-    for (int m = 0; m < spec->order; ++m)
-        if (dims[m] < 0) return fail(DEINSUM_ERR_SHAPE, "dims must be >= 0");
-    // Element count must fit comfortably in 62 bits.
-    long double total = 1;
-    for (int m = 0; m < spec->order; ++m) total *= static_cast<long double>(dims[m]);
-    if (total > 4.0e18L) return fail(DEINSUM_ERR_SHAPE, "tensor too large");
-    return DEINSUM_OK;
-}
 
 __global__ void zero_fill_kernel(unsigned char *p, int64_t n)
 {
@@ -684,7 +716,7 @@ deinsum_status deinsum_mttkrp(const deinsum_spec *spec, const int64_t *dims, int
     if (ws) {
         if (o.workspace_bytes < call_workspace(c))
             return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(call_workspace(c)) + " bytes");
-    } else if (deinsum_status st = pool_get(call_workspace(c), &ws)) {
+    } else if (deinsum_status st = pool_get(call_workspace(c), stream, &ws)) {
         return st;
     }
     fill_report(o.report, c.orig, c.plan, call_workspace(c), c.merged, c.via_ttmc ? c.ttmc_variant : -1, est);
@@ -763,7 +795,7 @@ deinsum_status deinsum_mttkrp_mm(const deinsum_spec *spec, const int64_t *dims, 
     if (ws) {
         if (o.workspace_bytes < total)
             return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(total) + " bytes");
-    } else if (deinsum_status st = pool_get(total, &ws)) {
+    } else if (deinsum_status st = pool_get(total, stream, &ws)) {
         return st;
     }
     double *M = reinterpret_cast<double *>(static_cast<char *>(ws) + mws);
@@ -833,7 +865,7 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
                 cc.plan.order = variant & 1;
                 cc.plan.xcd = variant >> 1;
                 void *ws = nullptr;
-                if (deinsum_status st = pool_get(call_workspace(cc), &ws)) return st;
+                if (deinsum_status st = pool_get(call_workspace(cc), stream, &ws)) return st;
                 double us = 0;
                 if (deinsum_status st = time_median([&] { return run_mttkrp(cc, ws, s); }, reps, s, &us)) return st;
                 if (verbose)
@@ -861,7 +893,7 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
             cc.ttmc_variant = v;
             if (mttkrp_via_ttmc_workspace(c.pb.dims, c.pb.R, c.pb.prec, v, &cc.ttmc_bytes) != DEINSUM_OK) break;
             void *ws = nullptr;
-            if (deinsum_status st = pool_get(cc.ttmc_bytes, &ws)) return st;
+            if (deinsum_status st = pool_get(cc.ttmc_bytes, stream, &ws)) return st;
             double us = 0;
             if (deinsum_status st = time_median([&] { return run_mttkrp(cc, ws, s); }, reps, s, &us)) return st;
             if (verbose) std::fprintf(stderr, "[deinsum tune] mttkrp_via_ttmc hint %d: %.1f us\n", v, us);
@@ -974,7 +1006,7 @@ deinsum_status deinsum_ttmc(const deinsum_spec *spec, const int64_t *dims, const
         if (o.workspace_bytes < need)
             return fail(DEINSUM_ERR_NO_MEMORY, "workspace too small: need " + std::to_string(need) + " bytes");
     } else if (need) {
-        if (deinsum_status st = pool_get(need, &ws)) return st;
+        if (deinsum_status st = pool_get(need, stream, &ws)) return st;
     }
     if (deinsum_status st = run_ttmc(spec, dims, ranks, X, U, Y, o, ws, need, static_cast<hipStream_t>(stream)))
         return st;
@@ -1123,11 +1155,17 @@ deinsum_status deinsum_shutdown(void)
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (int d = 0; d < 64; ++d) {
-        if (!g_pool[d].ptr) continue;
-        (void)hipSetDevice(d);
-        (void)hipDeviceSynchronize();
-        (void)hipFree(g_pool[d].ptr);
-        g_pool[d] = Pool{};
+        bool synced = false;
+        for (Pool &q : g_pool[d]) {
+            if (!q.ptr) continue;
+            if (!synced) {
+                (void)hipSetDevice(d);
+                (void)hipDeviceSynchronize();
+                synced = true;
+            }
+            (void)hipFree(q.ptr);
+            q = Pool{};
+        }
     }
     (void)hipSetDevice(cur);
     clear_error();

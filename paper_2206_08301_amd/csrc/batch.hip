@@ -314,14 +314,33 @@ deinsum_status batch_add(deinsum_batch *b, const deinsum_spec *spec, const int64
     if (o.precision == DEINSUM_PREC_FP64 && o.out_dtype != DEINSUM_F64)
         return fail(DEINSUM_ERR_INVALID_ARG, "batch_add: the FP64 form writes an F64 output");
     if (R < 1 || R > 64) return fail(DEINSUM_ERR_SHAPE, "batch_add: rank must be 1..64");
+    if (deinsum_status st = check_dims(spec, dims)) return st;
     const int N = spec->order, n = spec->free_mode;
-    if (N < 2 || N > DEINSUM_MAX_ORDER) return fail(DEINSUM_ERR_INVALID_ARG, "batch_add: bad spec");
     MttkrpProblem pb;
     pb.N = N;
     pb.n = n;
+    int64_t nx = 1;
     for (int m = 0; m < N; ++m) {
         if (dims[m] < 1) return fail(DEINSUM_ERR_SHAPE, "batch_add: dims must be >= 1");
         pb.dims[m] = dims[m];
+        nx *= dims[m];
+    }
+    {
+        // Same argument checks as deinsum_mttkrp: element alignment, and an output
+        // that overlaps neither X nor a factor.
+        const size_t eb = o.precision == DEINSUM_PREC_FP64 ? 8 : 4, obytes = o.out_dtype == DEINSUM_F64 ? 8 : 4;
+        const size_t mbytes = static_cast<size_t>(dims[n] * R) * obytes;
+        if (reinterpret_cast<uintptr_t>(X) % eb != 0 || reinterpret_cast<uintptr_t>(M) % obytes != 0)
+            return fail(DEINSUM_ERR_INVALID_ARG, "batch_add: X, M and the factors must be aligned to their element size");
+        if (overlaps(M, mbytes, X, static_cast<size_t>(nx) * eb))
+            return fail(DEINSUM_ERR_INVALID_ARG, "batch_add: output overlaps X");
+        for (int k = 0; k < N - 1; ++k) {
+            if (!U[k]) return fail(DEINSUM_ERR_INVALID_ARG, "batch_add: null factor");
+            if (reinterpret_cast<uintptr_t>(U[k]) % eb != 0)
+                return fail(DEINSUM_ERR_INVALID_ARG, "batch_add: X, M and the factors must be aligned to their element size");
+            if (overlaps(M, mbytes, U[k], static_cast<size_t>(dims[spec->factor_mode[k]] * R) * eb))
+                return fail(DEINSUM_ERR_INVALID_ARG, "batch_add: output overlaps factor operand " + std::to_string(k));
+        }
     }
     pb.R = R;
     pb.prec = o.precision;

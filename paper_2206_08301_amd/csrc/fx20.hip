@@ -231,7 +231,7 @@ deinsum_status deinsum_tensor_stats(const void *X, int32_t dtype, int64_t count,
     if (count == 0) return DEINSUM_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *buf = nullptr;
-    if (deinsum_status st = pool_get(sizeof(StatsAcc), &buf)) return st;
+    if (deinsum_status st = pool_get(sizeof(StatsAcc), stream, &buf)) return st;
     StatsAcc *acc = static_cast<StatsAcc *>(buf);
     stats_init_kernel<<<1, 64, 0, s>>>(acc);
     stats_max_kernel<<<grid_for(count), 256, 0, s>>>(X, dtype, count, acc);

@@ -14,9 +14,16 @@ void set_error(const std::string &msg);
 void clear_error();
 deinsum_status fail(deinsum_status st, const std::string &msg);
 
-// The library's grow-only device workspace of the current device (abi.cpp).  Work
-// that uses it must be ordered with every other user (one stream, or synchronised).
-deinsum_status pool_get(size_t bytes, void **out);
+// The library's grow-only device workspace of the current device for `stream` (a
+// hipStream_t; abi.cpp): work on one stream reuses its buffer in stream order, work
+// on different streams gets different buffers.
+deinsum_status pool_get(size_t bytes, void *stream, void **out);
+
+// Argument checks shared by the entry points (abi.cpp): a spec as deinsum_parse
+// writes it (order, free mode, one factor operand per other mode) and dims >= 0
+// with a representable element count; whether two byte ranges overlap.
+deinsum_status check_dims(const deinsum_spec *spec, const int64_t *dims);
+bool overlaps(const void *a, size_t na, const void *b, size_t nb);
 
 // Normwise relative storage error ||X - X_stored|| / ||X|| recorded in the header of
 // an FX20 buffer of `count` elements (fx20.hip).  Copies the header to the host and

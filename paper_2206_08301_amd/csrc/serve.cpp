@@ -7,7 +7,9 @@
 //     ready request (its tensor idle, it is the head of the tensor's FIFO)
 //     is admitted, in arrival order, while its workspace fits the HBM budget
 //     and the epoch has slots; the epoch runs as one persistent batch launch
-//     (deinsum_batch_*) followed by one batched CP-ALS update kernel.  Up to
+//     (deinsum_batch_*) followed by one batched CP-ALS update kernel (an
+//     epoch of one request takes the per-request launches instead, unless
+//     single_direct is 0).  Up to
 //     two epochs are in flight on two streams, so requests that arrive while
 //     one epoch runs start on the device before it finishes.
 //   * per request: each request is launched on arrival (MTTKRP, then the
@@ -141,7 +143,9 @@ struct deinsum_server {
     // per request
     std::deque<std::pair<int64_t, hipEvent_t>> inflight;
     std::vector<hipEvent_t> event_pool;
-    void *ws = nullptr;  // per request: the server's own MTTKRP workspace (stream-ordered reuse)
+    // The server's own MTTKRP workspaces, one per stream (stream-ordered reuse): per request
+    // on stream 0; batched for epochs of a single request, which launch it directly.
+    void *ws[2] = {nullptr, nullptr};
     size_t ws_bytes = 0;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
@@ -181,6 +185,8 @@ void finish_request(deinsum_server *s, int64_t r, double t)
     ++s->completed;
 }
 
+bool enqueue_request(deinsum_server *s, int64_t r, hipStream_t st, void *ws);
+
 bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
 {
     Epoch &ep = s->epoch[e];
@@ -198,6 +204,27 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
         [&](int64_t r) { return s->tensors[s->reqs[r].tensor].ws[s->reqs[r].mode]; },
         [&](int32_t t) { s->tensors[t].busy = true; });
     if (ep.reqs.empty()) return false;
+    auto fail_epoch = [&](const std::string &msg) {
+        for (int64_t r : ep.reqs) fail_request(s, r, DEINSUM_ERR_DEVICE, msg);
+        ep.reqs.clear();
+        return false;
+    };
+    if (ep.reqs.size() == 1 && s->cfg.single_direct) {
+        // One request: the direct launches of the per-request path on this slot's stream
+        // (no descriptor upload, no persistent batch kernel).
+        const int64_t r = ep.reqs[0];
+        if (!enqueue_request(s, r, s->stream[e], s->ws[e])) {
+            ep.reqs.clear();
+            return false;
+        }
+        s->reqs[r].epoch = s->epochs;
+        if (hipEventRecord(s->ev[e], s->stream[e]) != hipSuccess) return fail_epoch("event record failed");
+        ep.active = true;
+        s->footprint_used += ep.footprint;
+        ++s->epochs;
+        s->max_batch = std::max<int64_t>(s->max_batch, 1);
+        return true;
+    }
     deinsum_batch_reset(s->batch[e]);
     int64_t als_total = 0;
     std::vector<int64_t> added;
@@ -229,11 +256,6 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
     ep.reqs.swap(added);
     ep.footprint = footprint;
     if (ep.reqs.empty()) return false;
-    auto fail_epoch = [&](const std::string &msg) {
-        for (int64_t r : ep.reqs) fail_request(s, r, DEINSUM_ERR_DEVICE, msg);
-        ep.reqs.clear();
-        return false;
-    };
     for (int64_t r : ep.reqs) store_status(s->reqs[r], DEINSUM_REQ_RUNNING);
     if (deinsum_batch_launch(s->batch[e], s->stream[e]) != DEINSUM_OK)
         return fail_epoch(std::string("batch_launch: ") + deinsum_last_error());
@@ -272,7 +294,10 @@ void complete_epoch(deinsum_server *s, int e, bool device_ok)
     ep.reqs.clear();
 }
 
-bool launch_one(deinsum_server *s, int64_t r)
+// Request r's MTTKRP (deinsum_mttkrp into the tensor's FP64 output) and, if configured,
+// its factor update, enqueued on `st` with the stream's own workspace `ws`.  On failure
+// the request has ended with its status and false is returned.
+bool enqueue_request(deinsum_server *s, int64_t r, hipStream_t st, void *ws)
 {
     SRequest &rq = s->reqs[r];
     STensor &t = s->tensors[rq.tensor];
@@ -283,27 +308,33 @@ bool launch_one(deinsum_server *s, int64_t r)
     deinsum_opts_init(&o);
     o.precision = t.prec;
     o.out_dtype = DEINSUM_F64;
-    o.workspace = s->ws;
-    o.workspace_bytes = s->ws_bytes;
+    o.workspace = ws;
+    o.workspace_bytes = ws ? s->ws_bytes : 0;
     store_status(rq, DEINSUM_REQ_RUNNING);
-    deinsum_status st = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]);
-    if (st == DEINSUM_ERR_NO_MEMORY && s->ws) {  // a plan tuned after start needs more: the library pool
+    deinsum_status rc = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, st);
+    if (rc == DEINSUM_ERR_NO_MEMORY && ws) {  // a plan tuned after start needs more: the library pool
         o.workspace = nullptr;
         o.workspace_bytes = 0;
-        st = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, s->stream[0]);
+        rc = deinsum_mttkrp(&sp, t.dims, t.R, t.X, ops, t.M, &o, st);
     }
-    if (st != DEINSUM_OK) {
-        fail_request(s, r, st, std::string("mttkrp: ") + deinsum_last_error());
+    if (rc != DEINSUM_OK) {
+        fail_request(s, r, rc, std::string("mttkrp: ") + deinsum_last_error());
         return false;
     }
     if (s->cfg.als_update) {
         AlsJob aj = als_job_for(t, rq.mode);
         aj.flag = s->req_flags + r;
-        if (deinsum_status st2 = launch_als_one(aj, s->stream[0])) {
-            fail_request(s, r, st2, std::string("factor update: ") + deinsum_last_error());
+        if (deinsum_status rc2 = launch_als_one(aj, st)) {
+            fail_request(s, r, rc2, std::string("factor update: ") + deinsum_last_error());
             return false;
         }
     }
+    return true;
+}
+
+bool launch_one(deinsum_server *s, int64_t r)
+{
+    if (!enqueue_request(s, r, s->stream[0], s->ws[0])) return false;
     hipEvent_t ev;
     if (!s->event_pool.empty()) {
         ev = s->event_pool.back();
@@ -318,7 +349,7 @@ bool launch_one(deinsum_server *s, int64_t r)
         return false;
     }
     s->inflight.emplace_back(r, ev);
-    rq.epoch = s->epochs++;
+    s->reqs[r].epoch = s->epochs++;
     return true;
 }
 
@@ -417,6 +448,7 @@ void deinsum_server_config_init(deinsum_server_config *cfg)
     cfg->als_update = 1;
     cfg->max_requests = int64_t(1) << 20;
     cfg->hbm_budget_bytes = size_t(4) << 30;
+    cfg->single_direct = 1;
 }
 
 deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_server **out)
@@ -429,6 +461,10 @@ deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_s
     if (s->cfg.max_jobs_per_epoch < 1 || s->cfg.max_jobs_per_epoch > 65536) {
         delete s;
         return fail(DEINSUM_ERR_INVALID_ARG, "server_create: max_jobs_per_epoch must be 1..65536");
+    }
+    if (s->cfg.single_direct != 0 && s->cfg.single_direct != 1) {
+        delete s;
+        return fail(DEINSUM_ERR_INVALID_ARG, "server_create: single_direct must be 0 or 1");
     }
     if (s->cfg.max_requests < 1 || s->cfg.max_requests > (int64_t(1) << 28)) {
         delete s;
@@ -530,16 +566,18 @@ deinsum_status deinsum_server_start(deinsum_server *s)
         return fail(DEINSUM_ERR_NO_MEMORY, "server_start: request flag table allocation failed");
     }
     std::memset(s->req_flags, 0, sizeof(int32_t) * static_cast<size_t>(s->cfg.max_requests));
-    if (!s->cfg.batched) {
+    {
         size_t mx = 0;
         for (auto &t : s->tensors)
             for (int m = 0; m < t.order; ++m) mx = std::max(mx, t.ws[m]);
-        if (mx && hipMalloc(&s->ws, mx) != hipSuccess) {
-            (void)hipGetLastError();
-            s->ws = nullptr;
-            return fail(DEINSUM_ERR_NO_MEMORY, "server_start: workspace allocation failed");
-        }
-        s->ws_bytes = s->ws ? mx : 0;
+        const int nws = s->cfg.batched ? 2 : 1;
+        for (int e = 0; e < nws && mx; ++e)
+            if (hipMalloc(&s->ws[e], mx) != hipSuccess) {
+                (void)hipGetLastError();
+                s->ws[e] = nullptr;
+                return fail(DEINSUM_ERR_NO_MEMORY, "server_start: workspace allocation failed");
+            }
+        s->ws_bytes = mx;
     }
     s->t0 = Clock::now();
     s->started = true;
@@ -669,7 +707,8 @@ deinsum_status deinsum_server_destroy(deinsum_server *s)
     for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
     for (auto &t : s->tensors)
         if (t.M) (void)hipFree(t.M);
-    if (s->ws) (void)hipFree(s->ws);
+    for (void *w : s->ws)
+        if (w) (void)hipFree(w);
     if (s->req_flags) (void)hipHostFree(s->req_flags);
     delete s;
     return DEINSUM_OK;

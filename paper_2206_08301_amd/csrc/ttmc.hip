@@ -794,6 +794,26 @@ const TkEntry *find_tk(int prec, int nta, int ntc, bool s2, int variant)
 
 int64_t cdivl(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Untuned pick: the table's first entry, unless the contiguous mode is too short
+// to give that entry's workgroup its four waves (one wave per 16*MT-wide c-tile);
+// then the first entry with the most waves.  A 60-wide mode with MT = 4 leaves one
+// wave per workgroup and nothing to hide the slab loads behind.
+int default_variant(int prec, int nta, int ntc, bool s2, int64_t Ic)
+{
+    int best = 0, best_w = -1;
+    for (int v = 0;; ++v) {
+        const TkEntry *e = find_tk(prec, nta, ntc, s2, v);
+        if (!e) break;
+        const int w = static_cast<int>(std::min<int64_t>(4, cdivl(Ic, 16 * e->mt)));
+        if (w > best_w) {
+            best = v;
+            best_w = w;
+        }
+        if (w == 4) break;
+    }
+    return best;
+}
+
 }  // namespace
 
 std::string ttmc_tune_key(const deinsum_spec *spec, const int64_t *dims, const int64_t *ranks, int prec)
@@ -876,6 +896,8 @@ deinsum_status make_plan(const deinsum_spec *spec, const int64_t *dims, const in
         TuneChoice tc;
         if (tune_lookup(ttmc_tune_key(spec, dims, ranks, prec), &tc) && find_tk(prec, p.nta, p.ntc, p.stage2, tc.split))
             v = tc.split;
+        else
+            v = default_variant(prec, p.nta, p.ntc, p.stage2, dims[p.c]);
     }
     p.kernel = find_tk(prec, p.nta, p.ntc, p.stage2, v);
     if (!p.kernel)

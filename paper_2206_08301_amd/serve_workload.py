@@ -8,10 +8,11 @@ probability 0.7 else FP64; X ~ U[-1, 1] from the counter generator, factors
 N(0, 1).  Request q goes to tensor q mod T and cycles through that tensor's
 modes.  Arrivals are a Poisson process of rate ``rate`` per second.
 
-Latency = host-observed completion - scheduled arrival.  Two runs per server
-mode: open loop at the Poisson arrivals (p50/p99 latency, median of
-``repeats``), and saturation with every request released at t = 0
-(throughput in requests/s and algorithmic GB/s).
+Latency = host-observed completion - scheduled arrival.  Two kinds of run per
+server mode: open loop at the Poisson arrivals (``repeats`` runs, the two modes
+alternating; p50/p99 of the pooled latencies with a 95 % bootstrap interval), and
+saturation with every request released at t = 0 (throughput in requests/s and
+algorithmic GB/s).
 """
 from __future__ import annotations
 
@@ -92,7 +93,21 @@ def serve_once(dn, wl, state, batched, open_loop, max_jobs=256, epochs_in_flight
     span = float(done.max() - arr.min())
     return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "max_ms": float(lat.max() * 1e3), "req_per_s": n / span, "span_s": span,
-            "epochs": stats["epochs"], "max_batch": stats["max_batch"], "completed": stats["completed"]}
+            "epochs": stats["epochs"], "max_batch": stats["max_batch"], "completed": stats["completed"],
+            "lat": lat}
+
+
+def percentile_ci(runs, q, n_boot=1000, seed=2206083600):
+    """Percentile q of the latencies pooled over the runs, with a 95 % bootstrap interval
+    (each resample redraws every run's latencies with replacement, run sizes kept)."""
+    rng = np.random.default_rng(seed)
+    pooled = np.concatenate(runs)
+    est = float(np.percentile(pooled, q))
+    boots = np.empty(n_boot)
+    for b in range(n_boot):
+        boots[b] = np.percentile(np.concatenate([r[rng.integers(0, len(r), len(r))] for r in runs]), q)
+    lo, hi = np.percentile(boots, [2.5, 97.5])
+    return est, float(lo), float(hi)
 
 
 def measure(dn, n_requests=4096, rate=2000.0, sweeps=10, repeats=3, log=None):
@@ -102,25 +117,36 @@ def measure(dn, n_requests=4096, rate=2000.0, sweeps=10, repeats=3, log=None):
     out = {"workload": f"{n_requests} CP-ALS requests (MTTKRP + factor update), {len(wl['tensors'])} order-3 "
                        f"tensors, dims U[32,512], R in {{8,16,32,64}}, 70% FP32, Poisson {rate:g}/s, "
                        f"{sweeps} sweeps",
-           "resident_gb": sum(s["X"].numel() * s["X"].element_size() for s in state) / 1e9}
-    for name, batched in (("batched", True), ("per_request", False)):
-        runs = []
-        for r in range(repeats):
-            runs.append(serve_once(dn, wl, state, batched, open_loop=True))
+           "resident_gb": sum(s["X"].numel() * s["X"].element_size() for s in state) / 1e9,
+           "statistic": f"p50 / p99 of the latencies pooled over {repeats} open-loop runs per server mode "
+                        "(the two modes alternate run by run), 95 % bootstrap interval over the pooled runs"}
+    modes = (("batched", True), ("per_request", False))
+    runs = {name: [] for name, _ in modes}
+    for r in range(repeats):
+        for name, batched in (modes if r % 2 == 0 else modes[::-1]):
+            runs[name].append(serve_once(dn, wl, state, batched, open_loop=True))
             if log:
-                log(f"serving {name} open-loop run {r}: p50 {runs[-1]['p50_ms']:.3f} ms "
-                    f"p99 {runs[-1]['p99_ms']:.3f} ms epochs {runs[-1]['epochs']}")
-        runs.sort(key=lambda d: d["p99_ms"])
-        ol = runs[len(runs) // 2]
+                log(f"serving {name} open-loop run {r}: p50 {runs[name][-1]['p50_ms']:.3f} ms "
+                    f"p99 {runs[name][-1]['p99_ms']:.3f} ms epochs {runs[name][-1]['epochs']}")
+    for name, batched in modes:
+        lats = [d["lat"] for d in runs[name]]
+        p50 = percentile_ci(lats, 50)
+        p99 = percentile_ci(lats, 99)
         sat = serve_once(dn, wl, state, batched, open_loop=False)
         if log:
             log(f"serving {name} saturation: {sat['req_per_s']:.0f} req/s, max batch {sat['max_batch']}")
-        out[name] = {"p50_ms": ol["p50_ms"], "p99_ms": ol["p99_ms"], "open_loop_req_per_s": ol["req_per_s"],
-                     "epochs": ol["epochs"],
+        out[name] = {"p50_ms": p50[0] * 1e3, "p50_ci95_ms": [p50[1] * 1e3, p50[2] * 1e3],
+                     "p99_ms": p99[0] * 1e3, "p99_ci95_ms": [p99[1] * 1e3, p99[2] * 1e3],
+                     "runs_p50_ms": [d["p50_ms"] for d in runs[name]],
+                     "runs_p99_ms": [d["p99_ms"] for d in runs[name]],
+                     "open_loop_req_per_s": float(np.median([d["req_per_s"] for d in runs[name]])),
+                     "epochs": int(np.median([d["epochs"] for d in runs[name]])),
                      "saturation_req_per_s": sat["req_per_s"],
                      "saturation_GBps": total_bytes / sat["span_s"] / 1e9,
                      "saturation_p99_ms": sat["p99_ms"], "saturation_max_batch": sat["max_batch"]}
     b, p = out["batched"], out["per_request"]
     out["p99_ratio"] = p["p99_ms"] / b["p99_ms"]
+    out["p50_ratio"] = p["p50_ms"] / b["p50_ms"]
+    out["p99_ci_disjoint"] = b["p99_ci95_ms"][1] < p["p99_ci95_ms"][0]
     out["throughput_ratio"] = b["saturation_req_per_s"] / p["saturation_req_per_s"]
     return out

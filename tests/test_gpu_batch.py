@@ -102,3 +102,42 @@ def test_batch_rejects_unsupported(dn):
     with pytest.raises(dn.DeinsumError):
         b.add("ijk,ja,ka->ia", X, U, precision="bf16x3")
     b.close()
+
+
+def test_batch_add_validates_like_mttkrp(dn):
+    """deinsum_batch_add_mttkrp rejects what deinsum_mttkrp rejects, before planning: a
+    hand-built spec whose free mode or factor modes are out of range or inconsistent,
+    misaligned pointers, and an output overlapping X or a factor.  Nothing is queued."""
+    import ctypes
+    lib = dn._lib.load()
+    b = dn.Batch()
+    X = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    U = [torch.zeros((8, 4), dtype=torch.float64, device="cuda") for _ in range(2)]
+    M = torch.zeros((8, 4), dtype=torch.float64, device="cuda")
+    dims = (ctypes.c_int64 * 3)(8, 8, 8)
+    o = dn._opts("fp64", torch.float64, None, 0, 0, None)
+
+    def add(sp, Xp=X.data_ptr(), Up=None, Mp=M.data_ptr()):
+        Up = Up or [u.data_ptr() for u in U]
+        ptrs = (ctypes.c_void_p * 2)(*Up)
+        return lib.deinsum_batch_add_mttkrp(b._h, ctypes.byref(sp), dims, 4, ctypes.c_void_p(Xp), ptrs,
+                                            ctypes.c_void_p(Mp), ctypes.byref(o), None)
+
+    good = dn.parse("ijk,ja,ka->ia")
+    bad = []
+    s = dn.parse("ijk,ja,ka->ia"); s.free_mode = 3; bad.append(s)
+    s = dn.parse("ijk,ja,ka->ia"); s.factor_mode[1] = 1; bad.append(s)           # mode 1 twice
+    s = dn.parse("ijk,ja,ka->ia"); s.factor_mode[0] = 0; bad.append(s)           # the free mode
+    s = dn.parse("ijk,ja,ka->ia"); s.factor_mode[1] = 7; bad.append(s)           # out of range
+    s = dn.parse("ijk,ja,ka->ia"); s.n_factors = 3; bad.append(s)
+    for sp in bad:
+        assert add(sp) == -1, dn.last_error()
+    assert add(good, Mp=X.data_ptr()) == -1                      # output is X
+    assert add(good, Mp=U[1].data_ptr()) == -1                   # output is a factor
+    assert add(good, Xp=X.data_ptr() + 4) == -1                  # misaligned X
+    assert add(good, Mp=M.data_ptr() + 4) == -1                  # misaligned M
+    assert add(good, Up=[U[0].data_ptr(), U[1].data_ptr() + 2]) == -1
+    assert b.info()["jobs"] == 0
+    assert add(good) == 0                                        # the well-formed call is accepted
+    assert b.info()["jobs"] == 1
+    b.close()

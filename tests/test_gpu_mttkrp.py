@@ -124,6 +124,36 @@ def test_run_to_run_bitwise(dn):
         assert torch.equal(a, b)
 
 
+def test_library_pool_per_stream(dn):
+    """Calls without a workspace of their own on two streams, enqueued back to back with
+    no synchronisation between them, each get their stream's pool buffer: every output
+    equals the same call run alone."""
+    rng = np.random.default_rng(11)
+    probs = []
+    for dims, R in (((96, 640, 320), 24), ((200, 48, 700), 40)):
+        X = to_dev(rng.uniform(-1, 1, dims))
+        U = [to_dev(rng.standard_normal((d, R))) for d in dims]
+        probs.append((X, U))
+    specs = [(p, n) for p in range(2) for n in range(3)]
+    need = [dn.workspace_size(SPEC3[n], tuple(probs[p][0].shape), [probs[p][1][0].shape[1]]) for p, n in specs]
+    assert sum(w > 0 for w in need) >= 2, need  # pool buffers are really in play on both streams
+    alone = {}
+    for p, n in specs:
+        X, U = probs[p]
+        alone[(p, n)] = dn.mttkrp(SPEC3[n], X, [U[m] for m in range(3) if m != n])
+        torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        outs = {}
+        for k, (p, n) in enumerate(specs):
+            X, U = probs[p]
+            outs[(p, n)] = dn.mttkrp(SPEC3[n], X, [U[m] for m in range(3) if m != n], stream=streams[k % 2])
+        torch.cuda.synchronize()
+        for key, out in outs.items():
+            assert torch.equal(out, alone[key]), (rep, key)
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("bf16x3", 1e-5), ("bf16", 2e-2)])
 def test_mixed_precision_error(dn, synth, oracle_mod, precision, tol):
     dims, R = (96, 128, 256), 24

@@ -42,10 +42,11 @@ def oracle_sweeps(oracle_mod, X, U, modes):
     return U
 
 
-def run_server(dn, tensors, requests, batched=True, arrivals=None, max_jobs=64):
+def run_server(dn, tensors, requests, batched=True, arrivals=None, max_jobs=64, single_direct=True):
     """tensors: list of (X, U, prec) host arrays; requests: list of (tensor, mode).
     Returns the device factors after serving, the server's results and stats."""
-    srv = dn.Server(batched=batched, max_jobs_per_epoch=max_jobs, max_requests=len(requests) + 8)
+    srv = dn.Server(batched=batched, max_jobs_per_epoch=max_jobs, max_requests=len(requests) + 8,
+                    single_direct=single_direct)
     dev = []
     for X, U, prec in tensors:
         Xd, Ud = device_copy(X, U, prec)
@@ -127,23 +128,45 @@ def c5_like(seed, count):
 
 
 def test_server_alone_vs_mix_bitwise(dn):
-    """Each tensor's factors after its requests are bitwise the same served alone, in the
-    full mix submitted at once, and in the mix arriving over time (different epochs)."""
+    """With single_direct off, each tensor's factors after its requests are bitwise the
+    same served alone, in the full mix submitted at once, and in the mix arriving over
+    time (different epochs)."""
     tensors = c5_like(7, 10)
     reqs = round_robin([3] * len(tensors), 2)
-    mix, (_, _, ep_mix), st_mix = run_server(dn, tensors, reqs)
+    mix, (_, _, ep_mix), st_mix = run_server(dn, tensors, reqs, single_direct=False)
     arrivals = np.arange(len(reqs)) * 2e-4
-    spread, (_, _, ep_sp), st_sp = run_server(dn, tensors, reqs, arrivals=arrivals)
+    spread, (_, _, ep_sp), st_sp = run_server(dn, tensors, reqs, arrivals=arrivals, single_direct=False)
     flush(f"mix epochs={st_mix['epochs']} max_batch={st_mix['max_batch']}; "
           f"spread epochs={st_sp['epochs']} max_batch={st_sp['max_batch']}")
     assert st_mix["max_batch"] > 1
     for k in (0, 3, 9):
-        alone, _, _ = run_server(dn, [tensors[k]], [(0, n) for t, n in reqs if t == k])
+        alone, _, _ = run_server(dn, [tensors[k]], [(0, n) for t, n in reqs if t == k], single_direct=False)
         for m in range(3):
             assert np.array_equal(alone[0][m], mix[k][m]), (k, m)
     for k in range(len(tensors)):
         for m in range(3):
             assert np.array_equal(spread[k][m], mix[k][m]), (k, m)
+
+
+def test_server_alone_vs_mix_single_direct(dn, oracle_mod):
+    """With single_direct on (the default), a tensor served alone runs every request with
+    the per-request launches; its factors match the mix (batched epochs) within the
+    form's tolerance, and both match the oracle's sweeps."""
+    tensors = c5_like(7, 10)
+    reqs = round_robin([3] * len(tensors), 2)
+    mix, _, st_mix = run_server(dn, tensors, reqs)
+    assert st_mix["max_batch"] > 1
+    for k in (0, 3, 9):
+        alone, (_, _, ep), st = run_server(dn, [tensors[k]], [(0, n) for t, n in reqs if t == k])
+        assert st["max_batch"] == 1
+        X, U, prec = tensors[k]
+        ref = oracle_sweeps(oracle_mod, X, U, [n for t, n in reqs if t == k])
+        tol = 1e-10 if prec == "fp64" else 5e-4
+        for m in range(3):
+            flush(f"  tensor {k} ({prec}) mode {m}: alone vs mix {nrel(alone[0][m], mix[k][m]):.2e}, "
+                  f"alone vs oracle {nrel(alone[0][m], ref[m]):.2e}")
+            assert nrel(alone[0][m], mix[k][m]) <= tol, (k, m)
+            assert nrel(alone[0][m], ref[m]) <= tol, (k, m)
 
 
 def test_server_batched_matches_per_request(dn):

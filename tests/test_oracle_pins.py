@@ -192,14 +192,18 @@ def test_order2_is_gemm(oracle_mod):
 
 
 def test_two_step_equivalence(oracle_mod):
-    """The paper's decomposition: KRP t0 = ja,ka->jka, then tensordot over (j,k)."""
+    """Sec. II-A: MTTKRP equals the mode-0 unfolding of X times the Khatri-Rao product
+    of the other factors, formed here as an explicit (J*K) x R matrix whose row j*K + k
+    is the elementwise product of row j of B and row k of C."""
     rng = np.random.default_rng(6)
     I, J, K, R = 6, 5, 4, 3
     X = rng.standard_normal((I, J, K))
     B, C = rng.standard_normal((J, R)), rng.standard_normal((K, R))
-    t0 = B[:, None, :] * C[None, :, :]
-    t1 = np.tensordot(X, t0, axes=([1, 2], [0, 1]))
-    assert nrel(oracle_mod.mttkrp(X, [None, B, C], 0), t1) <= 1e-14
+    krp = np.empty((J * K, R))
+    for j in range(J):
+        for k in range(K):
+            krp[j * K + k] = B[j] * C[k]
+    assert nrel(oracle_mod.mttkrp(X, [None, B, C], 0), X.reshape(I, J * K) @ krp) <= 1e-14
 
 
 def test_linearity(oracle_mod):
