@@ -72,6 +72,23 @@ __device__ __forceinline__ float bf16_bits_to_f32(uint16_t h)
     return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+// Two FP32 values rounded to BF16 (nearest even, as f32_to_bf16_bits for every finite
+// value) by one packed conversion instruction; v[0] in the low half.
+__device__ __forceinline__ uint32_t f32x2_to_bf16x2_bits(f32x2 v)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+// Split of two FP32 values into BF16 hi = RNE(x) and lo = RNE(x - hi) (x - hi is exact
+// in FP32), packed two per word: three conversions and two subtractions per pair.
+__device__ __forceinline__ void split_bf16x2(f32x2 v, uint32_t &hi, uint32_t &lo)
+{
+    hi = f32x2_to_bf16x2_bits(v);
+    const f32x2 hf = {__uint_as_float(hi << 16), __uint_as_float(hi & 0xffff0000u)};
+    lo = f32x2_to_bf16x2_bits(v - hf);
+}
+
 __device__ __forceinline__ double to_f64(double x) { return x; }
 __device__ __forceinline__ double to_f64(float x) { return static_cast<double>(x); }
 __device__ __forceinline__ double to_f64(bf16_t x) { return static_cast<double>(bf16_bits_to_f32(x.u)); }

@@ -531,13 +531,11 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
                     for (int nt = 0; nt < NT; ++nt) d[mt][nt] = mfma_bf16(xa, frh[q * NT + nt], d[mt][nt]);
                 } else {
                     u16x8 xh, xl;
+                    uint32_t wh[4], wl[4];
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const float xv = xe(e);
-                        const uint16_t h = f32_to_bf16_bits(xv);
-                        xh[e] = h;
-                        xl[e] = f32_to_bf16_bits(xv - bf16_bits_to_f32(h));
-                    }
+                    for (int j = 0; j < 4; ++j) split_bf16x2(f32x2{xe(2 * j), xe(2 * j + 1)}, wh[j], wl[j]);
+                    __builtin_memcpy(&xh, wh, 16);
+                    __builtin_memcpy(&xl, wl, 16);
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) {
                         d[mt][nt] = mfma_bf16(xh, frh[q * NT + nt], d[mt][nt]);
