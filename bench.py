@@ -48,6 +48,9 @@ def parse_args():
                     help="print a kernel-time table from a rocprofv3 kernel_trace.csv and exit (no GPU)")
     ap.add_argument("--summarize-pmc", default="", metavar="CSV",
                     help="print a per-kernel counter table from a rocprofv3 counter_collection.csv and exit")
+    ap.add_argument("--summarize-workloads", nargs=4, default=None, metavar=("TRACE", "FETCH", "WRITE", "MFMA"),
+                    help="print per-workload kernel time, HBM bytes and matrix-core use from a kernel_trace.csv and "
+                         "three counter_collection.csv files (FETCH_SIZE, WRITE_SIZE, MfmaUtil passes) and exit")
     ap.add_argument("--last", type=int, default=0, help="--summarize-*: steady state = the last N launches per kernel")
     ap.add_argument("--bytes", type=float, default=0.0,
                     help="--summarize-trace: algorithmic bytes per launch of the kernel named by --kernel")
@@ -356,7 +359,7 @@ def summarize_pmc(path, dominant):
     rows = _csv_rows(path)
     disp = {}
     for r in rows:
-        key = (_col(r, "Dispatch_Id", "Dispatch_ID", "dispatch"), _short(_col(r, "Kernel_Name", "KernelName", "Name")))
+        key = (int(_col(r, "Dispatch_Id", "Dispatch_ID", "dispatch")), _short(_col(r, "Kernel_Name", "KernelName", "Name")))
         cname = _col(r, "Counter_Name", "CounterName")
         disp.setdefault(key, {}).setdefault(cname, 0.0)
         disp[key][cname] += float(_col(r, "Counter_Value", "CounterValue"))
@@ -364,17 +367,24 @@ def summarize_pmc(path, dominant):
     for (_, name), cs in disp.items():
         for c, v in cs.items():
             per.setdefault(name, {}).setdefault(c, []).append(v)
+    # The calibration copy: the runtime copy dispatches issued before the first kernel of
+    # the library (the 1 GiB probe runs before X is generated); later copies are uploads.
+    first_lib = min((d for d, name in disp if "copyBuffer" not in name and "at::" not in name), default=None)
+    probe = {c: sum(cs.get(c, 0.0) for (d, name), cs in disp.items()
+                    if "copyBuffer" in name and (first_lib is None or d < first_lib))
+             for c in ("FETCH_SIZE", "WRITE_SIZE")}
     counters = sorted({c for cs in per.values() for c in cs})
     print(f"{'kernel':<70} {'n':>4} " + " ".join(f"{c:>14}" for c in counters))
     for name, cs in sorted(per.items(), key=lambda kv: kv[0]):
         n = max(len(v) for v in cs.values())
         print(f"{name[:70]:<70} {n:>4} " + " ".join(f"{statistics.mean(cs[c]) if c in cs else 0.0:>14.1f}"
                                                     for c in counters))
-    copy = [n for n in per if "copyBuffer" in n]
-    if copy and dominant:
+    if dominant and any(probe.values()):
         gib_kib = float(1 << 20)
-        cs = per[copy[0]]
-        scale = {c: gib_kib / sum(cs[c]) for c in ("FETCH_SIZE", "WRITE_SIZE") if c in cs and sum(cs[c]) > 0}
+        scale = {c: gib_kib / v for c, v in probe.items() if v > 0}
+        for c, v in probe.items():
+            if v > 0:
+                print(f"calibration copy (1 GiB read + 1 GiB written): {c} {v:.1f} KiB -> scale {gib_kib / v:.4f}")
         hits = [n for n in per if dominant in n]
         for h in hits:
             for c, sc in scale.items():
@@ -384,8 +394,77 @@ def summarize_pmc(path, dominant):
                           f"{kib * sc * 1024:.0f} bytes")
 
 
+def _launch_groups(path, is_trace):
+    """Dispatches of the matrix-core kernels grouped by (kernel, grid size, run): a run is a
+    stretch of launches of one kernel and grid no more than 50 dispatches apart, so the
+    calls of one workload and form (its warm-up launch first) form one group."""
+    rows = _csv_rows(path)
+    per = {}
+    for r in rows:
+        d = int(_col(r, "Dispatch_Id", "Dispatch_ID"))
+        name = _short(_col(r, "Kernel_Name", "KernelName"))
+        if not any(k in name for k in ("stream_kernel", "ttmc_fused", "small_ttm")):
+            continue
+        grid = int(_col(r, "Grid_Size_X", "Grid_Size")) if is_trace else int(_col(r, "Grid_Size"))
+        e = per.setdefault(d, {"name": name, "grid": grid, "c": {}})
+        if is_trace:
+            e["c"]["us"] = (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e3
+        else:
+            c = _col(r, "Counter_Name")
+            e["c"][c] = e["c"].get(c, 0.0) + float(_col(r, "Counter_Value"))
+    groups = {}
+    for d in sorted(per):
+        e = per[d]
+        runs = groups.setdefault((e["name"], e["grid"]), [])
+        if not runs or d - runs[-1][-1][0] > 50:
+            runs.append([])
+        runs[-1].append((d, e["c"]))
+    return groups
+
+
+def summarize_workloads(trace, fetch, write, mfma):
+    """Per (kernel, grid, run): launches, steady-state median duration (the run without its
+    first launch), HBM bytes per launch from FETCH_SIZE / WRITE_SIZE scaled by the 1 GiB
+    calibration copy, matrix-core utilisation and executed matrix-core GFLOP per launch."""
+    def probe_scale(path, c):
+        rows = _csv_rows(path)
+        first_lib, tot = None, 0.0
+        disp = {}
+        for r in rows:
+            d = int(_col(r, "Dispatch_Id")); name = _col(r, "Kernel_Name")
+            if _col(r, "Counter_Name") == c:
+                disp[d] = (name, disp.get(d, (name, 0.0))[1] + float(_col(r, "Counter_Value")))
+        libs = [d for d, (n, _) in disp.items() if "copyBuffer" not in n and "at::" not in n]
+        first_lib = min(libs) if libs else None
+        tot = sum(v for d, (n, v) in disp.items() if "copyBuffer" in n and (first_lib is None or d < first_lib))
+        return float(1 << 30) / (tot * 1024) if tot else None
+    sf, sw = probe_scale(fetch, "FETCH_SIZE"), probe_scale(write, "WRITE_SIZE")
+    print(f"calibration: FETCH_SIZE x {sf:.4f}, WRITE_SIZE x {sw:.4f} (1 GiB device copy before the first library kernel)")
+    gt, gf, gw, gm = (_launch_groups(trace, True), _launch_groups(fetch, False), _launch_groups(write, False),
+                      _launch_groups(mfma, False))
+    print(f"{'kernel':<52} {'grid':>8} {'run':>3} {'n':>3} {'steady us':>10} {'HBM GB':>8} {'GB/s':>7} "
+          f"{'MfmaUtil':>8} {'F64 GF':>7} {'F16 GF':>7}")
+    for key in sorted(gf, key=lambda k: gf[k][0][0][0]):
+        for ri, run in enumerate(gf[key]):
+            fb = statistics.mean(c.get("FETCH_SIZE", 0.0) for _, c in run) * 1024 * sf
+            wr = gw.get(key, [])
+            wb = statistics.mean(c.get("WRITE_SIZE", 0.0) for _, c in wr[ri]) * 1024 * sw if ri < len(wr) else float("nan")
+            tr = gt.get(key, [])
+            us = statistics.median([c["us"] for _, c in tr[ri][1:]] or [c["us"] for _, c in tr[ri]]) if ri < len(tr) else float("nan")
+            mr = gm.get(key, [])
+            mu = statistics.mean(c.get("MfmaUtil", 0.0) for _, c in mr[ri]) if ri < len(mr) else float("nan")
+            f64 = statistics.mean(c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for _, c in mr[ri]) * 512 / 1e9 if ri < len(mr) else float("nan")
+            f16 = statistics.mean(c.get("SQ_INSTS_VALU_MFMA_MOPS_F16", 0.0) for _, c in mr[ri]) * 512 / 1e9 if ri < len(mr) else float("nan")
+            hbm = fb + wb
+            print(f"{key[0][:52]:<52} {key[1]:>8} {ri:>3} {len(run):>3} {us:>10.1f} {hbm / 1e9:>8.3f} "
+                  f"{hbm / (us * 1e-6) / 1e9:>7.0f} {mu:>8.1f} {f64:>7.2f} {f16:>7.2f}")
+
+
 def main():
     args = parse_args()
+    if args.summarize_workloads:
+        summarize_workloads(*args.summarize_workloads)
+        return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.last, args.kernel, args.bytes)
         return

@@ -129,6 +129,10 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_FP64, L_MCONTIG, 1, 8, 2, 3), SK(P_FP64, L_MCONTIG, 2, 8, 2, 2), SK(P_FP64, L_MCONTIG, 4, 8, 1, 2),
     SK(P_FP32, L_MCONTIG, 1, 8, 4, 3), SK(P_FP32, L_MCONTIG, 2, 8, 2, 3), SK(P_FP32, L_MCONTIG, 4, 8, 2, 2),
     SKN(P_FP32, L_MCONTIG, 1, 8, 4, 3), SKN(P_FP32, L_MCONTIG, 2, 8, 2, 3), SKN(P_FP32, L_MCONTIG, 4, 8, 2, 2),
+    // 64-index tiles: a contiguous mode of at most 64 is one tile, so no row of X is split
+    // between workgroups (60^5 last mode: 480-byte rows)
+    SKN(P_FP64, L_MCONTIG, 2, 4, 4, 3), SK(P_FP64, L_MCONTIG, 2, 4, 4, 3), SKN(P_FP64, L_MCONTIG, 2, 2, 4, 3),
+    SKN(P_FP32, L_MCONTIG, 2, 4, 4, 3), SK(P_FP32, L_MCONTIG, 2, 4, 4, 3),
     SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
     SKN(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SKN(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SKN(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),

@@ -116,15 +116,22 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
         // An entry for a variant that is no longer compiled falls back to the heuristic.
     }
     const StreamKernelInfo *best = nullptr;
-    int64_t best_padded = 0;
+    int64_t best_padded = 0, best_split = 0;
+    // Short contiguous output mode (M-contiguous, rows under 64 elements): among equal
+    // K padding, fewer row tiles per X row (a row split between workgroups is read in
+    // partial cache lines twice).
+    auto row_tiles = [&](const StreamKernelInfo &k) -> int64_t {
+        return (layout == L_MCONTIG && pb.dims[n] <= 64) ? cdiv(pb.dims[n], 16LL * k.mt) : 0;
+    };
     for (int i = 0; i < count; ++i) {
         const StreamKernelInfo &k = table[i];
         if (k.prec != pb.prec || k.layout != layout || k.nt != nt) continue;
         const int64_t slice = 4LL * k.ni * ke_of(pb.prec, layout);
         const int64_t padded = cdiv(Ig, slice) * slice;
-        if (!best || padded < best_padded) {
+        if (!best || padded < best_padded || (padded == best_padded && row_tiles(k) < best_split)) {
             best = &k;
             best_padded = padded;
+            best_split = row_tiles(k);
         }
     }
     // Forms without a kernel of this column width take narrower tiles (more column blocks).

@@ -468,10 +468,30 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
         for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[mt][nt][v] = 0.0;
+    // FP64 with 64-index tiles: the step's Hadamard weights scale the factor operand
+    // (one multiply per operand register) and the matrix cores accumulate straight into
+    // acc across steps, so no per-step product tile is held (it does not fit beside the
+    // accumulators and the ring).
+    constexpr bool WB = (P == P_FP64 && MT >= 4);
 
     // One step: stage 1 on the matrix cores, then the Hadamard fold (stage 2).
     auto step = [&](const XT *x, const double *wv) {
-        if constexpr (FX16) {
+        if constexpr (WB) {
+#pragma unroll
+            for (int q = 0; q < NI; ++q)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const double b = fr64[q * NT + nt] * wv[nt];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const double xa = (L == L_KCONTIG) ? x[q] : x[q * MT + mt];
+                        f64x4 t = {acc[mt][nt][0], acc[mt][nt][1], acc[mt][nt][2], acc[mt][nt][3]};
+                        t = mfma_f64(xa, b, t);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[mt][nt][v] = t[v];
+                    }
+                }
+        } else if constexpr (FX16) {
             // sum_k (256 h + l) u' = 256 (h.uh + h.ul + ((1152 + l)/256).uh) - 1152 sum uh
             DT dh[MT][NT];
 #pragma unroll

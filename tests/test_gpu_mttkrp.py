@@ -369,3 +369,35 @@ def test_order3_mode0_never_merges_last_modes(dn, synth, oracle_mod, precision, 
     assert not name.endswith(" m2"), name
     tol = {"fx20": 4e-6, "bf16x3": 1e-5, "bf16": 2e-2}[precision]
     assert nrel(got.cpu().numpy(), oracle_mod.mttkrp(X, U, 0)) <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("dims", [(30, 50, 60), (7, 9, 11, 64), (40, 33, 45), (20, 24, 17)])
+def test_short_last_mode(dn, oracle_mod, prec, tol, dims):
+    """Last-mode MTTKRP whose contiguous output mode has at most 64 elements: the default
+    plan keeps each X row in one 64-index tile when 32 < I_last <= 64 (the FP64 form then
+    scales the factor operand by the step weights and accumulates on the matrix cores);
+    uniform inputs against the oracle, integer inputs exact."""
+    rng = np.random.default_rng(sum(dims))
+    N, n, R = len(dims), len(dims) - 1, 24
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    for dist in ("uniform", "int"):
+        if dist == "uniform":
+            X = rng.uniform(-1, 1, dims)
+            U = [rng.standard_normal((d, R)) for d in dims]
+        else:
+            X = rng.integers(-3, 4, dims).astype(np.float64)
+            U = [rng.integers(-2, 3, (d, R)).astype(np.float64) for d in dims]
+        rep = dn.Report()
+        M = dn.mttkrp(mttkrp_spec(N, n), to_dev(X, dt), [to_dev(U[m], dt) for m in range(N - 1)], precision=prec,
+                      out_dtype=torch.float64, report=rep)
+        torch.cuda.synchronize()
+        name = rep.plan_name.decode()
+        flush(f"short last mode {dims} {prec} {dist}: {name}")
+        if 32 < dims[-1] <= 64:
+            assert ",mt4" in name, name
+        ref = oracle_mod.mttkrp(X, U[:-1] + [None], n)
+        if dist == "uniform":
+            assert nrel(M.cpu().numpy(), ref) <= tol
+        else:
+            assert np.array_equal(M.cpu().numpy(), ref)
