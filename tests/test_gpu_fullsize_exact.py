@@ -85,7 +85,7 @@ def test_ttmc_full_size_integer_exact(dn, synth, oracle_mod, dims, rank):
 def test_order5_60_last_mode_and_ttmc(dn, synth, oracle_mod):
     """The paper's order-5 forms at I = 60, R = 24: MTTKRP in the last mode (FP64, sampled
     rows against the oracle) and TTMc in mode 0 (FP64 on integer inputs, sampled slabs
-    exact; FP32 and BF16 forms within their bounds against the FP64 result)."""
+    exact; the FP32, BF16 and FX20 forms exact too on these integer inputs)."""
     dims, R = (60,) * 5, 24
     seed = synth.config_seed(3, 70)
     X = torch.empty(dims, dtype=torch.float64, device="cuda")
@@ -107,11 +107,12 @@ def test_order5_60_last_mode_and_ttmc(dn, synth, oracle_mod):
     dn.convert(X, X32)
     X16 = torch.empty(dims, dtype=torch.bfloat16, device="cuda")
     dn.convert(X, X16)
-    for prec, Xp in (("fp32", X32), ("bf16", X16)):
+    Xf = dn.to_fx20(X)
+    for prec, Xp in (("fp32", X32), ("bf16", X16), ("fx20", Xf)):
         flush(f"60^5 TTMc mode 0 {prec}")
         Yp = dn.ttmc(ttmc_spec(5, 0), Xp, [to_dev(U[m], torch.float32) for m in range(1, 5)], precision=prec,
                      out_dtype=torch.float64)
         torch.cuda.synchronize()
         assert torch.equal(Yp, Y), prec  # integer inputs: exact in every form
-    del X, X32, X16, Y
+    del X, X32, X16, Xf, Y
     torch.cuda.empty_cache()
