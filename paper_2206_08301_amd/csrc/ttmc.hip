@@ -770,10 +770,11 @@ const TkEntry kTkTable[] = {
     TK(P_BF16, 4, 4, 2, 1, 2),
     TK(P_BF16, 1, 1, 4, 1, 3), TK(P_BF16, 1, 1, 8, 1, 2), TKN(P_BF16, 2, 2, 4, 1, 3), TK(P_BF16, 2, 2, 4, 1, 2),
     TKN(P_BF16, 2, 2, 4, 1, 2),
-    TK(P_FX20, 1, 1, 4, 1, 2), TK(P_FX20, 1, 2, 4, 1, 2), TK(P_FX20, 1, 4, 4, 1, 2), TK(P_FX20, 2, 1, 4, 1, 2),
-    TK(P_FX20, 2, 2, 4, 1, 2), TK(P_FX20, 2, 4, 4, 1, 2), TK(P_FX20, 4, 1, 4, 1, 2), TK(P_FX20, 4, 2, 4, 1, 2),
+    TK(P_FX20, 1, 1, 4, 2, 2), TK(P_FX20, 1, 2, 4, 1, 2), TK(P_FX20, 1, 4, 4, 1, 2), TK(P_FX20, 2, 1, 4, 1, 2),
+    TK(P_FX20, 2, 2, 4, 1, 3), TK(P_FX20, 2, 4, 4, 1, 2), TK(P_FX20, 4, 1, 4, 1, 2), TK(P_FX20, 4, 2, 4, 1, 2),
     TK(P_FX20, 4, 4, 4, 1, 2),
-    TKN(P_FX20, 1, 1, 4, 1, 2), TK(P_FX20, 1, 1, 4, 1, 3), TKN(P_FX20, 2, 2, 4, 1, 2), TK(P_FX20, 2, 2, 4, 1, 3),
+    TK(P_FX20, 1, 1, 4, 1, 2), TKN(P_FX20, 1, 1, 4, 1, 2), TK(P_FX20, 1, 1, 4, 1, 3), TKN(P_FX20, 1, 1, 4, 2, 2),
+    TKN(P_FX20, 2, 2, 4, 1, 2), TK(P_FX20, 2, 2, 4, 1, 2),
     TKN(P_FX20, 2, 2, 4, 1, 3), TK(P_FX20, 2, 2, 4, 1, 4), TK(P_FX20, 2, 2, 4, 2, 2),
     TK1(P_FP64, 1, 4, 2, 4), TK1(P_FP64, 2, 2, 2, 4), TK1(P_FP64, 4, 1, 2, 4),
     TK1(P_FP32, 1, 4, 2, 4), TK1(P_FP32, 2, 4, 2, 4), TK1(P_FP32, 4, 2, 2, 4),
