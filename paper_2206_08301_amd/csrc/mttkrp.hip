@@ -118,7 +118,7 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16, L_KCONTIG, 1, 1, 1, 3),  SK(P_BF16, L_KCONTIG, 2, 1, 1, 3),
     SK(P_BF16X3, L_KCONTIG, 1, 4, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 4, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_KCONTIG, 1, 3, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 3, 1, 2), SK(P_BF16X3, L_KCONTIG, 4, 3, 1, 2),
-    SK(P_BF16X3, L_KCONTIG, 1, 1, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 1, 1, 3),
+    SK(P_BF16X3, L_KCONTIG, 1, 1, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 1, 1, 3), SK(P_BF16X3, L_KCONTIG, 2, 2, 1, 4),
     // FX20: FP16 matrix cores; runs of 16 elements per chunk (32 bytes of the FP16 plane, 16 of the int8 plane)
     SK(P_FX20, L_KCONTIG, 1, 4, 1, 3), SK(P_FX20, L_KCONTIG, 2, 4, 1, 3), SK(P_FX20, L_KCONTIG, 4, 2, 1, 2),
     SK(P_FX20, L_KCONTIG, 1, 2, 1, 3), SK(P_FX20, L_KCONTIG, 2, 2, 1, 3),
@@ -136,6 +136,7 @@ static const StreamKernelInfo kStreamTable[] = {
     SK(P_BF16, L_MCONTIG, 1, 2, 4, 2), SK(P_BF16, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16, L_MCONTIG, 4, 2, 1, 2),
     SK(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SK(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SK(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
     SKN(P_BF16X3, L_MCONTIG, 1, 2, 2, 3), SKN(P_BF16X3, L_MCONTIG, 2, 2, 2, 2), SKN(P_BF16X3, L_MCONTIG, 4, 2, 1, 2),
+    SK(P_BF16X3, L_MCONTIG, 2, 1, 4, 2), SKN(P_BF16X3, L_MCONTIG, 2, 1, 4, 2),
     // FX20: 8 slice rows per instruction, MT output indices per lane (2*MT bytes of the FP16 plane and
     // MT of the int8 plane per row)
     SK(P_FX20, L_MCONTIG, 2, 1, 4, 2), SKN(P_FX20, L_MCONTIG, 2, 1, 4, 2), SK(P_FX20, L_MCONTIG, 2, 1, 2, 3),
