@@ -152,7 +152,9 @@ typedef struct deinsum_opts {
     size_t workspace_bytes;   /* its size                                            */
     int32_t plan_hint;        /* MTTKRP: 0 = autotuned plan if cached, else the
                                  heuristic; 1 / 2 = heuristic, and the free mode
-                                 must be < N-1 / = N-1 (tests).
+                                 must be < N-1 / = N-1 (tests); 3 = free mode 0
+                                 of an order-3 tensor, reduced forms: mode-1
+                                 tiles walked per output row (tests).
                                  TTMc: 0 = autotuned fused-kernel variant if cached,
                                  else the default; k >= 1 = compiled variant k-1
                                  for the ranks (tests, tuning)                        */

@@ -475,7 +475,8 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
         ws = static_cast<char *>(ws_all) + c.krp_bytes;
     }
     const int N = pb.N, n = pb.n;
-    const bool kcontig = p.family == PLAN_MTTKRP_KCONTIG;
+    const bool kout = p.family == PLAN_MTTKRP_KOUT;
+    const bool kcontig = p.family == PLAN_MTTKRP_KCONTIG || kout;
     const int gmode = kcontig ? N - 1 : N - 2;
     const size_t ub = u_elem_bytes(pb.prec), xb = x_elem_bytes(pb.prec);
     int64_t stride[DEINSUM_MAX_ORDER];
@@ -521,6 +522,11 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
         a.wk = p.wk;
         a.O = 1;
         for (int i = 0; i < k; ++i) a.O *= a.od.dim[i];
+        const int64_t w_rows = a.O;  // rows of the outer-weight table
+        if (kout) {
+            a.O = pb.dims[0];  // the walk's outer range: output rows (od holds mode 1)
+            a.n_tiles = static_cast<int>(p.n_tiles);
+        }
         a.o_per_chunk = p.o_per_chunk;
         a.order = p.order;
         a.xcd_remap = p.xcd;
@@ -535,13 +541,22 @@ deinsum_status run_mttkrp(const MttkrpCall &c, void *ws_all, hipStream_t s)
         double *W = reinterpret_cast<double *>(static_cast<char *>(ws) + p.w_offset);
         a.W = W;
         a.ldw = cols_pad;
-        if (deinsum_status st = launch_outer_weights(a.od, a.O, pb.R, ncols, cols_pad, pb.prec, W, s)) return st;
+        if (kout) {
+            if (deinsum_status st = launch_kout_weights(a.od.U[0], pb.dims[1], pb.R, ncols, p.nt, pb.prec,
+                                                        reinterpret_cast<float *>(W), s))
+                return st;
+        } else if (deinsum_status st = launch_outer_weights(a.od, w_rows, pb.R, ncols, cols_pad, pb.prec, W, s)) {
+            return st;
+        }
         const int kt = ktimer_begin(s, KK_MTTKRP_STREAM);
         const deinsum_status lst = launch_mttkrp_stream(*p.kernel, a, p.groups, p.waves, s);
         ktimer_end(kt, s);
         if (lst) return lst;
-        if (deinsum_status st = launch_reduce_partials(a.P, p.parts, p.n_tiles, p.tile_rows, cols_pad, pb.dims[n],
-                                                       ncols, static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
+        // L_KOUT partials are [slice][row][col]: one tile of all I_0 rows per partial.
+        if (deinsum_status st = launch_reduce_partials(a.P, p.parts, kout ? 1 : p.n_tiles,
+                                                       kout ? static_cast<int>(pb.dims[0]) : p.tile_rows,
+                                                       cols_pad, pb.dims[n], ncols,
+                                                       static_cast<char *>(c.M) + col0 * dtype_bytes(c.out_dtype),
                                                        c.out_dtype, pb.R, hx, nx, s))
             return st;
     }
@@ -842,7 +857,8 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
     for (int k = 0; k < spec->order - 1; ++k) c.U[spec->factor_mode[k]] = U[k];
     c.X = X;
     c.M = M;
-    const int layout = c.plan.family == PLAN_MTTKRP_KCONTIG ? L_KCONTIG : L_MCONTIG;
+    const int layout = c.pb.n == c.pb.N - 1 ? L_MCONTIG : L_KCONTIG;
+    const bool try_kout = c.pb.N == 3 && c.pb.n == 0 && c.pb.prec != P_FP64 && c.pb.dims[0] < (int64_t(1) << 31);
     const char *vb = std::getenv("DEINSUM_TUNE_VERBOSE");
     const bool verbose = vb && vb[0] && vb[0] != '0';
     int count = 0;
@@ -852,13 +868,14 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
     TuneChoice choice;
     for (int i = 0; i < count; ++i) {
         const StreamKernelInfo &k = table[i];
-        if (k.prec != c.pb.prec || k.layout != layout) continue;
+        const bool kout = k.layout == L_KOUT;
+        if (k.prec != c.pb.prec || (k.layout != layout && !(kout && try_kout))) continue;
         MttkrpPlan p0;
         if (plan_geometry(c.pb, &k, 0, &p0) != DEINSUM_OK) continue;
         int splits[8];
         const int ns = tune_splits(p0.n_chunks, p0.O, splits);
         for (int si = 0; si < ns; ++si)
-            for (int variant = 0; variant < 4; ++variant) {
+            for (int variant = 0; variant < (kout ? 1 : 4); ++variant) {
                 MttkrpCall cc = c;
                 cc.via_ttmc = false;
                 if (deinsum_status st = plan_geometry(c.pb, &k, splits[si], &cc.plan)) return st;
@@ -879,7 +896,7 @@ deinsum_status deinsum_tune_mttkrp(const deinsum_spec *spec, const int64_t *dims
                     choice.mt = k.mt;
                     choice.xnt = k.xnt;
                     choice.split = splits[si];
-                    choice.order = cc.plan.order;
+                    choice.order = kout ? kTuneKout : cc.plan.order;
                     choice.xcd = cc.plan.xcd;
                     choice.us = us;
                 }

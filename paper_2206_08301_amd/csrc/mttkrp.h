@@ -12,6 +12,8 @@ namespace deinsum {
 enum StreamLayout {
     L_KCONTIG = 0,  // free mode n < N-1, matrix-core K over the contiguous mode N-1
     L_MCONTIG = 1,  // free mode n = N-1 (the contiguous one), K over mode N-2
+    L_KOUT = 2,     // order 3, free mode 0: matrix-core rows over mode 1, K over mode 2;
+                    // the walk takes output rows outside and mode-1 tiles inside
 };
 
 // One launch processes one column block of the output.
@@ -23,6 +25,12 @@ enum StreamLayout {
 //   unit u: kgroup = u % n_kgroups, then (order 0) tile = (u / n_kgroups) % n_tiles,
 //     chunk = rest, or (order 1) chunk = (u / n_kgroups) % n_chunks, tile = rest;
 //   wave w: slice kgroup*wk + w % wk of mode g, outer sub-range w / wk of the chunk.
+// L_KOUT (order 3, n = 0): unit u -> kgroup = u % n_kgroups, chunk = u / n_kgroups of
+//   the output rows i (O = I_0 of them, o_per_chunk per chunk); a wave walks its rows
+//   i and, for each, the n_tiles 16-row tiles of mode 1 (od.dim[0] = I_1 rows of
+//   stride od.xstride[0]; W = U^1 in FP32 packed per tile and lane,
+//   [n_tiles][64 lanes][4 tile rows][NT] (kout_weights_kernel)); each row's sum over mode 1
+//   is written to P[slice][i][ldw] (n_kgroups * wk partials, no tile structure).
 struct StreamArgs {
     const void *X;       // FX20: the 16-bit plane
     const void *X2;      // FX20: the 8-bit plane (unused otherwise)
@@ -57,6 +65,11 @@ struct StreamKernelInfo {
 const StreamKernelInfo *stream_kernels(int *count);
 deinsum_status launch_mttkrp_stream(const StreamKernelInfo &k, const StreamArgs &a, int64_t grid, int waves,
                                     hipStream_t s);
+// L_KOUT weights: U^1's column block in FP32 as [tile][lane][v][nt] =
+// U^1[16 tile + 4 (lane / 16) + v][16 nt + lane % 16] (zero past I_1 or ncols), the
+// FP32 matrix-core output rows each lane holds.
+deinsum_status launch_kout_weights(const void *U1, int64_t I1, int64_t ldu, int ncols, int nt, int prec, float *W,
+                                   hipStream_t s);
 deinsum_status launch_outer_weights(const OuterDesc &od, int64_t O, int64_t ldu, int ncols, int ldw, int prec,
                                     double *W, hipStream_t s);
 // hx (FX20 only, else null): the header of X; the sums are scaled by 2^exp2, and

@@ -62,6 +62,20 @@ __global__ void __launch_bounds__(256) outer_weights_kernel(const OuterDesc od, 
     W[e] = w;
 }
 
+__global__ void __launch_bounds__(256) kout_weights_kernel(const void *U1, int64_t I1, int64_t ldu, int ncols,
+                                                           int nt, int prec, float *__restrict__ W, int64_t total)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int ntt = static_cast<int>(e % nt);
+    const int v = static_cast<int>((e / nt) % 4);
+    const int lane = static_cast<int>((e / (4 * nt)) % 64);
+    const int64_t tile = e / (256 * nt);
+    const int64_t row = tile * 16 + 4 * (lane >> 4) + v;
+    const int col = ntt * 16 + (lane & 15);
+    W[e] = (row < I1 && col < ncols) ? static_cast<float>(ld_u(U1, row * ldu + col, prec)) : 0.0f;
+}
+
 // Fixed-order FP64 sum of the partial tiles into the output column block.
 // P layout: [part][tile][tile_rows][cols_pad]; output row i lives in tile i / tile_rows.
 template <typename OT>
@@ -122,6 +136,11 @@ static const StreamKernelInfo kStreamTable[] = {
     // FX20: FP16 matrix cores; runs of 16 elements per chunk (32 bytes of the FP16 plane, 16 of the int8 plane)
     SK(P_FX20, L_KCONTIG, 1, 4, 1, 3), SK(P_FX20, L_KCONTIG, 2, 4, 1, 3), SK(P_FX20, L_KCONTIG, 4, 2, 1, 2),
     SK(P_FX20, L_KCONTIG, 1, 2, 1, 3), SK(P_FX20, L_KCONTIG, 2, 2, 1, 3),
+    // Order-3 mode 0, mode-1 tiles walked per output row (the K-contiguous tile and loads)
+    SK(P_FP32, L_KOUT, 1, 32, 1, 3), SK(P_FP32, L_KOUT, 2, 32, 1, 3),
+    SK(P_BF16, L_KOUT, 1, 8, 1, 2), SK(P_BF16, L_KOUT, 2, 8, 1, 2), SK(P_BF16, L_KOUT, 4, 4, 1, 2),
+    SK(P_BF16X3, L_KOUT, 1, 4, 1, 3), SK(P_BF16X3, L_KOUT, 2, 4, 1, 2),
+    SK(P_FX20, L_KOUT, 1, 4, 1, 3), SK(P_FX20, L_KOUT, 2, 4, 1, 3),
     // M-contiguous: NI K-steps of 4*KE rows; MT output indices per lane
     // (FP64: non-temporal X loads first -- they keep the per-K-step factor rows cached, 1.50 -> 1.37 ms
     //  for the 1024^3 R=24 last mode; the K-contiguous kernels lose with them and keep plain loads.)
@@ -165,6 +184,14 @@ deinsum_status launch_outer_weights(const OuterDesc &od, int64_t O, int64_t ldu,
     const int64_t total = O * ldw;
     outer_weights_kernel<<<static_cast<unsigned>((total + 255) / 256), 256, 0, s>>>(od, O, ldu, ncols, ldw, prec, W);
     return check_launch("outer_weights");
+}
+
+deinsum_status launch_kout_weights(const void *U1, int64_t I1, int64_t ldu, int ncols, int nt, int prec, float *W,
+                                   hipStream_t s)
+{
+    const int64_t total = (I1 + 15) / 16 * 256 * nt;
+    kout_weights_kernel<<<static_cast<unsigned>((total + 255) / 256), 256, 0, s>>>(U1, I1, ldu, ncols, nt, prec, W, total);
+    return check_launch("kout_weights");
 }
 
 deinsum_status launch_reduce_partials(const double *P, int64_t nparts, int64_t n_tiles, int tile_rows,

@@ -31,7 +31,57 @@ int ke_of(int prec, int layout)
     return (prec == P_BF16 || prec == P_BF16X3 || prec == P_FX20) ? 8 : 1;
 }
 
+// L_KOUT (order 3, free mode 0): a unit is (k-group, chunk of output rows); every
+// wave of a k-group's workgroup walks the chunk's rows, each over all mode-1 tiles.
+deinsum_status plan_geometry_kout(const MttkrpProblem &pb, const StreamKernelInfo *kernel, int split_hint,
+                                  MttkrpPlan *out)
+{
+    if (pb.N != 3 || pb.n != 0) return fail(DEINSUM_ERR_UNSUPPORTED, "the mode-1-tiled walk is for order-3 mode 0");
+    MttkrpPlan p;
+    p.prec = pb.prec;
+    p.kernel = kernel;
+    p.family = PLAN_MTTKRP_KOUT;
+    p.nt = kernel->nt;
+    p.ni = kernel->ni;
+    p.mt = 1;
+    p.col_blocks = cdiv(pb.R, 16 * p.nt);
+    p.slice = 4 * p.ni * ke_of(pb.prec, L_KCONTIG);
+    p.tile_rows = 16;
+    const int64_t I0 = pb.dims[0], I1 = pb.dims[1], I2 = pb.dims[2];
+    const int64_t nks = cdiv(I2, p.slice);
+    p.waves = kWaves;
+    p.wk = (nks % 4 == 0) ? 4 : (nks % 2 == 0 ? 2 : 1);
+    const int wo = p.waves / p.wk;
+    p.n_kgroups = cdiv(nks, p.wk);
+    p.n_tiles = cdiv(I1, 16);  // mode-1 tiles per output row
+    int64_t chunks = split_hint > 0 ? split_hint : cdiv(kTargetGroups, p.n_kgroups);
+    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, cdiv(I0, wo)));
+    p.o_per_chunk = cdiv(I0, chunks);
+    p.n_chunks = cdiv(I0, p.o_per_chunk);
+    p.groups = p.n_chunks * p.n_kgroups;
+    p.parts = p.n_kgroups * p.wk;
+    p.O = I0;
+    p.order = 0;
+    p.xcd = 0;
+    const size_t part_bytes = static_cast<size_t>(p.parts * I0) * 16 * p.nt * sizeof(double);
+    p.w_offset = (part_bytes + 255) / 256 * 256;
+    p.workspace = p.w_offset + static_cast<size_t>(p.n_tiles) * 256 * p.nt * sizeof(float);  // packed FP32 U^1
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "mttkrp_kout<p%d,nt%d,ni%d%s> wk%d", pb.prec, p.nt, p.ni, kernel->xnt ? ",nt" : "",
+                  p.wk);
+    p.name = buf;
+    *out = p;
+    return DEINSUM_OK;
+}
+
 }  // namespace
+
+bool kout_default(const MttkrpProblem &pb)
+{
+    if (pb.N != 3 || pb.n != 0 || pb.prec == P_FP64 || pb.dims[1] < 16) return false;
+    const int64_t eb = pb.prec == P_FX20 ? 2 : (pb.prec == P_BF16 ? 2 : 4);
+    return pb.dims[1] * pb.dims[2] * eb >= (int64_t(1) << 20);
+}
 
 deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *kernel, int split_hint, MttkrpPlan *out)
 {
@@ -42,6 +92,7 @@ deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *ke
     p.nt = kernel->nt;
     p.col_blocks = cdiv(pb.R, 16 * p.nt);
     const int layout = kernel->layout;
+    if (layout == L_KOUT) return plan_geometry_kout(pb, kernel, split_hint, out);
     p.family = (layout == L_KCONTIG) ? PLAN_MTTKRP_KCONTIG : PLAN_MTTKRP_MCONTIG;
     if ((layout == L_MCONTIG) != (n == N - 1))
         return fail(DEINSUM_ERR_UNSUPPORTED, "kernel layout does not match the free mode");
@@ -93,16 +144,28 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
 {
     const int N = pb.N, n = pb.n;
     const int nt = pb.R <= 16 ? 1 : (pb.R <= 32 ? 2 : 4);
-    const int family = (n == N - 1) ? PLAN_MTTKRP_MCONTIG : PLAN_MTTKRP_KCONTIG;
+    int family = (n == N - 1) ? PLAN_MTTKRP_MCONTIG : PLAN_MTTKRP_KCONTIG;
+    const bool kout_ok = N == 3 && n == 0 && pb.prec != P_FP64 && pb.dims[0] < (int64_t(1) << 31);
+    if (plan_hint == PLAN_MTTKRP_KOUT && kout_ok) family = PLAN_MTTKRP_KOUT;
     if (plan_hint != 0 && plan_hint != family)
         return fail(DEINSUM_ERR_UNSUPPORTED, "plan_hint does not match the free mode");
-    const int layout = (family == PLAN_MTTKRP_KCONTIG) ? L_KCONTIG : L_MCONTIG;
-    const int g = (layout == L_KCONTIG) ? N - 1 : N - 2;
-    const int64_t Ig = pb.dims[g];
     int count = 0;
     const StreamKernelInfo *table = stream_kernels(&count);
     TuneChoice tc;
-    if (plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc) && tc.order != kTuneViaTtmc) {
+    const bool tuned = plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc);
+    if (tuned && tc.order == kTuneKout && kout_ok) {
+        for (int i = 0; i < count; ++i) {
+            const StreamKernelInfo &k = table[i];
+            if (k.prec == pb.prec && k.layout == L_KOUT && k.nt == tc.nt && k.ni == tc.ni && k.xnt == tc.xnt)
+                return plan_geometry(pb, &k, tc.split, out);
+        }
+        // a variant that is no longer compiled: the heuristic below
+    }
+    if (plan_hint == 0 && !tuned && kout_ok && kout_default(pb)) family = PLAN_MTTKRP_KOUT;
+    const int layout = family == PLAN_MTTKRP_KOUT ? L_KOUT : (family == PLAN_MTTKRP_KCONTIG ? L_KCONTIG : L_MCONTIG);
+    const int g = (layout == L_MCONTIG) ? N - 2 : N - 1;
+    const int64_t Ig = pb.dims[g];
+    if (tuned && tc.order != kTuneViaTtmc && tc.order != kTuneKout) {
         for (int i = 0; i < count; ++i) {
             const StreamKernelInfo &k = table[i];
             if (k.prec == pb.prec && k.layout == layout && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt &&

@@ -12,7 +12,9 @@ namespace deinsum {
 enum PlanFamily {
     PLAN_MTTKRP_KCONTIG = 1,  // free mode n < N-1
     PLAN_MTTKRP_MCONTIG = 2,  // free mode n = N-1
+    PLAN_MTTKRP_KOUT = 3,     // order 3, free mode 0: mode-1 tiles walked per output row
 };
+
 
 struct MttkrpPlan {
     int family = 0;
@@ -41,6 +43,11 @@ struct MttkrpProblem {
     int64_t R = 0;
     int prec = 0;
 };
+
+// Order-3 mode 0 whose K-contiguous tiles would read rows far apart (at least 1 MiB
+// between consecutive output rows): the mode-1-tiled walk streams one X slab per
+// output row instead.  The FP64 form takes the fused TTMc pass for that (abi.cpp).
+bool kout_default(const MttkrpProblem &pb);
 
 // Launch geometry for a given kernel variant; split_hint > 0 forces the number of outer chunks.
 deinsum_status plan_geometry(const MttkrpProblem &pb, const StreamKernelInfo *kernel, int split_hint, MttkrpPlan *out);

@@ -321,15 +321,20 @@ __device__ __forceinline__ void fx20_operands_m(const uint32_t *x, int q, int mt
 }
 
 template <int L, int NT, int MT>
-constexpr int unit_lds_elems() { return ((L == L_KCONTIG) ? 16 : 16 * MT) * 16 * NT; }
+constexpr int unit_lds_elems() { return L == L_KOUT ? 1 : ((L == L_KCONTIG) ? 16 : 16 * MT) * 16 * NT; }
 
 // One workgroup unit: block index b of the launch geometry in `a` (see
 // StreamArgs).  `lds` holds unit_lds_elems() doubles.  Called by the
 // per-call kernel below and by the persistent batch kernel.  XNT: X loads
 // are non-temporal.
-template <int P, int L, int NT, int NI, int MT, int NBUF, bool XNT = false>
+template <int P, int L0, int NT, int NI, int MT, int NBUF, bool XNT = false>
 __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, double *lds)
 {
+    // L_KOUT streams tiles exactly as the K-contiguous layout does (rows of 16 along
+    // mode 1 instead of the free mode); only the unit walk and the fold differ.
+    constexpr bool KOUT = (L0 == L_KOUT);
+    constexpr int L = KOUT ? L_KCONTIG : L0;
+    static_assert(!KOUT || MT == 1, "L_KOUT tiles are K-contiguous tiles");
     using TL = Tile<P, L, NI, MT>;
     using XT = typename TL::XT;
     using DT = typename PrecTypes<P>::DT;
@@ -350,7 +355,10 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     const int kgroup = static_cast<int>(u % a.n_kgroups);
     int tile;
     int64_t chunk;
-    if (a.order == 0) {
+    if (KOUT) {
+        tile = 0;
+        chunk = u / a.n_kgroups;
+    } else if (a.order == 0) {
         tile = static_cast<int>((u / a.n_kgroups) % a.n_tiles);
         chunk = u / (static_cast<int64_t>(a.n_kgroups) * a.n_tiles);
     } else {
@@ -368,7 +376,12 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     int64_t lim;    // K-contig: run elements available; M-contig: slice rows available
     int ivalid = 0;
     bool full;
-    if constexpr (L == L_KCONTIG) {
+    if constexpr (KOUT) {
+        // row c of every mode-1 tile; per-step offsets and limits come from the walk
+        xlane = s0 + g * TL::VE;
+        lim = slice_avail - g * TL::VE;
+        full = a.vec_ok && a.od.dim[0] % 16 == 0 && slice_avail >= TL::SLICE;
+    } else if constexpr (L == L_KCONTIG) {
         const int64_t row = static_cast<int64_t>(tile) * 16 + c;
         xlane = row * a.stride_n + s0 + g * TL::VE;
         lim = (row < a.In) ? slice_avail - g * TL::VE : 0;
@@ -473,9 +486,15 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     // acc across steps, so no per-step product tile is held (it does not fit beside the
     // accumulators and the ring).
     constexpr bool WB = (P == P_FP64 && MT >= 4);
+    // L_KOUT: each column's weighted sum over the tile rows and the mode-1 tiles of
+    // the current output row (the step's weights are 4 * NT values: the lane's four
+    // tile rows of U^1 per column tile).
+    double tacc[KOUT ? NT : 1];
+#pragma unroll
+    for (int nt = 0; nt < (KOUT ? NT : 1); ++nt) tacc[nt] = 0.0;
 
     // One step: stage 1 on the matrix cores, then the Hadamard fold (stage 2).
-    auto step = [&](const XT *x, const double *wv) {
+    auto step = [&](const XT *x, const auto *wv) {  // wv: double, or float (L_KOUT)
         if constexpr (WB) {
 #pragma unroll
             for (int q = 0; q < NI; ++q)
@@ -514,13 +533,21 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
                 }
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                const double wc = wv[nt] * cs[nt];
                 const double off = 1152.0 * sh[nt];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                if constexpr (KOUT) {
+                    double sum = 0.0;
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        acc[mt][nt][v] += (256.0 * static_cast<double>(dh[mt][nt][v]) - off) * wc;
+                        sum += (256.0 * static_cast<double>(dh[0][nt][v]) - off) * static_cast<double>(wv[v * NT + nt]);
+                    tacc[nt] += sum * cs[nt];
+                } else {
+                    const double wc = wv[nt] * cs[nt];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            acc[mt][nt][v] += (256.0 * static_cast<double>(dh[mt][nt][v]) - off) * wc;
+                }
             }
         } else {
         DT d[MT][NT];
@@ -564,12 +591,20 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
                     }
                 }
             }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
+        if constexpr (KOUT) {
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[mt][nt][v] += static_cast<double>(d[mt][nt][v]) * wv[nt];
+                for (int v = 0; v < 4; ++v)
+                    tacc[nt] += static_cast<double>(d[0][nt][v]) * static_cast<double>(wv[v * NT + nt]);
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[mt][nt][v] += static_cast<double>(d[mt][nt][v]) * wv[nt];
+        }
         }
     };
 
@@ -581,6 +616,91 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     const int64_t o0 = imin64(c1, c0 + osub * per);
     const int64_t o1 = imin64(c1, o0 + per);
     const XT *__restrict__ X = static_cast<const XT *>(a.X);
+
+    if constexpr (KOUT) {
+        // Output rows [o0, o1) of this wave; per row, the n_tiles mode-1 tiles in order.
+        const int64_t I1 = a.od.dim[0], rs = a.od.xstride[0];
+        const int njt = a.n_tiles;
+        double *__restrict__ Pout = a.P + static_cast<int64_t>(ks) * a.O * a.ldw;
+        if (slice_avail <= 0) {  // a slice past mode 2: its partial rows are zero
+            if (g == 0)
+                for (int64_t i = o0; i < o1; ++i)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) Pout[i * a.ldw + nt * 16 + c] = 0.0;
+            return;
+        }
+        // Fixed-order sum over the four lane groups, then lane group 0 writes the row.
+        auto flush = [&](int64_t i) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                double v = tacc[nt];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (g == 0) Pout[i * a.ldw + nt * 16 + c] = v;
+                tacc[nt] = 0.0;
+            }
+        };
+        auto walk_kout = [&](auto full_tag) {
+            constexpr bool FULL = decltype(full_tag)::value;
+            XT xb[NBUF][TL::XW];
+            float wb[NBUF][4 * NT];
+            int64_t li = o0;  // output row and mode-1 tile of the next load
+            int ljt = 0;
+            int64_t ci = o0;  // output row and tile of the next step
+            int cjt = 0;
+            // The lane's 4 * NT weights of a tile, packed contiguously by the weight kernel.
+            const float *__restrict__ Wk = reinterpret_cast<const float *>(a.W) + static_cast<int64_t>(lane) * 4 * NT;
+            auto issue = [&](int slot) {
+                const int64_t j0 = static_cast<int64_t>(ljt) * 16;
+                load_vec<float, 4 * NT>(wb[slot], Wk + static_cast<int64_t>(ljt) * 64 * 4 * NT);
+                const int64_t row = j0 + c;
+                const int64_t off = li * a.stride_n + row * rs + xlane;
+                const int64_t lim_t = (row < I1) ? lim : 0;
+                if constexpr (P == P_FX20)
+                    load_tile_fx20<L, NI, MT, FULL, XNT>(xb[slot], off, a, lim_t, 0, g);
+                else
+                    load_tile<P, L, NI, MT, FULL, XNT>(xb[slot], X + off, a, g, lim_t, 0);
+                if (++ljt == njt) {
+                    ljt = 0;
+                    ++li;
+                }
+            };
+            auto consume = [&](int slot) {
+                step(xb[slot], wb[slot]);
+                if (++cjt == njt) {
+                    flush(ci);
+                    cjt = 0;
+                    ++ci;
+                }
+            };
+            const int64_t nsteps = (o1 - o0) * njt;
+#pragma unroll
+            for (int u = 0; u < NBUF - 1; ++u)
+                if (u < nsteps) issue(u);
+            int64_t t = 0;
+            for (; t + 2 * NBUF - 2 < nsteps; t += NBUF) {
+#pragma unroll
+                for (int u = 0; u < NBUF; ++u) {
+                    issue((u + NBUF - 1) % NBUF);
+                    consume(u);
+                }
+            }
+            for (; t < nsteps; t += NBUF) {
+#pragma unroll
+                for (int u = 0; u < NBUF; ++u) {
+                    if (t + u < nsteps) {
+                        if (t + u + NBUF - 1 < nsteps) issue((u + NBUF - 1) % NBUF);
+                        consume(u);
+                    }
+                }
+            }
+        };
+        if (o0 < o1) {
+            if (full) walk_kout(std::true_type{});
+            else walk_kout(std::false_type{});
+        }
+        return;
+    }
 
     // Walk of the outer range with an NBUF-deep register ring: the tile and the
     // Hadamard weights of step t+NBUF-1 are loaded while step t computes.

@@ -36,7 +36,7 @@ deinsum_status load_file(const char *path, bool must_exist)
         std::string key;
         TuneChoice c;
         if (!(is >> key >> c.nt >> c.ni >> c.mt >> c.xnt >> c.split >> c.order >> c.xcd >> c.us) || c.nt < 1 ||
-            c.ni < 1 || c.mt < 1 || c.xnt < 0 || c.xnt > 1 || c.split < 0 || c.order < 0 || c.order > kTuneViaTtmc || c.xcd < 0 ||
+            c.ni < 1 || c.mt < 1 || c.xnt < 0 || c.xnt > 1 || c.split < 0 || c.order < 0 || c.order > kTuneKout || c.xcd < 0 ||
             c.xcd > 1)
             return fail(DEINSUM_ERR_PARSE, std::string("tune_load: bad entry at line ") + std::to_string(lineno));
         g_cache[key] = c;

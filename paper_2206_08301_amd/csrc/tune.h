@@ -9,6 +9,7 @@ namespace deinsum {
 
 enum TunePath { TUNE_STREAM = 0, TUNE_BATCH = 1 };
 constexpr int kTuneViaTtmc = 2;
+constexpr int kTuneKout = 3;  // order field: the L_KOUT kernel (nt, ni, mt, xnt) with `split` chunks
 
 // A tuned choice: the tile shape (kernel variant) and the outer-chunk count.
 struct TuneChoice {

@@ -243,3 +243,17 @@ def test_tune_rejects_bad_input(dn, tmp_path):
     for fn in (lib.deinsum_tune_mttkrp, lib.deinsum_tune_batch_mttkrp):
         assert fn(ctypes.byref(s), d, 4, None, ptrs, None, None, 0, None, None) == -1  # reps = 0
     dn.tune_clear()
+
+
+def test_row_walk_plan_hint_host(dn):
+    """plan_hint 3 (order-3 mode 0, reduced forms) plans without a GPU; other modes, other
+    orders and the FP64 form reject it."""
+    ws = dn.workspace_size("ijk,ja,ka->ia", (40, 70, 200), [24], "fp32", plan_hint=3)
+    # FP32 slices of 128 along mode 2: 2 FP64 partials of 40 rows x 32 columns, then U^1 in FP32
+    # packed per 16-row tile (5 tiles) and lane: 5 x 64 lanes x 4 rows x 2 column tiles
+    assert ws == 2 * 40 * 32 * 8 + 5 * 64 * 4 * 2 * 4
+    for spec, dims, prec in (("ijk,ia,ka->ja", (40, 70, 200), "fp32"), ("ijk,ja,ka->ia", (40, 70, 200), "fp64"),
+                             ("ijkl,ja,ka,la->ia", (8, 9, 10, 11), "fp32")):
+        with pytest.raises(dn.DeinsumError) as e:
+            dn.workspace_size(spec, dims, [24], prec, plan_hint=3)
+        assert e.value.status == -3

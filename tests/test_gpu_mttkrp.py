@@ -401,3 +401,53 @@ def test_short_last_mode(dn, oracle_mod, prec, tol, dims):
             assert nrel(M.cpu().numpy(), ref) <= tol
         else:
             assert np.array_equal(M.cpu().numpy(), ref)
+
+
+KOUT_FORMS = [("fp32", torch.float32, torch.float32, 1e-6), ("bf16x3", torch.float32, torch.float32, 1e-5),
+              ("bf16", torch.bfloat16, torch.float32, 2e-2), ("fx20", None, torch.float32, 4e-6)]
+
+
+@pytest.mark.parametrize("form,xdt,udt,tol", KOUT_FORMS)
+@pytest.mark.parametrize("dims,R", [((40, 70, 200), 24), ((33, 45, 256), 20), ((20, 64, 130), 8), ((17, 48, 96), 40)])
+def test_mode0_row_walk_every_form(dn, oracle_mod, form, xdt, udt, tol, dims, R):
+    """Order-3 mode 0 through the mode-1-tiled walk (plan_hint 3): ragged mode-1 tiles,
+    slices past mode 2, one to four column blocks; uniform inputs within each form's
+    bound of the oracle, integer inputs exact."""
+    rng = np.random.default_rng(sum(dims) + R)
+    for dist in ("uniform", "int"):
+        if dist == "uniform":
+            X = rng.uniform(-1, 1, dims)
+            U = [rng.standard_normal((d, R)) for d in dims]
+        else:
+            X = rng.integers(-3, 4, dims).astype(np.float64)
+            U = [rng.integers(-2, 3, (d, R)).astype(np.float64) for d in dims]
+        Xd = dn.to_fx20(to_dev(X)) if form == "fx20" else to_dev(X, xdt)
+        rep = dn.Report()
+        M = dn.mttkrp(mttkrp_spec(3, 0), Xd, [to_dev(U[1], udt), to_dev(U[2], udt)], precision=form,
+                      out_dtype=torch.float64, plan_hint=3, report=rep)
+        torch.cuda.synchronize()
+        name = rep.plan_name.decode()
+        assert name.startswith("mttkrp_kout"), name
+        ref = oracle_mod.mttkrp(X, [None, U[1], U[2]], 0)
+        got = M.cpu().numpy()
+        flush(f"row walk {form} {dims} R={R} {dist}: {name}, err {nrel(got, ref):.2e}")
+        if dist == "int":
+            assert np.array_equal(got, ref)
+        else:
+            assert nrel(got, ref) <= tol
+
+
+def test_mode0_row_walk_is_default_for_far_rows(dn, synth):
+    """1 MiB or more between consecutive mode-0 rows: the reduced forms take the walk by
+    default (FP64 keeps the fused TTMc pass); a short tensor keeps the K-contiguous kernel."""
+    big, small = (128, 1024, 1024), (64, 48, 64)
+    assert dn.workspace_size(mttkrp_spec(3, 0), big, [24], "fp32") > 0
+    for prec, dt in (("fp32", torch.float32), ("bf16x3", torch.float32), ("bf16", torch.bfloat16)):
+        for dims, want in ((big, "mttkrp_kout"), (small, "mttkrp_kcontig")):
+            X = torch.empty(dims, dtype=dt, device="cuda")
+            X.zero_()
+            U = [torch.zeros((d, 24), dtype=torch.float32, device="cuda") for d in dims[1:]]
+            rep = dn.Report()
+            dn.mttkrp(mttkrp_spec(3, 0), X, U, precision=prec, out_dtype=torch.float64, report=rep)
+            torch.cuda.synchronize()
+            assert rep.plan_name.decode().startswith(want), (prec, dims, rep.plan_name)
