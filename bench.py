@@ -589,12 +589,19 @@ def main():
             k0 = med[0]
             how = "median call duration (HIP events around the whole call)"
         dom_gbs = bytes_mode[0] / (k0 / 1e3) / 1e9
+        # Streaming peak of this machine: a plain full read of the same 8 GiB X (torch's sum,
+        # the runtime's own reduction), median of 10, against which the fraction is also given.
+        probe_ms = event_samples(torch, stream, lambda: X.sum(), 10)
+        probe_gbs = X.numel() * 8 / (statistics.median(probe_ms) / 1e3) / 1e9
         result["roofline"] = {"bound": "hbm", "achieved": round(dom_gbs, 1), "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                               "traffic": measured_traffic(plan0),
                               "kernel": kname, "kernel_ms": round(k0, 4),
                               "kernel_ms_ci95": boot_ci(kernel_ms[0]) if kernel_ms[0] else None,
-                              "alg_bytes_per_launch": bytes_mode[0], "duration": how}
+                              "alg_bytes_per_launch": bytes_mode[0], "duration": how,
+                              "measured_stream_GBps": round(probe_gbs, 1),
+                              "frac_of_measured_stream": round(dom_gbs / probe_gbs, 4),
+                              "stream_probe": "full read of the 8 GiB FP64 X by torch.sum, median of 10 event-timed runs"}
         result["modes"] = {}
         for n in range(3):
             e = {"ms": round(med[n], 4), "ci95_ms": boot_ci(per_mode_ms[n]), "GB/s": round(gbs[n], 1),

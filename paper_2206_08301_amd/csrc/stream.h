@@ -335,6 +335,7 @@ __device__ __forceinline__ void stream_unit(const StreamArgs &a, int64_t b, doub
     constexpr bool KOUT = (L0 == L_KOUT);
     constexpr int L = KOUT ? L_KCONTIG : L0;
     static_assert(!KOUT || MT == 1, "L_KOUT tiles are K-contiguous tiles");
+    static_assert(!KOUT || P != P_FP64, "L_KOUT weights are packed for the FP32 accumulator layout (row 4g + v)");
     using TL = Tile<P, L, NI, MT>;
     using XT = typename TL::XT;
     using DT = typename PrecTypes<P>::DT;
