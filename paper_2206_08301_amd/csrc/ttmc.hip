@@ -495,16 +495,16 @@ __global__ void __launch_bounds__(256) pad_factor_kernel(const T *src, int64_t r
     dst[e] = (j < r) ? src[i * r + j] : T{};
 }
 
-// BF16 stage-1 factor: for K step kb (rows 32 kb ..), column tile nt and lane
-// (g, c), the eight BF16 values of rows 32 kb + 8 g .. + 7 in column 16 nt + c,
-// contiguous (one 16-byte load per lane); zero past the factor's rows and columns.
-// FX20 stage-1 factor, one workgroup per column: k with max |u| < 2^k, scale = 2^k,
-// and off = 1152 * the sum of the FP16 hi parts of the column scaled by 2^-k (removes
-// the int8 operand's offset).  Rows are strided over the threads and both results are
-// combined by a fixed-order tree, so they do not depend on timing.  Columns past r are
-// zero (k = 0).
-__global__ void __launch_bounds__(256) fx20_factor_cols_kernel(const float *src, int64_t rows, int r, int *kexp,
-                                                               double *scale, double *off)
+// Stage-1 factor of the FX20 form, one workgroup per (padded) column: the column's
+// power-of-two scale 2^-k with |u| 2^-k < 1 (tree maximum; scale = 2^k, zero columns
+// past r take k = 0), then its values scaled, split into FP16 hi + lo and written
+// into the per-K-step, per-lane packing of the BF16 form (eight rows of one column
+// per lane; zero past the rows), and off = 1152 * the sum of the hi parts (removes the
+// int8 operand's offset).  Rows are strided over the threads and both reductions are
+// fixed-order trees, so the results do not depend on timing.
+__global__ void __launch_bounds__(256) fx20_factor_cols_kernel(const float *src, int64_t rows, int r, int nta,
+                                                               int64_t nkb, int *kexp, double *scale, double *off,
+                                                               uint16_t *hi, uint16_t *lo)
 {
     __shared__ float smx[256];
     __shared__ double ssum[256];
@@ -521,10 +521,19 @@ __global__ void __launch_bounds__(256) fx20_factor_cols_kernel(const float *src,
     }
     int k = 0;
     if (smx[0] > 0.0f) (void)frexpf(smx[0], &k);
+    const int nt = col / 16, c = col % 16;
     double sh = 0.0;
-    if (col < r)
-        for (int64_t i = t; i < rows; i += 256)
-            sh += static_cast<double>(static_cast<float>(static_cast<_Float16>(ldexpf(src[i * r + col], -k))));
+    for (int64_t i = t; i < nkb * 32; i += 256) {
+        const float v = (col < r && i < rows) ? ldexpf(src[i * r + col], -k) : 0.0f;
+        const _Float16 h = static_cast<_Float16>(v);
+        const _Float16 l = static_cast<_Float16>(v - static_cast<float>(h));
+        sh += static_cast<double>(static_cast<float>(h));
+        const int64_t kb = i / 32;
+        const int w = static_cast<int>(i % 32);
+        const int64_t e = ((kb * nta + nt) * 64 + 16 * (w / 8) + c) * 8 + w % 8;
+        hi[e] = __builtin_bit_cast(uint16_t, h);
+        lo[e] = __builtin_bit_cast(uint16_t, l);
+    }
     ssum[t] = sh;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -538,27 +547,9 @@ __global__ void __launch_bounds__(256) fx20_factor_cols_kernel(const float *src,
     }
 }
 
-// FP16 hi and lo parts of U^a scaled per column by 2^-k, packed per K step and lane
-// as the BF16 form packs its factor (eight rows of one column per lane).
-__global__ void __launch_bounds__(256) pack_factor_fx20_kernel(const float *src, int64_t rows, int r, int nta,
-                                                               int64_t nkb, const int *kexp, uint16_t *hi,
-                                                               uint16_t *lo)
-{
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= nkb * nta * 512) return;
-    const int q = static_cast<int>(e % 8);
-    const int lane = static_cast<int>((e / 8) % 64);
-    const int nt = static_cast<int>((e / 512) % nta);
-    const int64_t kb = e / (512 * static_cast<int64_t>(nta));
-    const int64_t row = kb * 32 + 8 * (lane >> 4) + q;
-    const int col = nt * 16 + (lane & 15);
-    const float v = (row < rows && col < r) ? ldexpf(src[row * r + col], -kexp[col]) : 0.0f;
-    const _Float16 h = static_cast<_Float16>(v);
-    const _Float16 l = static_cast<_Float16>(v - static_cast<float>(h));
-    hi[e] = __builtin_bit_cast(uint16_t, h);
-    lo[e] = __builtin_bit_cast(uint16_t, l);
-}
-
+// BF16 stage-1 factor: for K step kb (rows 32 kb ..), column tile nt and lane
+// (g, c), the eight BF16 values of rows 32 kb + 8 g .. + 7 in column 16 nt + c,
+// contiguous (one 16-byte load per lane); zero past the factor's rows and columns.
 __global__ void __launch_bounds__(256) pack_factor_bf16_kernel(const float *src, int64_t rows, int r, int nta,
                                                               int64_t nkb, uint16_t *dst)
 {
@@ -1053,10 +1044,8 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
             double *off = reinterpret_cast<double *>(lo + pk + align256(ta * 8));
             int *kexp = reinterpret_cast<int *>(lo + pk + 2 * align256(ta * 8));
             fx20_factor_cols_kernel<<<static_cast<unsigned>(ta), 256, 0, s>>>(
-                static_cast<const float *>(Um[p.a]), p.I[p.a], static_cast<int>(p.Rm[p.a]), kexp, scale, off);
-            pack_factor_fx20_kernel<<<static_cast<unsigned>(cdivl(n, 256)), 256, 0, s>>>(
-                static_cast<const float *>(Um[p.a]), p.I[p.a], static_cast<int>(p.Rm[p.a]), p.nta, nkb, kexp,
-                reinterpret_cast<uint16_t *>(Ua_pad), reinterpret_cast<uint16_t *>(lo));
+                static_cast<const float *>(Um[p.a]), p.I[p.a], static_cast<int>(p.Rm[p.a]), p.nta, nkb, kexp, scale,
+                off, reinterpret_cast<uint16_t *>(Ua_pad), reinterpret_cast<uint16_t *>(lo));
         } else {
             pad(p.a, 16 * p.nta, Ua_pad);
         }
