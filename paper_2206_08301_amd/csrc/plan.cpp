@@ -152,14 +152,23 @@ deinsum_status plan_mttkrp(const MttkrpProblem &pb, int plan_hint, int split_hin
     int count = 0;
     const StreamKernelInfo *table = stream_kernels(&count);
     TuneChoice tc;
-    const bool tuned = plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc);
-    if (tuned && tc.order == kTuneKout && kout_ok) {
-        for (int i = 0; i < count; ++i) {
+    bool tuned = plan_hint == 0 && split_hint == 0 && tune_lookup(tune_key(TUNE_STREAM, pb), &tc);
+    if (tuned && tc.order == kTuneKout) {
+        for (int i = 0; i < count && kout_ok; ++i) {
             const StreamKernelInfo &k = table[i];
             if (k.prec == pb.prec && k.layout == L_KOUT && k.nt == tc.nt && k.ni == tc.ni && k.xnt == tc.xnt)
                 return plan_geometry(pb, &k, tc.split, out);
         }
-        // a variant that is no longer compiled: the heuristic below
+        tuned = false;  // a variant that is no longer compiled: the untuned choice below
+    } else if (tuned && tc.order != kTuneViaTtmc) {
+        const int base = (n == N - 1) ? L_MCONTIG : L_KCONTIG;
+        bool found = false;
+        for (int i = 0; i < count; ++i) {
+            const StreamKernelInfo &k = table[i];
+            found |= k.prec == pb.prec && k.layout == base && k.nt == tc.nt && k.ni == tc.ni && k.mt == tc.mt &&
+                     k.xnt == tc.xnt;
+        }
+        tuned = found;
     }
     if (plan_hint == 0 && !tuned && kout_ok && kout_default(pb)) family = PLAN_MTTKRP_KOUT;
     const int layout = family == PLAN_MTTKRP_KOUT ? L_KOUT : (family == PLAN_MTTKRP_KCONTIG ? L_KCONTIG : L_MCONTIG);

@@ -257,3 +257,32 @@ def test_row_walk_plan_hint_host(dn):
         with pytest.raises(dn.DeinsumError) as e:
             dn.workspace_size(spec, dims, [24], prec, plan_hint=3)
         assert e.value.status == -3
+
+
+def test_tune_cache_row_walk_entry(dn, tmp_path):
+    """Order-3 mode 0 in a reduced form: the default for far-apart rows is the row walk;
+    a cache entry with order 3 names a row-walk kernel and its chunk count, one with a
+    stream-kernel order keeps the K-contiguous kernel, and an entry for a row-walk
+    variant that is not compiled falls back to the heuristic."""
+    spec, dims = "ijk,ja,ka->ia", [1024, 1024, 1024]
+    key = "s:N3:n0:p1:R24:1024x1024x1024"  # FP32
+    dn.tune_clear()
+    default = dn.workspace_size(spec, dims, [24], "fp32")
+    walk = dn.workspace_size(spec, dims, [24], "fp32", plan_hint=3)
+    assert default == walk  # 1024^3 FP32: rows 4 MiB apart, the walk by default
+    # row walk with 8 chunks: FP32 slices of 128 -> 8 slices of 1024 rows x 32 columns
+    # in FP64, then U^1 packed in FP32 (64 tiles x 64 lanes x 4 rows x 2 column tiles)
+    f = tmp_path / "walk.txt"
+    f.write_text(f"{key} 2 32 1 0 8 3 0 1.0\n")
+    dn.tune_load(f)
+    assert dn.workspace_size(spec, dims, [24], "fp32") == 8 * 1024 * 32 * 8 + 64 * 64 * 4 * 2 * 4
+    f.write_text(f"{key} 2 32 1 0 4 0 0 1.0\n")  # the K-contiguous kernel, 4 chunks
+    dn.tune_clear()
+    dn.tune_load(f)
+    kc = dn.workspace_size(spec, dims, [24], "fp32")
+    assert kc == dn.workspace_size(spec, dims, [24], "fp32", plan_hint=1, split_hint=4)
+    f.write_text(f"{key} 2 99 1 0 8 3 0 1.0\n")  # no such row-walk variant
+    dn.tune_clear()
+    dn.tune_load(f)
+    assert dn.workspace_size(spec, dims, [24], "fp32") == default
+    dn.tune_clear()
