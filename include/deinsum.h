@@ -444,7 +444,7 @@ deinsum_status deinsum_batch_destroy(deinsum_batch *b);
  * epoch has slots and the sum of the admitted requests' MTTKRP workspaces stays
  * within hbm_budget_bytes, and runs the epoch as one batch launch
  * (deinsum_batch_*) plus one batched update kernel on the slot's stream (an
- * epoch of one request: see single_direct).  With
+ * small epoch: see direct_max_jobs).  With
  * batched=0 every request is launched on arrival (deinsum_mttkrp + one update
  * kernel) on a single stream: the per-request baseline.
  *
@@ -466,16 +466,18 @@ typedef struct deinsum_server_config {
     int32_t als_update;         /* 1: run the factor update after each MTTKRP         */
     int64_t max_requests;       /* capacity of the request table                     */
     size_t hbm_budget_bytes;    /* admission limit on summed MTTKRP workspace         */
-    int32_t single_direct;      /* batched: 1 = an epoch of one request runs it with
-                                   the per-request launches (no descriptor upload or
-                                   batch graph); its result then matches the batched
-                                   one within the form's tolerance, not bitwise.
-                                   0 = every epoch is a batch launch: each result is
-                                   bitwise the same alone and in any mix            */
+    int32_t direct_max_jobs;    /* batched: an epoch of at most this many requests
+                                   runs them with the per-request launches, one after
+                                   the other on the slot's stream (no descriptor
+                                   upload or batch graph); their results then match
+                                   the batched ones within the form's tolerance, not
+                                   bitwise.  0 = every epoch is a batch launch: each
+                                   result is bitwise the same alone and in any mix.
+                                   0..max_jobs_per_epoch                            */
 } deinsum_server_config;
 
 /* Defaults: batched, 256 jobs per epoch, 2 in flight, update on, 1<<20 requests, 4 GiB,
- * single_direct 1. */
+ * direct_max_jobs 4. */
 void deinsum_server_config_init(deinsum_server_config *cfg);
 
 deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_server **out);

@@ -638,14 +638,13 @@ class Server:
     Each request (tensor, mode) runs the mode's MTTKRP and the factor update
     in the library; the factors registered with ``add_tensor`` are updated in
     place.  ``batched=True`` runs continuous batching, ``False`` one launch
-    per request.  ``single_direct=True`` runs an epoch of one request with the
-    per-request launches (lower latency; its result matches the batched one within
-    the form's tolerance); ``False`` keeps every result bitwise the same alone and
-    in any mix.
+    per request.  ``direct_max_jobs=k`` runs an epoch of at most k requests with the
+    per-request launches (lower latency; results match the batched ones within the
+    form's tolerance); ``0`` keeps every result bitwise the same alone and in any mix.
     """
 
     def __init__(self, batched=True, max_jobs_per_epoch=256, epochs_in_flight=2, als_update=True,
-                 max_requests=1 << 20, hbm_budget_bytes=4 << 30, single_direct=True):
+                 max_requests=1 << 20, hbm_budget_bytes=4 << 30, direct_max_jobs=4):
         cfg = _lib.ServerConfig()
         _lib.load().deinsum_server_config_init(ctypes.byref(cfg))
         cfg.batched = int(bool(batched))
@@ -654,7 +653,7 @@ class Server:
         cfg.als_update = int(bool(als_update))
         cfg.max_requests = int(max_requests)
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
-        cfg.single_direct = int(bool(single_direct))
+        cfg.direct_max_jobs = int(direct_max_jobs)
         self._h = ctypes.c_void_p()
         _lib.check(_lib.load().deinsum_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._keep = []

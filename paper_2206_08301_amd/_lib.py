@@ -87,7 +87,7 @@ class ServerConfig(ctypes.Structure):
         ("als_update", ctypes.c_int32),
         ("max_requests", ctypes.c_int64),
         ("hbm_budget_bytes", ctypes.c_size_t),
-        ("single_direct", ctypes.c_int32),
+        ("direct_max_jobs", ctypes.c_int32),
     ]
 
 

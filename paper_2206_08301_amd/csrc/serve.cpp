@@ -8,8 +8,8 @@
 //     is admitted, in arrival order, while its workspace fits the HBM budget
 //     and the epoch has slots; the epoch runs as one persistent batch launch
 //     (deinsum_batch_*) followed by one batched CP-ALS update kernel (an
-//     epoch of one request takes the per-request launches instead, unless
-//     single_direct is 0).  Up to
+//     epoch of at most direct_max_jobs requests takes the per-request launches
+//     instead).  Up to
 //     two epochs are in flight on two streams, so requests that arrive while
 //     one epoch runs start on the device before it finishes.
 //   * per request: each request is launched on arrival (MTTKRP, then the
@@ -209,20 +209,26 @@ bool launch_epoch(deinsum_server *s, int e, std::deque<int64_t> &pending)
         ep.reqs.clear();
         return false;
     };
-    if (ep.reqs.size() == 1 && s->cfg.single_direct) {
-        // One request: the direct launches of the per-request path on this slot's stream
-        // (no descriptor upload, no persistent batch kernel).
-        const int64_t r = ep.reqs[0];
-        if (!enqueue_request(s, r, s->stream[e], s->ws[e])) {
-            ep.reqs.clear();
-            return false;
+    if (static_cast<int64_t>(ep.reqs.size()) <= s->cfg.direct_max_jobs) {
+        // A small epoch: the direct launches of the per-request path, one request after
+        // the other on this slot's stream with its workspace (no descriptor upload, no
+        // persistent batch kernel).  A request that cannot be enqueued ends alone.
+        std::vector<int64_t> added;
+        size_t footprint = 0;
+        for (int64_t r : ep.reqs) {
+            if (!enqueue_request(s, r, s->stream[e], s->ws[e])) continue;
+            s->reqs[r].epoch = s->epochs;
+            footprint += s->tensors[s->reqs[r].tensor].ws[s->reqs[r].mode];
+            added.push_back(r);
         }
-        s->reqs[r].epoch = s->epochs;
+        ep.reqs.swap(added);
+        ep.footprint = footprint;
+        if (ep.reqs.empty()) return false;
         if (hipEventRecord(s->ev[e], s->stream[e]) != hipSuccess) return fail_epoch("event record failed");
         ep.active = true;
         s->footprint_used += ep.footprint;
         ++s->epochs;
-        s->max_batch = std::max<int64_t>(s->max_batch, 1);
+        s->max_batch = std::max<int64_t>(s->max_batch, static_cast<int64_t>(ep.reqs.size()));
         return true;
     }
     deinsum_batch_reset(s->batch[e]);
@@ -448,7 +454,7 @@ void deinsum_server_config_init(deinsum_server_config *cfg)
     cfg->als_update = 1;
     cfg->max_requests = int64_t(1) << 20;
     cfg->hbm_budget_bytes = size_t(4) << 30;
-    cfg->single_direct = 1;
+    cfg->direct_max_jobs = 4;
 }
 
 deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_server **out)
@@ -462,9 +468,9 @@ deinsum_status deinsum_server_create(const deinsum_server_config *cfg, deinsum_s
         delete s;
         return fail(DEINSUM_ERR_INVALID_ARG, "server_create: max_jobs_per_epoch must be 1..65536");
     }
-    if (s->cfg.single_direct != 0 && s->cfg.single_direct != 1) {
+    if (s->cfg.direct_max_jobs < 0 || s->cfg.direct_max_jobs > s->cfg.max_jobs_per_epoch) {
         delete s;
-        return fail(DEINSUM_ERR_INVALID_ARG, "server_create: single_direct must be 0 or 1");
+        return fail(DEINSUM_ERR_INVALID_ARG, "server_create: direct_max_jobs must be 0..max_jobs_per_epoch");
     }
     if (s->cfg.max_requests < 1 || s->cfg.max_requests > (int64_t(1) << 28)) {
         delete s;

@@ -10,7 +10,8 @@ modes.  Arrivals are a Poisson process of rate ``rate`` per second.
 
 Latency = host-observed completion - scheduled arrival.  Two kinds of run per
 server mode: open loop at the Poisson arrivals (``repeats`` runs, the two modes
-alternating; p50/p99 of the pooled latencies with a 95 % bootstrap interval), and
+alternating, after an untimed warm-up of both on the first 512 requests; p50/p99
+of the pooled latencies with a 95 % bootstrap interval), and
 saturation with every request released at t = 0 (throughput in requests/s and
 algorithmic GB/s).
 """
@@ -72,14 +73,14 @@ def request_bytes(wl):
     return out
 
 
-def serve_once(dn, wl, state, batched, open_loop, max_jobs=256, epochs_in_flight=2):
+def serve_once(dn, wl, state, batched, open_loop, max_jobs=256, epochs_in_flight=2, **server_kw):
     for s in state:
         for u, u0 in zip(s["U"], s["U0"]):
             u.copy_(u0)
     torch.cuda.synchronize()
     n = len(wl["tensor_of"])
     srv = dn.Server(batched=batched, max_jobs_per_epoch=max_jobs, epochs_in_flight=epochs_in_flight,
-                    max_requests=n + 16)
+                    max_requests=n + 16, **server_kw)
     for s in state:
         srv.add_tensor(s["X"], s["U"], precision=s["prec"])
     srv.start()
@@ -121,6 +122,11 @@ def measure(dn, n_requests=4096, rate=2000.0, sweeps=10, repeats=3, log=None):
            "statistic": f"p50 / p99 of the latencies pooled over {repeats} open-loop runs per server mode "
                         "(the two modes alternate run by run), 95 % bootstrap interval over the pooled runs"}
     modes = (("batched", True), ("per_request", False))
+    # Untimed warm-up of both servers on the first 512 requests: the first launches of the
+    # batch graph, the update kernels and every plan in the process load their code.
+    warm = dict(wl, tensor_of=wl["tensor_of"][:512], mode_of=wl["mode_of"][:512], arrivals=wl["arrivals"][:512])
+    for _, batched in modes:
+        serve_once(dn, warm, state, batched, open_loop=True)
     runs = {name: [] for name, _ in modes}
     for r in range(repeats):
         for name, batched in (modes if r % 2 == 0 else modes[::-1]):

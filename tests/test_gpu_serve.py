@@ -42,11 +42,11 @@ def oracle_sweeps(oracle_mod, X, U, modes):
     return U
 
 
-def run_server(dn, tensors, requests, batched=True, arrivals=None, max_jobs=64, single_direct=True):
+def run_server(dn, tensors, requests, batched=True, arrivals=None, max_jobs=64, direct_max_jobs=4):
     """tensors: list of (X, U, prec) host arrays; requests: list of (tensor, mode).
     Returns the device factors after serving, the server's results and stats."""
     srv = dn.Server(batched=batched, max_jobs_per_epoch=max_jobs, max_requests=len(requests) + 8,
-                    single_direct=single_direct)
+                    direct_max_jobs=direct_max_jobs)
     dev = []
     for X, U, prec in tensors:
         Xd, Ud = device_copy(X, U, prec)
@@ -128,19 +128,19 @@ def c5_like(seed, count):
 
 
 def test_server_alone_vs_mix_bitwise(dn):
-    """With single_direct off, each tensor's factors after its requests are bitwise the
+    """With direct launches off (direct_max_jobs 0), each tensor's factors after its requests are bitwise the
     same served alone, in the full mix submitted at once, and in the mix arriving over
     time (different epochs)."""
     tensors = c5_like(7, 10)
     reqs = round_robin([3] * len(tensors), 2)
-    mix, (_, _, ep_mix), st_mix = run_server(dn, tensors, reqs, single_direct=False)
+    mix, (_, _, ep_mix), st_mix = run_server(dn, tensors, reqs, direct_max_jobs=0)
     arrivals = np.arange(len(reqs)) * 2e-4
-    spread, (_, _, ep_sp), st_sp = run_server(dn, tensors, reqs, arrivals=arrivals, single_direct=False)
+    spread, (_, _, ep_sp), st_sp = run_server(dn, tensors, reqs, arrivals=arrivals, direct_max_jobs=0)
     flush(f"mix epochs={st_mix['epochs']} max_batch={st_mix['max_batch']}; "
           f"spread epochs={st_sp['epochs']} max_batch={st_sp['max_batch']}")
     assert st_mix["max_batch"] > 1
     for k in (0, 3, 9):
-        alone, _, _ = run_server(dn, [tensors[k]], [(0, n) for t, n in reqs if t == k], single_direct=False)
+        alone, _, _ = run_server(dn, [tensors[k]], [(0, n) for t, n in reqs if t == k], direct_max_jobs=0)
         for m in range(3):
             assert np.array_equal(alone[0][m], mix[k][m]), (k, m)
     for k in range(len(tensors)):
@@ -148,8 +148,8 @@ def test_server_alone_vs_mix_bitwise(dn):
             assert np.array_equal(spread[k][m], mix[k][m]), (k, m)
 
 
-def test_server_alone_vs_mix_single_direct(dn, oracle_mod):
-    """With single_direct on (the default), a tensor served alone runs every request with
+def test_server_alone_vs_mix_direct(dn, oracle_mod):
+    """With direct launches for small epochs (the default), a tensor served alone runs every request with
     the per-request launches; its factors match the mix (batched epochs) within the
     form's tolerance, and both match the oracle's sweeps."""
     tensors = c5_like(7, 10)
@@ -287,3 +287,25 @@ def test_poll_states_and_errors(dn):
     with pytest.raises(dn.DeinsumError):
         srv.poll(rid + 100)
     srv.close()
+
+
+def test_server_small_epochs_direct(dn, oracle_mod):
+    """direct_max_jobs = 4: epochs of up to four requests run the per-request launches
+    one after the other; the factors match the all-batched server within the form's
+    tolerance and, for FP64 tensors, the oracle.  Out-of-range values are rejected."""
+    tensors = c5_like(7, 10)
+    reqs = round_robin([3] * len(tensors), 2)
+    arrivals = np.arange(len(reqs)) * 5e-5  # small epochs
+    batched, _, _ = run_server(dn, tensors, reqs, arrivals=arrivals, direct_max_jobs=0)
+    direct, _, st = run_server(dn, tensors, reqs, arrivals=arrivals, direct_max_jobs=4)
+    assert st["completed"] == len(reqs)
+    for k, (X, U, prec) in enumerate(tensors):
+        tol = 1e-10 if prec == "fp64" else 5e-4
+        ref = oracle_sweeps(oracle_mod, X, U, [n for t, n in reqs if t == k]) if prec == "fp64" else None
+        for m in range(3):
+            assert nrel(direct[k][m], batched[k][m]) <= tol, (k, m)
+            if ref is not None:
+                assert nrel(direct[k][m], ref[m]) <= tol, (k, m)
+    for bad in (-1, 65):
+        with pytest.raises(dn.DeinsumError):
+            dn.Server(max_jobs_per_epoch=64, direct_max_jobs=bad)
