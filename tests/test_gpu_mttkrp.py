@@ -408,7 +408,8 @@ KOUT_FORMS = [("fp32", torch.float32, torch.float32, 1e-6), ("bf16x3", torch.flo
 
 
 @pytest.mark.parametrize("form,xdt,udt,tol", KOUT_FORMS)
-@pytest.mark.parametrize("dims,R", [((40, 70, 200), 24), ((33, 45, 256), 20), ((20, 64, 130), 8), ((17, 48, 96), 40)])
+@pytest.mark.parametrize("dims,R", [((40, 70, 200), 24), ((33, 45, 256), 20), ((20, 64, 130), 8), ((17, 48, 96), 40),
+                                    ((9, 5, 40), 3)])
 def test_mode0_row_walk_every_form(dn, oracle_mod, form, xdt, udt, tol, dims, R):
     """Order-3 mode 0 through the mode-1-tiled walk (plan_hint 3): ragged mode-1 tiles,
     slices past mode 2, one to four column blocks; uniform inputs within each form's
