@@ -637,10 +637,23 @@ struct SmallTtmArgs {
 
 // Largest factor (rows x ranks rounded up to RB, FP64) staged in LDS per workgroup.
 constexpr size_t kTtmLdsBytes = 48 * 1024;
+// Below this many threads (four waves on each of the 1024 SIMDs) a small TTM takes
+// the pipelined row walk.
+constexpr int64_t kTtmPipeThreads = int64_t{1024} * 4 * 64;
 
-template <int RB, bool LDS>
+// Where a thread's factor weights come from: global memory per lane (ranks in
+// blocks of RB), LDS (the factor staged per workgroup), or, when one block holds
+// every rank, global memory at wave-uniform addresses (scalar loads into SGPRs, the
+// products' scalar operand; no LDS traffic, which bounds the LDS form: every row
+// returns RB broadcast weights to all 64 lanes for RB products per lane).
+enum { kTtmWGlobal = 0, kTtmWLds = 1, kTtmWUniform = 2 };
+using const_f64_k = const __attribute__((address_space(4))) double;
+using const_f32_k = const __attribute__((address_space(4))) float;
+
+template <int RB, int WM, bool PIPE>
 __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
 {
+    constexpr bool LDS = (WM == kTtmWLds);
     extern __shared__ double su[];  // LDS: U as FP64, row stride ldl = ranks rounded up to RB
     const int64_t ldl = (a.odim[a.m] + RB - 1) / RB * RB;
     if constexpr (LDS) {
@@ -669,53 +682,100 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
 #pragma unroll
     for (int q = 0; q < RB; ++q) acc[q] = 0.0;
     const int64_t sm = a.tstr[a.m];
-    if constexpr (LDS) {
-        // every rank of the block is staged (zero past the last): no clamping needed
-        int64_t i = 0;
-        for (; i + 8 <= a.Im; i += 8) {
-            double t[8];  // eight loads in flight per thread
-#pragma unroll
-            for (int k = 0; k < 8; ++k) t[k] = a.T[ioff + (i + k) * sm];
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-#pragma unroll
-                for (int q = 0; q < RB; ++q) acc[q] += t[k] * su[(i + k) * ldl + r0 + q];
-        }
-        for (; i < a.Im; ++i) {
-            const double t = a.T[ioff + i * sm];
-#pragma unroll
-            for (int q = 0; q < RB; ++q) acc[q] += t * su[i * ldl + r0 + q];
-        }
-    } else {
-        // Factor read from global memory; ranks past the last are clamped (their sums dropped),
-        // so the loads of an unrolled step are unconditional.
-        auto body = [&](const auto *U) {
+    // Rows of the input fibre summed in ascending order, in batches of eight loads.
+    // PIPE (launches with few fibres, e.g. 192^4 R=16: 768 waves) takes batches of
+    // sixteen, issues the next batch's loads before the current batch's products and
+    // reads each row's weights together, so that up to 32 loads per thread are in
+    // flight: such a launch is otherwise bound by one memory latency per batch.  Without PIPE the kernel
+    // keeps its lower register count, and the occupancy that hides latency in
+    // launches with many fibres.
+    auto walk = [&](auto wt) {  // wt(i, q): factor entry of row i, rank r0 + q
+        if constexpr (!PIPE) {
             int64_t i = 0;
             for (; i + 8 <= a.Im; i += 8) {
-                double t[8];
+                double t[8];  // eight loads in flight per thread
 #pragma unroll
                 for (int k = 0; k < 8; ++k) t[k] = a.T[ioff + (i + k) * sm];
 #pragma unroll
                 for (int k = 0; k < 8; ++k)
 #pragma unroll
-                    for (int q = 0; q < RB; ++q)
-                        acc[q] += t[k] * static_cast<double>(U[(i + k) * a.ldu + r0 + (q < nr ? q : 0)]);
+                    for (int q = 0; q < RB; ++q) acc[q] += t[k] * wt(i + k, q);
             }
             for (; i < a.Im; ++i) {
                 const double t = a.T[ioff + i * sm];
 #pragma unroll
-                for (int q = 0; q < RB; ++q) acc[q] += t * static_cast<double>(U[i * a.ldu + r0 + (q < nr ? q : 0)]);
+                for (int q = 0; q < RB; ++q) acc[q] += t * wt(i, q);
+            }
+            return;
+        }
+        constexpr int KB = 16;  // rows per batch
+        const int64_t nb = a.Im / KB * KB;
+        double ta[KB], tb[KB];
+        auto load = [&](double(&t)[KB], int64_t i) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) t[k] = a.T[ioff + (i + k) * sm];
+        };
+        auto use = [&](const double(&t)[KB], int64_t i) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                double w[RB];
+#pragma unroll
+                for (int q = 0; q < RB; ++q) w[q] = wt(i + k, q);
+#pragma unroll
+                for (int q = 0; q < RB; ++q) acc[q] += t[k] * w[q];
             }
         };
-        if (a.uprec == P_FP64) body(static_cast<const double *>(a.U));
-        else body(static_cast<const float *>(a.U));
+        int64_t i = 0;
+        if (nb > 0) load(ta, 0);
+        for (; i < nb; i += 2 * KB) {
+            const bool more = i + KB < nb;
+            if (more) load(tb, i + KB);
+            use(ta, i);
+            if (!more) {
+                i += KB;
+                break;
+            }
+            if (i + 2 * KB < nb) load(ta, i + 2 * KB);
+            use(tb, i + KB);
+        }
+        for (; i < a.Im; ++i) {
+            const double t = a.T[ioff + i * sm];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) acc[q] += t * wt(i, q);
+        }
+    };
+    if constexpr (WM == kTtmWUniform) {
+        // launched only when the factor has exactly RB columns: r0 = 0 in every thread
+        if (a.uprec == P_FP64) {
+            const_f64_k *U = (const_f64_k *)(a.U);
+            walk([&](int64_t i, int q) { return U[i * a.ldu + q]; });
+        } else {
+            const_f32_k *U = (const_f32_k *)(a.U);
+            walk([&](int64_t i, int q) { return static_cast<double>(U[i * a.ldu + q]); });
+        }
+    } else if constexpr (LDS) {
+        // every rank of the block is staged (zero past the last): no clamping needed
+        walk([&](int64_t i, int q) { return su[i * ldl + r0 + q]; });
+    } else {
+        // Factor read from global memory; ranks past the last are clamped (their sums dropped),
+        // so the loads of an unrolled step are unconditional.
+        if (a.uprec == P_FP64) {
+            const double *U = static_cast<const double *>(a.U);
+            walk([&](int64_t i, int q) { return U[i * a.ldu + r0 + (q < nr ? q : 0)]; });
+        } else {
+            const float *U = static_cast<const float *>(a.U);
+            walk([&](int64_t i, int q) { return static_cast<double>(U[i * a.ldu + r0 + (q < nr ? q : 0)]); });
+        }
     }
+    // Predicated stores, not an early exit: a loop that leaves early is not unrolled,
+    // and indexing acc in it would place acc in scratch memory.
 #pragma unroll
     for (int q = 0; q < RB; ++q) {
-        if (q >= nr) break;
-        const int64_t o = ooff + (r0 + q) * a.ostr[a.m];
-        if (a.out_dtype == DEINSUM_F64) static_cast<double *>(a.out)[o] = acc[q];
-        else static_cast<float *>(a.out)[o] = static_cast<float>(acc[q]);
+        if (q < nr) {
+            const int64_t o = ooff + (r0 + q) * a.ostr[a.m];
+            if (a.out_dtype == DEINSUM_F64) static_cast<double *>(a.out)[o] = acc[q];
+            else static_cast<float *>(a.out)[o] = static_cast<float>(acc[q]);
+        }
     }
 }
 
@@ -1211,11 +1271,28 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         const size_t ubytes = static_cast<size_t>(t.Im * cdivl(p.Rm[m], rb) * rb) * 8;
         t.lds = ubytes <= kTtmLdsBytes;
         const unsigned tg = static_cast<unsigned>(cdivl(t.total, 256));
-        if (!t.lds) small_ttm_kernel<8, false><<<tg, 256, 0, s>>>(t);
-        else if (rb == 8) small_ttm_kernel<8, true><<<tg, 256, ubytes, s>>>(t);
-        else if (rb == 16) small_ttm_kernel<16, true><<<tg, 256, ubytes, s>>>(t);
-        else if (rb == 24) small_ttm_kernel<24, true><<<tg, 256, ubytes, s>>>(t);
-        else small_ttm_kernel<32, true><<<tg, 256, ubytes, s>>>(t);
+        // Few fibres (fewer threads than four waves per SIMD of the chip): the pipelined
+        // row walk, factor in LDS when it fits.  Many fibres and one block of exactly
+        // every rank: the weights as scalar operands.
+        auto go = [&](auto pipe) {
+            constexpr bool PP = decltype(pipe)::value;
+            if constexpr (!PP) {
+                if (p.Rm[m] == rb) {
+                    if (rb == 8) small_ttm_kernel<8, kTtmWUniform, false><<<tg, 256, 0, s>>>(t);
+                    else if (rb == 16) small_ttm_kernel<16, kTtmWUniform, false><<<tg, 256, 0, s>>>(t);
+                    else if (rb == 24) small_ttm_kernel<24, kTtmWUniform, false><<<tg, 256, 0, s>>>(t);
+                    else small_ttm_kernel<32, kTtmWUniform, false><<<tg, 256, 0, s>>>(t);
+                    return;
+                }
+            }
+            if (!t.lds) small_ttm_kernel<8, kTtmWGlobal, PP><<<tg, 256, 0, s>>>(t);
+            else if (rb == 8) small_ttm_kernel<8, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
+            else if (rb == 16) small_ttm_kernel<16, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
+            else if (rb == 24) small_ttm_kernel<24, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
+            else small_ttm_kernel<32, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
+        };
+        if (t.total < kTtmPipeThreads) go(std::true_type{});
+        else go(std::false_type{});
         if (deinsum_status st2 = check_launch("ttmc_small_ttm")) return st2;
         src = static_cast<const double *>(dst);
     }

@@ -24,6 +24,10 @@ CASES = [
     ((33, 47), (5, 6)),
     # remaining product over a 900-long mode: its factor is read from global memory, not LDS
     ((3, 900, 20, 24), (2, 8, 8, 8)),
+    # mode 0: a remaining product over 288,000 fibres, more than the pipelined row walk
+    # takes (factor in LDS for rank 5; as scalar operands for exactly 8 ranks)
+    ((2000, 10, 12, 16), (3, 5, 12, 12)),
+    ((2000, 10, 12, 16), (3, 8, 12, 12)),
     # several c-groups per slab (partials reduced) before the remaining products; ragged last tile
     ((5, 6, 7, 300), (3, 4, 5, 6)),
 ]
