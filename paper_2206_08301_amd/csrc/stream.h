@@ -121,7 +121,8 @@ struct Tile {
     static constexpr int FROWS = NI * KE;  // slice rows of one lane per step (M-contiguous)
     static constexpr int XW = (P != P_FX20) ? XN : (L == L_KCONTIG ? XN / 2 + XN / 4 : FROWS * (FHW + 1));
     static_assert(L == L_MCONTIG || (NI * KE) % VE == 0, "K-contiguous runs must be whole chunks");
-    static_assert(P != P_FX20 || L == L_KCONTIG || MT <= 4, "FX20 M-contiguous tiles hold at most 4 indices");
+    static_assert(P != P_FX20 || L == L_KCONTIG || MT == 1 || MT == 2 || MT == 4,
+                  "FX20 M-contiguous tiles hold 1, 2 or 4 indices per lane");
 
     __device__ static int pos_k(int t, int g) { return (t / VE) * 4 * VE + g * VE + t % VE; }
     __device__ static int pos_m(int q, int g, int e) { return q * 4 * KE + g * KE + e; }
@@ -250,7 +251,9 @@ __device__ __forceinline__ void load_tile_fx20(uint32_t *x, int64_t off, const S
                 const int64_t e0 = static_cast<int64_t>(r) * a.stride_g;
                 uint32_t *wh = xh + rr * FHW;
                 uint32_t &wl = x[HW + rr];
-                if constexpr (FULL) {
+                // A whole run in range (every tile of an aligned full tensor; in a
+                // ragged tile the lanes whose MT indices all exist): vector loads.
+                if (FULL || (MT >= 2 && a.vec_ok && r < lim && ivalid >= MT)) {
                     if constexpr (MT == 4) {
                         const uint64_t h = ld_stream<NTL>(reinterpret_cast<const uint64_t *>(H + e0));
                         wh[0] = static_cast<uint32_t>(h);

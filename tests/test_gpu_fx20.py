@@ -131,3 +131,40 @@ def test_fx20_tuned_plan(dn, oracle_mod):
         ref = oracle_mod.mttkrp(X, [None if m == n else U[m] for m in range(3)], n)
         assert nrel(M.cpu().numpy(), ref) <= 4e-6
     dn.tune_clear()
+
+
+# Every compiled FX20 last-mode (M-contiguous) kernel variant: column tiles, K
+# instructions per step, output indices per lane, non-temporal loads.
+FX20_MCONTIG = [(2, 1, 4, 0), (2, 1, 4, 1), (2, 1, 2, 0), (2, 1, 2, 1), (2, 2, 2, 0), (1, 1, 4, 0),
+                (1, 2, 2, 0), (1, 2, 2, 1), (4, 1, 1, 0)]
+
+
+@pytest.mark.parametrize("dims", [(7, 9, 60), (5, 6, 7, 50), (3, 5, 130)])
+def test_fx20_last_mode_every_variant(dn, oracle_mod, tmp_path, dims):
+    """Ragged last modes on every FX20 last-mode variant, each forced by a plan-cache
+    entry.  In a ragged tile the lanes whose indices all exist take vector loads when the
+    rows are whole runs of the lane's width (60 for every width, 50 and 130 for 2-index
+    runs), element loads otherwise; integer inputs, exact against the oracle."""
+    rng = np.random.default_rng(sum(dims))
+    N, R = len(dims), 24
+    X = rng.integers(-2, 3, dims).astype(np.float64)
+    U = [rng.integers(-2, 3, (d, R)).astype(np.float64) for d in dims]
+    ref = oracle_mod.mttkrp(X, U[:-1] + [None], N - 1)
+    f = dn.to_fx20(to_dev(X))
+    ops = [to_dev(U[m], torch.float32) for m in range(N - 1)]
+    key = f"s:N{N}:n{N - 1}:p4:R{R}:" + "x".join(str(d) for d in dims)
+    cache = tmp_path / "fx20_mcontig.txt"
+    try:
+        for nt, ni, mt, xnt in FX20_MCONTIG:
+            cache.write_text(f"{key} {nt} {ni} {mt} {xnt} 0 0 0 1.0\n")
+            dn.tune_clear()
+            dn.tune_load(cache)
+            rep = dn.Report()
+            M = dn.mttkrp(mttkrp_spec(N, N - 1), f, ops, precision="fx20", out_dtype=torch.float64, report=rep)
+            torch.cuda.synchronize()
+            name = rep.plan_name.decode()
+            flush(f"fx20 last mode dims={dims}: {name}")
+            assert f"mcontig<p4,nt{nt},ni{ni},mt{mt}{',nt' if xnt else ''}>" in name, name
+            assert np.array_equal(M.cpu().numpy(), ref), name
+    finally:
+        dn.tune_clear()
