@@ -110,16 +110,20 @@ __device__ __forceinline__ int64_t slab_offset(const OuterDesc &od, int64_t stri
 // LDS of the fused kernel.  Stage-2 factor rows of the workgroup are held in LDS
 // when a four-wave workgroup's rows fit in 32 KB (they are the same for every
 // slab); per-wave Z tiles are summed after one barrier when four of them and those
-// rows stay within 64 KB (two workgroups per CU still fit in its 160 KB), else
-// accumulated wave by wave in one tile, one barrier per wave.  Sized at launch for
-// the workgroup's actual wave count (dynamic shared memory).
+// rows stay within 64 KB for FP32 rows (two workgroups per CU still fit in its
+// 160 KB) or 40 KB for FP64 rows, else accumulated wave by wave in one tile, one
+// barrier per wave.  Sized at launch for the workgroup's actual wave count
+// (dynamic shared memory).
 template <int P, int NTA, int NTC, int MT, bool STAGE2>
 struct TkLds {
     using CT = typename TkTypes<P>::CT;
     static constexpr int TA = 16 * NTA, TC = 16 * NTC;
     static constexpr size_t UC_BYTES = static_cast<size_t>(4 * 16 * MT) * TC * sizeof(CT);
     static constexpr bool UC_LDS = STAGE2 && UC_BYTES <= 32768;
-    static constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) + (UC_LDS ? UC_BYTES : 0) <= 65536;
+    // FP64 factor rows keep the 40 KB limit: the 60^5 R=24 FP64 pass (two-wave
+    // workgroups, 32 KB of rows) ran 2.5 -> 3.5 ms with the extra LDS per workgroup.
+    static constexpr size_t Z_PAR_LDS = sizeof(CT) == 4 ? 65536 : 40960;
+    static constexpr bool Z_PAR = STAGE2 && 4 * TA * TC * sizeof(double) + (UC_LDS ? UC_BYTES : 0) <= Z_PAR_LDS;
     __host__ __device__ static size_t z_elems(int nwaves) { return STAGE2 ? static_cast<size_t>(Z_PAR ? nwaves : 1) * TA * TC : 0; }
     __host__ __device__ static size_t bytes(int nwaves)
     {
