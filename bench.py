@@ -52,6 +52,10 @@ def parse_args():
                     help="print per-workload kernel time, HBM bytes and matrix-core use from a kernel_trace.csv and "
                          "three counter_collection.csv files (FETCH_SIZE, WRITE_SIZE, MfmaUtil passes) and exit")
     ap.add_argument("--last", type=int, default=0, help="--summarize-*: steady state = the last N launches per kernel")
+    ap.add_argument("--first-run", action="store_true",
+                    help="--summarize-*: the dominant kernel's launches are those of its first run (a stretch "
+                         "of launches at most 50 dispatches apart: the MTTKRP step's calls, when a later "
+                         "workload launches the same kernel)")
     ap.add_argument("--bytes", type=float, default=0.0,
                     help="--summarize-trace: algorithmic bytes per launch of the kernel named by --kernel")
     ap.add_argument("--kernel", default="", help="--summarize-*: substring naming the dominant kernel")
@@ -320,16 +324,27 @@ def _short(name):
     return re.sub(r"\((?![^()]*\)\s*$).*$|\([^()]*\)\s*$", "", name).strip()
 
 
-def summarize_trace(path, last, dominant, alg_bytes):
+def _first_run(ids):
+    """Indices of the first run of a kernel's dispatches (ids ascending): the stretch before
+    the first gap of more than 50 dispatches."""
+    n = 1
+    while n < len(ids) and ids[n] - ids[n - 1] <= 50:
+        n += 1
+    return n
+
+
+def summarize_trace(path, last, dominant, alg_bytes, first_run=False):
     """Kernel-time table from a rocprofv3 kernel_trace.csv: per kernel, launches, mean, and
     the median over the last `last` launches (the steady state of a run whose tuning and
-    warm-up launches come first); for the kernel matching `dominant`, bytes / that median."""
-    rows = _csv_rows(path)
-    per = {}
+    warm-up launches come first); for the kernel matching `dominant`, bytes / that median
+    (first_run: the last `last` launches of its first run)."""
+    rows = sorted(_csv_rows(path), key=lambda r: int(_col(r, "Dispatch_Id", "Dispatch_ID")))
+    per, ids = {}, {}
     for r in rows:
         name = _short(_col(r, "Kernel_Name", "KernelName", "Name"))
         d = (int(_col(r, "End_Timestamp", "EndNs")) - int(_col(r, "Start_Timestamp", "BeginNs"))) / 1e3
         per.setdefault(name, []).append(d)
+        ids.setdefault(name, []).append(int(_col(r, "Dispatch_Id", "Dispatch_ID")))
     tot = sum(sum(v) for v in per.values())
     print(f"{'kernel':<56} {'calls':>6} {'mean us':>9} {'median us':>10} {'steady med':>10} {'min us':>9} {'% time':>7}")
     for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
@@ -340,10 +355,16 @@ def summarize_trace(path, last, dominant, alg_bytes):
         hits = [n for n in per if dominant in n]
         if len(hits) == 1:
             v = per[hits[0]]
-            ss = v[-last:] if last else v
+            if first_run:
+                n = _first_run(ids[hits[0]])
+                ss = v[:n][-last:] if last else v[:n]
+                which = f"the last {len(ss)} of the {n} launches of its first run; {len(v)} in all"
+            else:
+                ss = v[-last:] if last else v
+                which = f"the last {len(ss)} of {len(v)}"
             med = statistics.median(ss)
             print(f"\ndominant kernel: {hits[0]}")
-            print(f"steady-state launches: {len(ss)} (the last {len(ss)} of {len(v)}); median {med:.1f} us")
+            print(f"steady-state launches: {len(ss)} ({which}); median {med:.1f} us")
             if alg_bytes:
                 gbs = alg_bytes / (med * 1e-6) / 1e9
                 print(f"algorithmic bytes per launch {alg_bytes:.0f} / median = {gbs:.1f} GB/s "
@@ -352,7 +373,7 @@ def summarize_trace(path, last, dominant, alg_bytes):
             print(f"\ndominant kernel: {len(hits)} names match {dominant!r}: {hits}")
 
 
-def summarize_pmc(path, dominant):
+def summarize_pmc(path, dominant, first_run=False):
     """Per-kernel counter table from a rocprofv3 counter_collection.csv: each counter summed
     per dispatch, then averaged over the dispatches of a kernel.  The runtime's copy kernel
     (bench.py --copy-probe: 1 GiB read and written) calibrates FETCH_SIZE / WRITE_SIZE."""
@@ -363,8 +384,9 @@ def summarize_pmc(path, dominant):
         cname = _col(r, "Counter_Name", "CounterName")
         disp.setdefault(key, {}).setdefault(cname, 0.0)
         disp[key][cname] += float(_col(r, "Counter_Value", "CounterValue"))
-    per = {}
-    for (_, name), cs in disp.items():
+    per, ids = {}, {}
+    for (d, name), cs in sorted(disp.items(), key=lambda kv: kv[0][0]):  # dispatch order
+        ids.setdefault(name, []).append(d)
         for c, v in cs.items():
             per.setdefault(name, {}).setdefault(c, []).append(v)
     # The calibration copy: the runtime copy dispatches issued before the first kernel of
@@ -389,8 +411,11 @@ def summarize_pmc(path, dominant):
         for h in hits:
             for c, sc in scale.items():
                 if c in per[h]:
-                    kib = statistics.mean(per[h][c])
-                    print(f"{h[:60]}: {c} {kib:.1f} KiB per dispatch x {sc:.4f} (copy calibration) = "
+                    n = _first_run(ids[h]) if first_run else len(per[h][c])
+                    vals = per[h][c][:n]
+                    kib = statistics.mean(vals)
+                    sel = f" (the {n} dispatches of its first run, of {len(per[h][c])})" if first_run else ""
+                    print(f"{h[:60]}: {c} {kib:.1f} KiB per dispatch{sel} x {sc:.4f} (copy calibration) = "
                           f"{kib * sc * 1024:.0f} bytes")
 
 
@@ -466,10 +491,10 @@ def main():
         summarize_workloads(*args.summarize_workloads)
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.last, args.kernel, args.bytes)
+        summarize_trace(args.summarize_trace, args.last, args.kernel, args.bytes, args.first_run)
         return
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc, args.kernel)
+        summarize_pmc(args.summarize_pmc, args.kernel, args.first_run)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; sharding across GPUs is not implemented",
