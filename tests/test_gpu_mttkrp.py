@@ -452,3 +452,38 @@ def test_mode0_row_walk_is_default_for_far_rows(dn, synth):
             dn.mttkrp(mttkrp_spec(3, 0), X, U, precision=prec, out_dtype=torch.float64, report=rep)
             torch.cuda.synchronize()
             assert rep.plan_name.decode().startswith(want), (prec, dims, rep.plan_name)
+
+
+# The FP64 64-index last-mode variants: column tiles, K instructions per step, output
+# indices per lane, non-temporal loads.
+FP64_MT4 = [(2, 4, 4, 1), (2, 4, 4, 0), (2, 2, 4, 1)]
+
+
+@pytest.mark.parametrize("dims", [(7, 9, 60), (5, 6, 7, 50), (3, 11, 13, 64)])
+def test_fp64_short_last_mode_every_variant(dn, oracle_mod, tmp_path, dims):
+    """Every FP64 64-index last-mode variant, each forced by a plan-cache entry, on short
+    last modes (ragged and whole tiles, contracted extents that leave a partial K step);
+    integer inputs, exact against the oracle."""
+    rng = np.random.default_rng(sum(dims) + 1)
+    N, R = len(dims), 24
+    X = rng.integers(-3, 4, dims).astype(np.float64)
+    U = [rng.integers(-2, 3, (d, R)).astype(np.float64) for d in dims]
+    ref = oracle_mod.mttkrp(X, U[:-1] + [None], N - 1)
+    Xd = to_dev(X)
+    ops = [to_dev(U[m]) for m in range(N - 1)]
+    key = f"s:N{N}:n{N - 1}:p0:R{R}:" + "x".join(str(d) for d in dims)
+    cache = tmp_path / "fp64_mt4.txt"
+    try:
+        for nt, ni, mt, xnt in FP64_MT4:
+            cache.write_text(f"{key} {nt} {ni} {mt} {xnt} 0 0 0 1.0\n")
+            dn.tune_clear()
+            dn.tune_load(cache)
+            rep = dn.Report()
+            M = dn.mttkrp(mttkrp_spec(N, N - 1), Xd, ops, precision="fp64", out_dtype=torch.float64, report=rep)
+            torch.cuda.synchronize()
+            name = rep.plan_name.decode()
+            flush(f"fp64 short last mode dims={dims}: {name}")
+            assert f"mcontig<p0,nt{nt},ni{ni},mt{mt}{',nt' if xnt else ''}>" in name, name
+            assert np.array_equal(M.cpu().numpy(), ref), name
+    finally:
+        dn.tune_clear()
