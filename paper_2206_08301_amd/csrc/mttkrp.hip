@@ -139,7 +139,7 @@ static const StreamKernelInfo kStreamTable[] = {
     // Order-3 mode 0, mode-1 tiles walked per output row (the K-contiguous tile and loads)
     SK(P_FP32, L_KOUT, 1, 32, 1, 3), SK(P_FP32, L_KOUT, 2, 32, 1, 3),
     SK(P_BF16, L_KOUT, 1, 8, 1, 2), SK(P_BF16, L_KOUT, 2, 8, 1, 2), SK(P_BF16, L_KOUT, 4, 4, 1, 2),
-    SK(P_BF16X3, L_KOUT, 1, 4, 1, 3), SK(P_BF16X3, L_KOUT, 2, 4, 1, 2),
+    SK(P_BF16X3, L_KOUT, 1, 4, 1, 3), SK(P_BF16X3, L_KOUT, 2, 4, 1, 3),
     SK(P_FX20, L_KOUT, 1, 4, 1, 3), SK(P_FX20, L_KOUT, 2, 4, 1, 3),
     // M-contiguous: NI K-steps of 4*KE rows; MT output indices per lane
     // (FP64: non-temporal X loads first -- they keep the per-K-step factor rows cached, 1.50 -> 1.37 ms
