@@ -642,9 +642,11 @@ struct SmallTtmArgs {
 
 // Largest factor (rows x ranks rounded up to RB, FP64) staged in LDS per workgroup.
 constexpr size_t kTtmLdsBytes = 48 * 1024;
-// Below this many threads (four waves on each of the 1024 SIMDs) a small TTM takes
-// the pipelined row walk.
+// Below this many output fibres (four waves' worth on each of the 1024 SIMDs) a small
+// TTM takes the pipelined row walk, when the staged factor and the waves' partial sums
+// fit in this much LDS.
 constexpr int64_t kTtmPipeThreads = int64_t{1024} * 4 * 64;
+constexpr size_t kTtmPipeLdsBytes = 64 * 1024;
 
 // Where a thread's factor weights come from: global memory per lane (ranks in
 // blocks of RB), LDS (the factor staged per workgroup), or, when one block holds
@@ -668,9 +670,14 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
         }
         __syncthreads();
     }
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= a.total) return;
-    int64_t rem = e, ioff = 0, ooff = 0, r0 = 0;
+    // PIPE: a workgroup's four waves share its 64 fibres, wave w summing rows
+    // [w Im / 4, (w + 1) Im / 4); otherwise one thread per fibre over every row.
+    const int wv = PIPE ? static_cast<int>(threadIdx.x >> 6) : 0;
+    const int64_t e = PIPE ? static_cast<int64_t>(blockIdx.x) * 64 + (threadIdx.x & 63)
+                           : static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const bool valid = e < a.total;
+    if (!PIPE && !valid) return;
+    int64_t rem = valid ? e : 0, ioff = 0, ooff = 0, r0 = 0;
     for (int d = a.nd - 1; d >= 0; --d) {
         const int64_t ext = (d == a.m) ? (a.odim[d] + RB - 1) / RB : a.odim[d];
         const int64_t i = rem % ext;
@@ -688,12 +695,13 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
     for (int q = 0; q < RB; ++q) acc[q] = 0.0;
     const int64_t sm = a.tstr[a.m];
     // Rows of the input fibre summed in ascending order, in batches of eight loads.
-    // PIPE (launches with few fibres, e.g. 192^4 R=16: 768 waves) takes batches of
-    // sixteen, issues the next batch's loads before the current batch's products and
-    // reads each row's weights together, so that up to 32 loads per thread are in
-    // flight: such a launch is otherwise bound by one memory latency per batch.  Without PIPE the kernel
-    // keeps its lower register count, and the occupancy that hides latency in
-    // launches with many fibres.
+    // PIPE (launches with few fibres, e.g. 192^4 R=16: 768 fibre waves) splits the rows
+    // over four waves, and each takes batches of sixteen, issuing the next batch's
+    // loads before the current batch's products and reading each row's weights
+    // together, so that up to 32 loads per thread are in flight: such a launch is
+    // otherwise bound by one memory latency per batch.  Without PIPE the kernel keeps
+    // its lower register count, and the occupancy that hides latency in launches with
+    // many fibres.
     auto walk = [&](auto wt) {  // wt(i, q): factor entry of row i, rank r0 + q
         if constexpr (!PIPE) {
             int64_t i = 0;
@@ -714,7 +722,9 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
             return;
         }
         constexpr int KB = 16;  // rows per batch
-        const int64_t nb = a.Im / KB * KB;
+        const int64_t r_lo = wv * a.Im / 4, r_hi = (wv + 1) * a.Im / 4;
+        if (!valid) return;
+        const int64_t nb = r_lo + (r_hi - r_lo) / KB * KB;
         double ta[KB], tb[KB];
         auto load = [&](double(&t)[KB], int64_t i) {
 #pragma unroll
@@ -730,8 +740,8 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
                 for (int q = 0; q < RB; ++q) acc[q] += t[k] * w[q];
             }
         };
-        int64_t i = 0;
-        if (nb > 0) load(ta, 0);
+        int64_t i = r_lo;
+        if (nb > r_lo) load(ta, r_lo);
         for (; i < nb; i += 2 * KB) {
             const bool more = i + KB < nb;
             if (more) load(tb, i + KB);
@@ -743,7 +753,7 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
             if (i + 2 * KB < nb) load(ta, i + 2 * KB);
             use(tb, i + KB);
         }
-        for (; i < a.Im; ++i) {
+        for (; i < r_hi; ++i) {
             const double t = a.T[ioff + i * sm];
 #pragma unroll
             for (int q = 0; q < RB; ++q) acc[q] += t * wt(i, q);
@@ -771,6 +781,20 @@ __global__ void __launch_bounds__(256) small_ttm_kernel(const SmallTtmArgs a)
             const float *U = static_cast<const float *>(a.U);
             walk([&](int64_t i, int q) { return static_cast<double>(U[i * a.ldu + r0 + (q < nr ? q : 0)]); });
         }
+    }
+    if constexpr (PIPE) {
+        // Waves 1-3 hand their partial sums to wave 0 through LDS (after the staged
+        // factor); wave 0 adds them in wave order and stores.
+        double *red = su + (LDS ? a.Im * ldl : 0);
+        if (wv > 0)
+#pragma unroll
+            for (int q = 0; q < RB; ++q) red[((wv - 1) * RB + q) * 64 + (threadIdx.x & 63)] = acc[q];
+        __syncthreads();
+        if (wv > 0 || !valid) return;
+#pragma unroll
+        for (int w = 0; w < 3; ++w)
+#pragma unroll
+            for (int q = 0; q < RB; ++q) acc[q] += red[(w * RB + q) * 64 + threadIdx.x];
     }
     // Predicated stores, not an early exit: a loop that leaves early is not unrolled,
     // and indexing acc in it would place acc in scratch memory.
@@ -1276,11 +1300,14 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
         const size_t ubytes = static_cast<size_t>(t.Im * cdivl(p.Rm[m], rb) * rb) * 8;
         t.lds = ubytes <= kTtmLdsBytes;
         const unsigned tg = static_cast<unsigned>(cdivl(t.total, 256));
-        // Few fibres (fewer threads than four waves per SIMD of the chip): the pipelined
-        // row walk, factor in LDS when it fits.  Many fibres and one block of exactly
-        // every rank: the weights as scalar operands.
-        auto go = [&](auto pipe) {
-            constexpr bool PP = decltype(pipe)::value;
+        // Few fibres (fewer than four waves' worth per SIMD of the chip): the pipelined
+        // row walk, four waves per 64 fibres, factor in LDS when it fits beside the
+        // waves' partial sums.  Many fibres and one block of exactly every rank: the
+        // weights as scalar operands.
+        const size_t red_bytes = static_cast<size_t>(3 * 64) * rb * 8;
+        const bool pipe = t.total < kTtmPipeThreads && (t.lds ? ubytes : 0) + red_bytes <= kTtmPipeLdsBytes;
+        auto go = [&](auto pipe_tag) {
+            constexpr bool PP = decltype(pipe_tag)::value;
             if constexpr (!PP) {
                 if (p.Rm[m] == rb) {
                     if (rb == 8) small_ttm_kernel<8, kTtmWUniform, false><<<tg, 256, 0, s>>>(t);
@@ -1290,13 +1317,15 @@ deinsum_status run_ttmc(const deinsum_spec *spec, const int64_t *dims, const int
                     return;
                 }
             }
-            if (!t.lds) small_ttm_kernel<8, kTtmWGlobal, PP><<<tg, 256, 0, s>>>(t);
-            else if (rb == 8) small_ttm_kernel<8, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
-            else if (rb == 16) small_ttm_kernel<16, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
-            else if (rb == 24) small_ttm_kernel<24, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
-            else small_ttm_kernel<32, kTtmWLds, PP><<<tg, 256, ubytes, s>>>(t);
+            const unsigned g = PP ? static_cast<unsigned>(cdivl(t.total, 64)) : tg;
+            const size_t lb = (t.lds ? ubytes : 0) + (PP ? red_bytes : 0);
+            if (!t.lds) small_ttm_kernel<8, kTtmWGlobal, PP><<<g, 256, lb, s>>>(t);
+            else if (rb == 8) small_ttm_kernel<8, kTtmWLds, PP><<<g, 256, lb, s>>>(t);
+            else if (rb == 16) small_ttm_kernel<16, kTtmWLds, PP><<<g, 256, lb, s>>>(t);
+            else if (rb == 24) small_ttm_kernel<24, kTtmWLds, PP><<<g, 256, lb, s>>>(t);
+            else small_ttm_kernel<32, kTtmWLds, PP><<<g, 256, lb, s>>>(t);
         };
-        if (t.total < kTtmPipeThreads) go(std::true_type{});
+        if (pipe) go(std::true_type{});
         else go(std::false_type{});
         if (deinsum_status st2 = check_launch("ttmc_small_ttm")) return st2;
         src = static_cast<const double *>(dst);
